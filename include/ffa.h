@@ -1,0 +1,148 @@
+/*
+ * ffa.h — exact C = Low(A * phi(A)) over a prime field on AMD MI355X (gfx950).
+ *
+ * The operation is the one of the paper "Some fast algorithms multiplying a
+ * matrix by its adjoint" (Dumas, Pernet, Sedoglavic), Section 3, Algorithm 1:
+ * given A and an involutive antihomomorphism phi, return the lower triangular
+ * part Low(A phi(A)) (Low/Up definition of Section 2: the diagonal belongs to
+ * the lower part).  Two antihomomorphisms are provided (Section 2, examples):
+ *   - phi = transpose over F_p                       -> ffa_syrk_modp
+ *   - phi = conjugate transpose over F_p[i]/(i^2+1)  -> ffa_herk_modp2
+ * The recursive algorithm uses 3 recursive and 2 general products per level
+ * and a skew-unitary Y (Y phi(Y) = -I) built from a^2 + b^2 = -1 mod p
+ * (Section 4, Algorithm 2).  The result is exact: every call returns the
+ * same bits as the definition, whatever recursion depth, Y or carrier is used.
+ *
+ * Conventions common to every entry point
+ *   - Matrices are row-major.  A is n x k with leading dimension lda >= k
+ *     (elements); C is n x n with ldc >= n.
+ *   - A and C are DEVICE pointers owned by the caller.  The library never
+ *     frees or keeps them; work is enqueued asynchronously on the context's
+ *     stream and the caller keeps the buffers alive until it synchronises.
+ *   - Only the lower triangle of C (diagonal included) is written; the strict
+ *     upper triangle is never read or written (BLAS uplo = 'L').
+ *   - Inputs are canonical residues in [0, p) (FFA_I8_CENTRED: centred
+ *     residues in [-(p-1)/2, (p-1)/2], p < 256).  Outputs are canonical.
+ *   - n = 0 is valid (nothing written); k = 0 writes zeros.
+ *   - Every argument is validated before anything is launched; on an error
+ *     nothing is written.  No exception or abort crosses this interface.
+ *   - A context is not thread safe; use one context per host thread.
+ */
+#ifndef FFA_H
+#define FFA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ffa_ctx ffa_ctx;
+typedef struct ffa_batch ffa_batch;
+
+/* status codes (0 = success) */
+enum {
+    FFA_OK = 0,
+    FFA_EINVAL = -1,       /* bad size, stride, pointer, dtype or option */
+    FFA_EPRIME = -2,       /* p is not an odd prime, or too large for the carrier */
+    FFA_ERANGE = -3,       /* an input entry is outside its residue range (check_inputs) */
+    FFA_ENOMEM = -4,       /* device workspace could not be allocated */
+    FFA_EDEVICE = -5,      /* a HIP call failed; ffa_last_device_error() has the code */
+    FFA_EUNSUPPORTED = -6, /* valid request this build does not support (e.g. herk with p = 1 mod 4) */
+    FFA_EBOUND = -7        /* the exact-accumulation bound of the carrier is exceeded */
+};
+
+/* element formats of A and C */
+enum {
+    FFA_I64 = 0,
+    FFA_I32 = 1,
+    FFA_U16 = 2,
+    FFA_U8 = 3,
+    FFA_F64 = 4,          /* doubles holding integers */
+    FFA_I8_CENTRED = 5    /* input only; p < 256 */
+};
+
+enum { FFA_ALGO_AUTO = 0, FFA_ALGO_CLASSICAL = 1, FFA_ALGO_RECURSIVE = 2 };
+enum { FFA_CARRIER_AUTO = 0, FFA_CARRIER_INT8 = 1, FFA_CARRIER_F64 = 2 };
+
+/* Options; pass NULL for the defaults (all fields zero except levels = -1, cutoff = 0).
+ *   algo          FFA_ALGO_*; CLASSICAL = no recursion (the plain modular SYRK)
+ *   levels        recursion depth of Algorithm 1 when >= 0; -1 = from cutoff
+ *   cutoff        recurse while the sub-problem has more than cutoff rows (0 = built-in default)
+ *   carrier       FFA_CARRIER_*: INT8 = balanced int8 limbs on INT8 MFMA (1 limb for p < 256,
+ *                 2 limbs for p < 2^16); F64 = doubles on FP64 MFMA (p < 2^26, real only)
+ *   check_inputs  nonzero: verify every entry of A (synchronises the stream; FFA_ERANGE) */
+typedef struct {
+    int32_t algo;
+    int32_t levels;
+    int32_t cutoff;
+    int32_t carrier;
+    int32_t check_inputs;
+    int32_t reserved[3];
+} ffa_opts;
+
+/* Context bound to a HIP device and stream (stream NULL = the null stream).
+ * Owns the device workspace (grown on demand, freed by ffa_destroy) and a
+ * cache of plans.  Returns FFA_EINVAL / FFA_EDEVICE on failure. */
+int ffa_create(ffa_ctx** out, int device, void* hip_stream);
+int ffa_destroy(ffa_ctx* ctx);
+int ffa_set_stream(ffa_ctx* ctx, void* hip_stream);
+/* hipError_t of the last failing HIP call of this context (0 if none). */
+int ffa_last_device_error(const ffa_ctx* ctx);
+const char* ffa_status_string(int status);
+
+/* The skew-unitary Y used for p (Section 4):
+ *   kind 0: Y = a I with a^2 = -1 (p = 1 mod 4, Proposition lemsqrt)
+ *   kind 1: Y = [[a, b], [-b, a]] (x) I, column halves (p = 3 mod 4, Proposition pigeonhole)
+ *   kind 2: Y = (a + i b) I over F_p[i] (hermitian != 0, p = 3 mod 4, Section 4.4)
+ * (a, b) come from Algorithm 2 with k = -1, smaller square roots.  Host only. */
+int ffa_skew_unitary(uint32_t p, int hermitian, uint32_t* a, uint32_t* b, int* kind);
+
+/* C = Low(A A^T) mod p  (Algorithm 1 with phi = transpose, Section 3).
+ * dA: FFA_I8_CENTRED, FFA_U8, FFA_U16, FFA_I32, FFA_I64 or FFA_F64;
+ * dC: FFA_U8 (p < 256), FFA_U16 (p < 2^16), FFA_I32, FFA_I64 or FFA_F64. */
+int ffa_syrk_modp(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p,
+                  int dA, const void* A, int64_t lda,
+                  int dC, void* C, int64_t ldc, const ffa_opts* opts);
+
+/* C = Low(A A^H) over F_{p^2} = F_p[i]/(i^2+1), p = 3 mod 4, conj(x + iy) = x - iy
+ * (Algorithm 1 with phi = conjugate transpose; Y of Section 4.4).  Planar storage:
+ * A = A_re + i A_im and C = C_re + i C_im, each plane as in ffa_syrk_modp, same lda/ldc.
+ * Im(C_ii) = 0.  p = 1 mod 4 gives FFA_EUNSUPPORTED (i^2 + 1 is reducible). */
+int ffa_herk_modp2(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA,
+                   const void* A_re, const void* A_im, int64_t lda,
+                   int dC, void* C_re, void* C_im, int64_t ldc, const ffa_opts* opts);
+
+/* Batched C_i = Low(A_i A_i^T) mod p for independent problems (one p).
+ * Problems use a PACKED layout: A_i starts at element a_off[i] of one buffer with
+ * lda = k_i, C_i at element c_off[i] of another with ldc = n_i; the offsets are
+ * fixed by the plan (ffa_batch_offsets).  The plan (host work, may allocate) is
+ * made once; ffa_batch_syrk_exec then only enqueues kernels (no allocation). */
+int ffa_batch_syrk_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int64_t* k,
+                        uint32_t p, int dA, int dC, const ffa_opts* opts, ffa_batch** out);
+int ffa_batch_offsets(const ffa_batch* b, int64_t* a_off, int64_t* c_off,
+                      int64_t* a_total, int64_t* c_total);
+int ffa_batch_syrk_exec(ffa_batch* b, const void* A_packed, void* C_packed);
+int ffa_batch_destroy(ffa_batch* b);
+
+/* Phase timing with HIP events recorded on the context's stream around each
+ * phase of every later call: 0 = conditioning, 1 = pre-additions (all levels),
+ * 2 = products (one grouped launch), 3 = post-additions (all levels).
+ * ffa_profile_read synchronises on the recorded events and returns the summed
+ * milliseconds and the number of calls measured for the phase. */
+int ffa_profile_enable(ffa_ctx* ctx, int on);
+int ffa_profile_read(ffa_ctx* ctx, int phase, double* total_ms, int64_t* calls);
+int ffa_profile_reset(ffa_ctx* ctx);
+
+/* Host-only description of the plan ffa_syrk_modp / ffa_herk_modp2 would use
+ * (no device needed): writes a JSON object (levels, padded sizes, carrier,
+ * limbs, workspace bytes, launches) into buf (NUL-terminated, truncated to
+ * size).  Returns the validation status the call would return. */
+int ffa_plan_describe(int64_t n, int64_t k, uint32_t p, int hermitian, int dA, int dC,
+                      int64_t lda, int64_t ldc, const ffa_opts* opts, char* buf, int64_t size);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFA_H */

@@ -1,0 +1,260 @@
+"""Exact Low(A * phi(A)) over F_p and F_p[i]/(i^2+1) on AMD MI355X.
+
+Thin Python binding of the C-ABI library ``libffa.so`` (``include/ffa.h``):
+argument marshalling only.  Every step of the computation runs in the HIP
+kernels of ``csrc/``; PyTorch only provides device memory and the current
+stream.  If the library is not built this module raises on use: there is no
+CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libffa.so")
+
+OK, EINVAL, EPRIME, ERANGE, ENOMEM, EDEVICE, EUNSUPPORTED, EBOUND = 0, -1, -2, -3, -4, -5, -6, -7
+I64, I32, U16, U8, F64, I8_CENTRED = 0, 1, 2, 3, 4, 5
+ALGO_AUTO, ALGO_CLASSICAL, ALGO_RECURSIVE = 0, 1, 2
+CARRIER_AUTO, CARRIER_INT8, CARRIER_F64 = 0, 1, 2
+
+SYMBOLS = [
+    "ffa_create", "ffa_destroy", "ffa_set_stream", "ffa_last_device_error", "ffa_status_string",
+    "ffa_skew_unitary", "ffa_syrk_modp", "ffa_herk_modp2", "ffa_batch_syrk_plan",
+    "ffa_batch_offsets", "ffa_batch_syrk_exec", "ffa_batch_destroy", "ffa_plan_describe",
+    "ffa_profile_enable", "ffa_profile_read", "ffa_profile_reset",
+]
+PHASE_COND, PHASE_PRE, PHASE_PRODUCTS, PHASE_POST = 0, 1, 2, 3
+
+
+class FfaError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__(f"ffa status {status} ({status_string(status)}) {msg}")
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("levels", ctypes.c_int32), ("cutoff", ctypes.c_int32),
+                ("carrier", ctypes.c_int32), ("check_inputs", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+def make_opts(algo=ALGO_AUTO, levels=-1, cutoff=0, carrier=CARRIER_AUTO, check_inputs=False):
+    return Opts(algo, levels, cutoff, carrier, int(bool(check_inputs)))
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libffa.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, i32, u32, P = ctypes.c_int64, ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p
+        L.ffa_create.argtypes = [ctypes.POINTER(P), i32, P]
+        L.ffa_destroy.argtypes = [P]
+        L.ffa_set_stream.argtypes = [P, P]
+        L.ffa_last_device_error.argtypes = [P]
+        L.ffa_status_string.argtypes = [i32]
+        L.ffa_status_string.restype = ctypes.c_char_p
+        L.ffa_skew_unitary.argtypes = [u32, i32, ctypes.POINTER(u32), ctypes.POINTER(u32),
+                                       ctypes.POINTER(i32)]
+        L.ffa_syrk_modp.argtypes = [P, i64, i64, u32, i32, P, i64, i32, P, i64, P]
+        L.ffa_herk_modp2.argtypes = [P, i64, i64, u32, i32, P, P, i64, i32, P, P, i64, P]
+        L.ffa_batch_syrk_plan.argtypes = [P, i64, P, P, u32, i32, i32, P, ctypes.POINTER(P)]
+        L.ffa_batch_offsets.argtypes = [P, P, P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.ffa_batch_syrk_exec.argtypes = [P, P, P]
+        L.ffa_batch_destroy.argtypes = [P]
+        L.ffa_profile_enable.argtypes = [P, i32]
+        L.ffa_profile_read.argtypes = [P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+        L.ffa_profile_reset.argtypes = [P]
+        L.ffa_plan_describe.argtypes = [i64, i64, u32, i32, i32, i32, i64, i64, P, ctypes.c_char_p,
+                                        i64]
+        _lib = L
+    return _lib
+
+
+def status_string(s):
+    try:
+        return lib().ffa_status_string(s).decode()
+    except Exception:
+        return "?"
+
+
+def _check(st, msg=""):
+    if st != OK:
+        raise FfaError(st, msg)
+
+
+def skew_unitary(p, hermitian=False):
+    """(a, b, kind) of the skew-unitary Y used for p (Section 4 of the paper)."""
+    a, b, k = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_int()
+    _check(lib().ffa_skew_unitary(p, int(hermitian), ctypes.byref(a), ctypes.byref(b),
+                                  ctypes.byref(k)))
+    return a.value, b.value, k.value
+
+
+def plan_describe(n, k, p, hermitian=False, dA=I64, dC=I64, lda=None, ldc=None, opts=None):
+    """Host-only plan summary (dict) and the status the call would return."""
+    buf = ctypes.create_string_buffer(4096)
+    o = ctypes.byref(opts) if opts is not None else None
+    st = lib().ffa_plan_describe(n, k, p, int(hermitian), dA, dC, lda if lda is not None else k,
+                                 ldc if ldc is not None else n, o, buf, 4096)
+    return st, json.loads(buf.value.decode())
+
+
+def profile_enable(device_index, on=True):
+    _check(lib().ffa_profile_enable(context(device_index), int(on)))
+
+
+def profile_reset(device_index):
+    _check(lib().ffa_profile_reset(context(device_index)))
+
+
+def profile_read(device_index, phase):
+    """(total milliseconds, calls) of a phase measured with HIP events."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(lib().ffa_profile_read(context(device_index), phase, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+# ---------------------------------------------------------------- torch glue
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t, for_output=False):
+    torch = _torch()
+    m = {torch.int64: I64, torch.int32: I32, torch.uint8: U8, torch.float64: F64}
+    if not for_output:
+        m[torch.int8] = I8_CENTRED
+    if hasattr(torch, "uint16"):
+        m[torch.uint16] = U16
+    if t.dtype not in m:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return m[t.dtype]
+
+
+_contexts = {}
+
+
+def context(device_index: int):
+    """Per-device ffa_ctx (created on first use, kept for the process)."""
+    c = _contexts.get(device_index)
+    if c is None:
+        h = ctypes.c_void_p()
+        _check(lib().ffa_create(ctypes.byref(h), device_index, None), "ffa_create")
+        c = _contexts[device_index] = h
+    return c
+
+
+def _prep(A):
+    torch = _torch()
+    if not A.is_cuda:
+        raise ValueError("A must be a device tensor")
+    if A.dim() != 2 or (A.numel() > 0 and A.stride(1) != 1):
+        raise ValueError("A must be a row-major 2-D tensor")
+    ctx = context(A.device.index)
+    lib().ffa_set_stream(ctx, ctypes.c_void_p(torch.cuda.current_stream(A.device).cuda_stream))
+    return ctx
+
+
+def _out(C, n, device, dtype):
+    torch = _torch()
+    if C is None:
+        C = torch.zeros((n, n), dtype=dtype, device=device)
+    if C.dim() != 2 or C.shape[0] != n or C.shape[1] != n or (n > 0 and C.stride(1) != 1):
+        raise ValueError("C must be a row-major n x n tensor")
+    return C
+
+
+def default_out_dtype(p):
+    torch = _torch()
+    if p < 256:
+        return torch.uint8
+    if p < 65536 and hasattr(torch, "uint16"):
+        return torch.uint16
+    return torch.int32
+
+
+def syrk_modp(A, p, C=None, out_dtype=None, opts=None, **kw):
+    """Lower triangle of A A^T mod p (ffa_syrk_modp).  Strict upper part of C is left as is."""
+    ctx = _prep(A)
+    n, k = A.shape
+    C = _out(C, n, A.device, out_dtype or default_out_dtype(p))
+    o = opts if opts is not None else make_opts(**kw)
+    st = lib().ffa_syrk_modp(ctx, n, k, p, _dtype_code(A), ctypes.c_void_p(A.data_ptr()),
+                             max(A.stride(0), k, 1), _dtype_code(C, True),
+                             ctypes.c_void_p(C.data_ptr()), max(C.stride(0), n, 1),
+                             ctypes.byref(o))
+    _check(st, f"(device error {lib().ffa_last_device_error(ctx)})" if st == EDEVICE else "")
+    return C
+
+
+def herk_modp2(A_re, A_im, p, C_re=None, C_im=None, out_dtype=None, opts=None, **kw):
+    """Lower triangle of A A^H over F_p[i]/(i^2+1), planar re/im (ffa_herk_modp2)."""
+    ctx = _prep(A_re)
+    if A_im.shape != A_re.shape or A_im.stride() != A_re.stride() or A_im.dtype != A_re.dtype:
+        raise ValueError("A_re and A_im must have the same shape, strides and dtype")
+    n, k = A_re.shape
+    od = out_dtype or default_out_dtype(p)
+    C_re = _out(C_re, n, A_re.device, od)
+    C_im = _out(C_im, n, A_re.device, od)
+    if C_im.stride() != C_re.stride() or C_im.dtype != C_re.dtype:
+        raise ValueError("C_re and C_im must have the same strides and dtype")
+    o = opts if opts is not None else make_opts(**kw)
+    st = lib().ffa_herk_modp2(ctx, n, k, p, _dtype_code(A_re), ctypes.c_void_p(A_re.data_ptr()),
+                              ctypes.c_void_p(A_im.data_ptr()), max(A_re.stride(0), k, 1),
+                              _dtype_code(C_re, True), ctypes.c_void_p(C_re.data_ptr()),
+                              ctypes.c_void_p(C_im.data_ptr()), max(C_re.stride(0), n, 1),
+                              ctypes.byref(o))
+    _check(st, f"(device error {lib().ffa_last_device_error(ctx)})" if st == EDEVICE else "")
+    return C_re, C_im
+
+
+class BatchSyrk:
+    """Batched Low(A_i A_i^T) mod p over a packed layout (ffa_batch_syrk_*)."""
+
+    def __init__(self, ns, ks, p, dA, dC, device_index=0, opts=None, **kw):
+        import numpy as np
+        self.count = len(ns)
+        self.ns = np.ascontiguousarray(ns, dtype=np.int64)
+        self.ks = np.ascontiguousarray(ks, dtype=np.int64)
+        self.p = p
+        self.ctx = context(device_index)
+        self.opts = opts if opts is not None else make_opts(**kw)
+        h = ctypes.c_void_p()
+        _check(lib().ffa_batch_syrk_plan(self.ctx, self.count, self.ns.ctypes.data,
+                                         self.ks.ctypes.data, p, dA, dC, ctypes.byref(self.opts),
+                                         ctypes.byref(h)), "batch plan")
+        self.handle = h
+        self.a_off = np.zeros(self.count, np.int64)
+        self.c_off = np.zeros(self.count, np.int64)
+        at, ct = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().ffa_batch_offsets(h, self.a_off.ctypes.data, self.c_off.ctypes.data,
+                                       ctypes.byref(at), ctypes.byref(ct)))
+        self.a_total, self.c_total = at.value, ct.value
+
+    def run(self, A_packed, C_packed):
+        torch = _torch()
+        lib().ffa_set_stream(self.ctx, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        _check(lib().ffa_batch_syrk_exec(self.handle, ctypes.c_void_p(A_packed.data_ptr()),
+                                         ctypes.c_void_p(C_packed.data_ptr())), "batch exec")
+
+    def close(self):
+        if self.handle:
+            lib().ffa_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

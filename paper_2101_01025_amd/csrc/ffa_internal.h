@@ -1,0 +1,165 @@
+// Internal definitions shared by the planner (host) and the HIP kernels.
+//
+// The recursion of Algorithm 1 (Section 3) is executed level by level:
+//   conditioning -> pre-additions level 0..l-1 (top-down) -> one grouped launch of
+//   every product (all leaf SYRKs and all P3/P4 general products of every level)
+//   -> post-additions level l-1..0 (bottom-up).
+// Each launch reads a device-resident task table.  Tasks address memory as
+// (buffer id, byte offset) so that one table serves every call with the same
+// shape: the kernels receive the buffer base pointers as arguments.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define FFA_HD __host__ __device__
+#else
+#define FFA_HD
+#endif
+
+namespace ffa {
+
+// ---- buffer ids -----------------------------------------------------------
+enum BufId : int32_t {
+    BUF_A = 0,   // caller's A (real part for the Hermitian product)
+    BUF_A2 = 1,  // caller's imaginary part of A
+    BUF_C = 2,   // caller's C (real part)
+    BUF_C2 = 3,  // caller's imaginary part of C
+    BUF_WS = 4,  // library workspace
+    NBUF = 5
+};
+
+struct Bases {
+    char* p[NBUF];
+};
+
+// ---- element formats ------------------------------------------------------
+// Residue storage formats (canonical values in [0, p)) and the caller formats.
+enum Dtype : int32_t {
+    DT_I64 = 0,
+    DT_I32 = 1,
+    DT_U16 = 2,
+    DT_U8 = 3,
+    DT_F64 = 4,
+    DT_I8C = 5,  // centred int8 (input only)
+};
+
+FFA_HD inline int dtype_size(int dt)
+{
+    switch (dt) {
+    case DT_I64: return 8;
+    case DT_I32: return 4;
+    case DT_U16: return 2;
+    case DT_U8: return 1;
+    case DT_F64: return 8;
+    case DT_I8C: return 1;
+    }
+    return 0;
+}
+
+// Carrier of the products: the representation the MFMA units consume.
+enum Carrier : int32_t {
+    CAR_I8 = 0,   // NL balanced int8 limbs per plane (NL = 1 or 2)
+    CAR_F64 = 1,  // fp64 holding exact integers
+};
+
+// Kind of skew-unitary Y (Section 4).
+enum YKind : int32_t {
+    Y_SCALAR = 0,  // Y = a I, a^2 = -1 (Proposition lemsqrt)
+    Y_BLOCKS = 1,  // Y = [[a, b], [-b, a]] (x) I on column halves (Proposition pigeonhole)
+    Y_GAUSS = 2,   // Y = (a + i b) I over F_p[i] (Section 4.4)
+};
+
+// ---- matrix references ----------------------------------------------------
+// Carrier matrix: sub-plane q (q = plane * NL + limb) starts at off + q * ps
+// bytes of buffer buf; rows are ld elements apart.
+struct CarRef {
+    int64_t off;
+    int64_t ps;
+    int32_t buf;
+    int32_t ld;
+};
+
+// Residue matrix: real plane at (buf, off), imaginary plane at (buf2, off2);
+// rows ld elements apart; element format dt.
+struct ResRef {
+    int64_t off;
+    int64_t off2;
+    int32_t buf;
+    int32_t buf2;
+    int32_t ld;
+    int32_t dt;
+};
+
+// ---- field parameters -----------------------------------------------------
+struct FieldParams {
+    int32_t p;
+    int32_t half;      // (p - 1) / 2 for the single-limb centred form
+    int32_t rep_max;   // largest representative of the two-limb form (32639)
+    int32_t ykind;
+    int32_t ya, yb;    // Y coefficients (canonical)
+    int32_t nl;        // limbs per plane (carrier CAR_I8)
+    int32_t cplx;      // 1 for F_p[i]
+    double inv_p;      // 1.0 / p
+};
+
+// ---- tasks ----------------------------------------------------------------
+// One node of the recursion: A is 2h x 2w (after padding); its blocks feed
+// S1..S4 (each h x w).
+struct PreaddTask {
+    CarRef a;
+    CarRef s[4];
+    int32_t h, w;
+};
+
+// Post-additions of one node: products P1..P5 (h x h residues) into the
+// node's C (2h x 2h), rows/columns >= nvalid are not written.
+struct PostaddTask {
+    ResRef p[5];
+    ResRef c;
+    int32_t h;
+    int32_t nvalid;
+};
+
+// One product C = X * phi(Z) restricted to tiles; syrk: X == Z, only the
+// lower triangle (row >= col) is produced.
+struct GemmTask {
+    CarRef x, z;
+    ResRef c;
+    int32_t M, N, K;       // K in carrier elements, a multiple of the k-tile
+    int32_t syrk;
+    int32_t tiles_m, tiles_n;
+    int32_t tile_begin;
+    int32_t pad_;
+};
+
+// Conditioning: caller's A (n x k, format dt_in) into a carrier matrix of
+// npad x kpad (zero padded), planes re (and im, -re for F_p[i]).
+struct CondTask {
+    int32_t n, k, npad, kpad;
+    int32_t lda, dt_in;
+    int32_t buf_re, buf_im;
+    int64_t off_re, off_im;
+    CarRef out;
+};
+
+// ---- launch wrappers (defined in the .hip files) ---------------------------
+// All return a hipError_t value cast to int.
+int launch_zero_flag(int32_t* d_flag, void* stream);
+int launch_condition(const CondTask* d_tasks, int ntasks, int max_blocks, const Bases& b,
+                     const FieldParams& fp, int carrier, int32_t* d_err, void* stream);
+int launch_preadd(const PreaddTask* d_tasks, int ntasks, int h, int w, const Bases& b,
+                  const FieldParams& fp, int carrier, void* stream);
+int launch_postadd(const PostaddTask* d_tasks, int ntasks, int h, const Bases& b,
+                   const FieldParams& fp, void* stream);
+int launch_gemm_i8(const GemmTask* d_tasks, int ntasks, int total_tiles, const Bases& b,
+                   const FieldParams& fp, void* stream);
+int launch_gemm_f64(const GemmTask* d_tasks, int ntasks, int total_tiles, const Bases& b,
+                    const FieldParams& fp, void* stream);
+// tile edge (rows and columns) of the product kernels
+int gemm_tile_i8(int nl, int cplx);
+int gemm_tile_f64();
+// k-tile of the product kernels, in carrier elements
+constexpr int KTILE_I8 = 64;
+constexpr int KTILE_F64 = 16;
+
+}  // namespace ffa

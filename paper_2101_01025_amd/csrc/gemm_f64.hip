@@ -1,0 +1,183 @@
+// Grouped product kernel on FP64 MFMA (gfx950 v_mfma_f64_16x16x4_f64) used as
+// an exact integer carrier: operands are centred residues held in doubles and
+// every partial sum is an integer below 2^53 (the planner checks
+// K * ((p-1)/2)^2 < 2^53), so the fused multiply-adds are exact and a single
+// reduction mod p per output ends the product.
+//
+// Same task table as the INT8 kernel (general products of every level and the
+// base-case lower-triangle products in one launch).  LDS rows hold 16 doubles
+// of K; element k of row r sits at position k ^ (r & 15) so that the 8-byte
+// fragment reads of 16 consecutive rows hit distinct banks.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "ffa_internal.h"
+
+namespace ffa {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+constexpr int KTD = 16;  // doubles of K per pipeline stage
+
+__device__ __forceinline__ int xcd_remap_d(int b, int G)
+{
+    const int xcd = b & 7, loc = b >> 3, per = G >> 3, rem = G & 7;
+    return (xcd < rem) ? xcd * (per + 1) + loc : rem * (per + 1) + (xcd - rem) * per + loc;
+}
+
+template <int BT, int WGM, int WGN>
+__global__ void __launch_bounds__(WGM* WGN * 64)
+    gemm_f64(Bases bases, const GemmTask* __restrict__ tasks, int ntasks, FieldParams fp)
+{
+    constexpr int NT = WGM * WGN * 64;
+    constexpr int WM = BT / WGM, WN = BT / WGN;
+    constexpr int FM = WM / 16, FN = WN / 16;
+    constexpr int TILE = BT * KTD;  // doubles
+    constexpr int STAGE = 2 * TILE;
+    constexpr int CH = BT * (KTD / 2) / NT;  // 16-byte chunks per thread per operand
+    static_assert(BT * (KTD / 2) % NT == 0, "chunking");
+
+    extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+    double* lds = reinterpret_cast<double*>(lds_raw);
+
+    const int lid = xcd_remap_d(blockIdx.x, gridDim.x);
+    int lo = 0, hi = ntasks - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tasks[mid].tile_begin <= lid) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmTask T = tasks[lo];
+    const int t = lid - T.tile_begin;
+    int ti, tj;
+    if (T.syrk) {
+        int r = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
+        while ((r + 1) * (r + 2) / 2 <= t) ++r;
+        while (r * (r + 1) / 2 > t) --r;
+        ti = r;
+        tj = t - r * (r + 1) / 2;
+    } else {
+        ti = t / T.tiles_n;
+        tj = t - ti * T.tiles_n;
+    }
+    const int row0 = ti * BT, col0 = tj * BT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
+
+    const double* aptr[CH];
+    const double* bptr[CH];
+    int lpos[CH];
+    bool swap[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+        const int c = tid + i * NT;
+        const int r = c / (KTD / 2), s = c % (KTD / 2);
+        const int ga = min(row0 + r, T.M - 1), gb = min(col0 + r, T.N - 1);
+        aptr[i] = reinterpret_cast<const double*>(bases.p[T.x.buf] + T.x.off) + (int64_t)ga * T.x.ld + 2 * s;
+        bptr[i] = reinterpret_cast<const double*>(bases.p[T.z.buf] + T.z.off) + (int64_t)gb * T.z.ld + 2 * s;
+        lpos[i] = r * KTD + (((2 * s) ^ (r & 15)) & ~1);
+        swap[i] = (r & 1) != 0;
+    }
+    const int nst = T.K / KTD;
+    v2d ra[CH], rb[CH];
+    auto gload = [&](int st) {
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            ra[i] = *reinterpret_cast<const v2d*>(aptr[i] + st * KTD);
+            rb[i] = *reinterpret_cast<const v2d*>(bptr[i] + st * KTD);
+        }
+    };
+    auto sstore = [&](int buf) {
+        double* base = lds + buf * STAGE;
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            v2d a = ra[i], b = rb[i];
+            if (swap[i]) {
+                a = v2d{a.y, a.x};
+                b = v2d{b.y, b.x};
+            }
+            *reinterpret_cast<v2d*>(base + lpos[i]) = a;
+            *reinterpret_cast<v2d*>(base + TILE + lpos[i]) = b;
+        }
+    };
+
+    v4d acc[FM][FN];
+#pragma unroll
+    for (int m = 0; m < FM; ++m)
+#pragma unroll
+        for (int n = 0; n < FN; ++n) acc[m][n] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    if (nst > 0) {
+        gload(0);
+        sstore(0);
+    }
+    __syncthreads();
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int st = 0; st < nst; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nst) gload(st + 1);
+        const double* base = lds + buf * STAGE;
+#pragma unroll
+        for (int ks = 0; ks < KTD / 4; ++ks) {
+            const int k = ks * 4 + lk;
+            double af[FM], bf[FN];
+#pragma unroll
+            for (int m = 0; m < FM; ++m) {
+                const int r = wm0 + m * 16 + lr;
+                af[m] = base[r * KTD + (k ^ (r & 15))];
+            }
+#pragma unroll
+            for (int n = 0; n < FN; ++n) {
+                const int r = wn0 + n * 16 + lr;
+                bf[n] = base[TILE + r * KTD + (k ^ (r & 15))];
+            }
+#pragma unroll
+            for (int m = 0; m < FM; ++m)
+#pragma unroll
+                for (int n = 0; n < FN; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[m], bf[n], acc[m][n], 0, 0, 0);
+        }
+        if (st + 1 < nst) sstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    char* cbase = bases.p[T.c.buf] + T.c.off;
+#pragma unroll
+    for (int m = 0; m < FM; ++m)
+#pragma unroll
+        for (int n = 0; n < FN; ++n)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                // output layout of the 16x16 f64 MFMA: lane group g = lane/16, register v -> row g + 4 v
+                const int i = row0 + wm0 + m * 16 + (lane >> 4) + 4 * v;
+                const int j = col0 + wn0 + n * 16 + (lane & 15);
+                if (i < T.M && j < T.N && (!T.syrk || i >= j))
+                    store_res(cbase, T.c.dt, (int64_t)i * T.c.ld + j,
+                              mod_canon(acc[m][n][v], fp.p, fp.inv_p));
+            }
+}
+
+constexpr int BT_F64 = 128;
+
+int launch_gemm_f64(const GemmTask* d_tasks, int ntasks, int total_tiles, const Bases& b,
+                    const FieldParams& fp, void* stream)
+{
+    if (ntasks <= 0 || total_tiles <= 0) return 0;
+    constexpr int lds_bytes = 2 * 2 * BT_F64 * KTD * 8;
+    auto kern = gemm_f64<BT_F64, 2, 2>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        if (e != hipSuccess) return (int)e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(total_tiles), dim3(256), lds_bytes, (hipStream_t)stream, b,
+                       d_tasks, ntasks, fp);
+    return (int)hipGetLastError();
+}
+
+int gemm_tile_f64() { return BT_F64; }
+
+}  // namespace ffa

@@ -1,0 +1,450 @@
+// Host planner for Algorithm 1 (Section 3) on one GPU.
+//
+// The paper runs the recursion depth-first and in place, with C's unused upper
+// triangle as scratch (schedule table of Section 7).  On the GPU the recursion
+// tree is flattened instead: every node of level i gets its own S1..S4 and
+// P1..P5 in a workspace, the pre-additions of all 3^i nodes of a level form
+// one launch, all products of all levels form ONE grouped launch, and the
+// post-additions run level by level bottom-up.  This order respects every edge
+// of the task DAG of Section 7 (S before the products that read them, all five
+// products before U1..U5).
+//
+// Odd sizes are zero-padded (Section 3 allows padding; Section 4.3 pads the
+// inner dimension so that the block-structured Y has even order): rows to a
+// multiple of 2^levels, columns to a multiple of ktile * 2^levels, which keeps
+// every level's blocks even, every Y of even order and every product's K a
+// multiple of the kernels' k-tile.  Zero rows give zero rows and columns of
+// C, which are not written back; zero columns do not change A A^T.
+#include "plan.h"
+
+#include <algorithm>
+#include <cstdio>
+
+#include "field.h"
+
+namespace ffa {
+
+static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+static bool dtype_in_ok(int dt) { return dt >= FFA_I64 && dt <= FFA_I8_CENTRED; }
+static bool dtype_out_ok(int dt) { return dt >= FFA_I64 && dt <= FFA_F64; }
+
+// Largest p a format can hold as canonical residues.
+static uint64_t dtype_pmax(int dt)
+{
+    switch (dt) {
+    case FFA_U8: return 256;
+    case FFA_I8_CENTRED: return 255;
+    case FFA_U16: return 65536;
+    case FFA_I32: return (1ull << 31);
+    case FFA_F64: return (1ull << 52);
+    default: return (1ull << 62);
+    }
+}
+
+namespace {
+
+struct Builder {
+    Plan& pl;
+    int esize;   // carrier element size in bytes
+    int npo;     // planes per carrier matrix: re, or re, im, -re
+    int rdt;     // residue storage of products
+    int rsize;
+    int bt;      // product tile edge
+    int64_t ws = 0;
+
+    int64_t alloc(int64_t bytes)
+    {
+        const int64_t o = ws;
+        ws += round_up(std::max<int64_t>(bytes, 1), 256);
+        return o;
+    }
+    CarRef new_car(int64_t rows, int64_t cols)
+    {
+        CarRef c;
+        c.buf = BUF_WS;
+        c.ld = (int32_t)cols;
+        c.ps = round_up(rows * cols * esize, 256);
+        c.off = alloc(c.ps * npo * pl.nl);
+        return c;
+    }
+    ResRef new_res(int64_t h)
+    {
+        ResRef r;
+        r.buf = r.buf2 = BUF_WS;
+        r.ld = (int32_t)round_up(h, 64);
+        r.dt = rdt;
+        const int64_t bytes = h * r.ld * rsize;
+        r.off = alloc(bytes);
+        r.off2 = pl.cplx ? alloc(bytes) : r.off;
+        return r;
+    }
+    CarRef view(const CarRef& a, int64_t row, int64_t col) const
+    {
+        CarRef v = a;
+        v.off += (row * a.ld + col) * esize;
+        return v;
+    }
+    void add_gemm(const CarRef& x, const CarRef& z, const ResRef& c, int64_t M, int64_t N,
+                  int64_t K, bool syrk)
+    {
+        GemmTask g{};
+        g.x = x;
+        g.z = z;
+        g.c = c;
+        g.M = (int32_t)M;
+        g.N = (int32_t)N;
+        g.K = (int32_t)K;
+        g.syrk = syrk ? 1 : 0;
+        g.tiles_m = (int32_t)((M + bt - 1) / bt);
+        g.tiles_n = (int32_t)((N + bt - 1) / bt);
+        pl.gemm.push_back(g);
+        pl.max_k = std::max(pl.max_k, K);
+        pl.products_macs += syrk ? M * (M + 1) / 2 * K : M * N * K;
+    }
+    // One node of the recursion: a is rows x cols, its result goes to c.
+    void node(int level, const CarRef& a, int64_t rows, int64_t cols, const ResRef& c,
+              int64_t nvalid)
+    {
+        if (level == pl.levels) {
+            add_gemm(a, a, c, rows, rows, cols, true);
+            return;
+        }
+        const int64_t h = rows / 2, w = cols / 2;
+        PreaddTask pt{};
+        pt.a = a;
+        for (int j = 0; j < 4; ++j) pt.s[j] = new_car(h, w);
+        pt.h = (int32_t)h;
+        pt.w = (int32_t)w;
+        pl.pre[level].push_back(pt);
+        ResRef P[5];
+        for (int j = 0; j < 5; ++j) P[j] = new_res(h);
+        const CarRef A11 = view(a, 0, 0), A12 = view(a, 0, w), A22 = view(a, h, w);
+        add_gemm(A22, pt.s[3], P[2], h, h, w, false);   // P3 = A22 phi(S4)
+        add_gemm(pt.s[0], pt.s[1], P[3], h, h, w, false);  // P4 = S1 phi(S2)
+        node(level + 1, A11, h, w, P[0], h);               // P1 = A11 phi(A11)
+        node(level + 1, A12, h, w, P[1], h);               // P2 = A12 phi(A12)
+        node(level + 1, pt.s[2], h, w, P[4], h);           // P5 = S3 phi(S3)
+        PostaddTask qt{};
+        for (int j = 0; j < 5; ++j) qt.p[j] = P[j];
+        qt.c = c;
+        qt.h = (int32_t)h;
+        qt.nvalid = (int32_t)nvalid;
+        pl.post[level].push_back(qt);
+    }
+};
+
+struct Common {
+    int status = FFA_OK;
+    int carrier = CAR_I8, nl = 1;
+    FieldParams fp{};
+};
+
+// Checks shared by single and batched calls; picks the carrier and Y.
+Common common_setup(uint32_t p, int herm, int dA, int dC, const ffa_opts& o)
+{
+    Common cm;
+    if (!dtype_in_ok(dA) || !dtype_out_ok(dC)) { cm.status = FFA_EINVAL; return cm; }
+    if (o.algo < FFA_ALGO_AUTO || o.algo > FFA_ALGO_RECURSIVE) { cm.status = FFA_EINVAL; return cm; }
+    if (o.carrier < FFA_CARRIER_AUTO || o.carrier > FFA_CARRIER_F64) { cm.status = FFA_EINVAL; return cm; }
+    if (!is_odd_prime(p)) { cm.status = FFA_EPRIME; return cm; }
+    if ((uint64_t)p > dtype_pmax(dA) || (uint64_t)p > dtype_pmax(dC)) { cm.status = FFA_EINVAL; return cm; }
+    if (herm && p % 4 != 3) { cm.status = FFA_EUNSUPPORTED; return cm; }
+    int car = o.carrier;
+    if (car == FFA_CARRIER_AUTO) car = (dA == FFA_F64 && !herm) ? FFA_CARRIER_F64 : FFA_CARRIER_INT8;
+    if (car == FFA_CARRIER_F64) {
+        if (herm) { cm.status = FFA_EUNSUPPORTED; return cm; }
+        if (p >= (1u << 26)) { cm.status = FFA_EPRIME; return cm; }
+        cm.carrier = CAR_F64;
+        cm.nl = 1;
+    } else {
+        if (p >= 65536) { cm.status = FFA_EPRIME; return cm; }
+        cm.carrier = CAR_I8;
+        cm.nl = p < 256 ? 1 : 2;
+    }
+    if (dA == FFA_I8_CENTRED && !(cm.carrier == CAR_I8 && cm.nl == 1)) {
+        cm.status = FFA_EINVAL;
+        return cm;
+    }
+    int kind;
+    uint64_t a, b;
+    if (skew_unitary_params(p, herm != 0, &kind, &a, &b)) { cm.status = FFA_EPRIME; return cm; }
+    FieldParams& fp = cm.fp;
+    fp.p = (int32_t)p;
+    fp.half = (int32_t)((p - 1) / 2);
+    fp.rep_max = 32639;
+    fp.ykind = kind;
+    fp.ya = (int32_t)a;
+    fp.yb = (int32_t)b;
+    fp.nl = cm.nl;
+    fp.cplx = herm ? 1 : 0;
+    fp.inv_p = 1.0 / (double)p;
+    return cm;
+}
+
+int default_cutoff(int carrier, int nl, int cplx)
+{
+    if (carrier == CAR_F64) return 512;
+    if (cplx) return 2048;
+    return nl == 1 ? 4096 : 2048;
+}
+
+int choose_levels(int64_t n, int64_t k, const ffa_opts& o, int carrier, int nl, int cplx)
+{
+    if (n < 2 || k == 0) return 0;
+    if (o.algo == FFA_ALGO_CLASSICAL) return 0;
+    int L;
+    if (o.levels >= 0) {
+        L = o.levels;
+    } else {
+        const int64_t cut = o.cutoff > 0 ? o.cutoff : default_cutoff(carrier, nl, cplx);
+        L = 0;
+        for (int64_t m = n; m > cut && L < 10; m = (m + 1) / 2) ++L;
+        if (o.algo == FFA_ALGO_RECURSIVE && L == 0) L = 1;
+    }
+    while (L > 0 && (n >> L) < 1) --L;
+    return L;
+}
+
+// Exact-accumulation bound of the carrier; FFA_OK or FFA_EBOUND.
+int check_bound(const Plan& pl)
+{
+    const double terms = (double)pl.max_k * (pl.cplx ? 2.0 : 1.0);
+    if (pl.carrier == CAR_F64) {
+        const double m = (double)pl.max_abs;
+        return terms * m * m < 9007199254740992.0 ? FFA_OK : FFA_EBOUND;
+    }
+    if (pl.nl == 1) {
+        const double m = (double)pl.max_abs;
+        return terms * m * m < 2147483648.0 ? FFA_OK : FFA_EBOUND;
+    }
+    // two limbs: the middle accumulator sums hi*lo + lo*hi, each at most 128^2
+    return 2.0 * terms * 16384.0 < 2147483648.0 ? FFA_OK : FFA_EBOUND;
+}
+
+void size_grids(Plan& pl)
+{
+    pl.pre_max_h.assign(pl.levels, 0);
+    pl.pre_max_w.assign(pl.levels, 0);
+    pl.post_max_h.assign(pl.levels, 0);
+    for (int l = 0; l < pl.levels; ++l) {
+        for (const auto& t : pl.pre[l]) {
+            pl.pre_max_h[l] = std::max(pl.pre_max_h[l], t.h);
+            pl.pre_max_w[l] = std::max(pl.pre_max_w[l], t.w);
+        }
+        for (const auto& t : pl.post[l]) pl.post_max_h[l] = std::max(pl.post_max_h[l], t.h);
+    }
+    // longest tiles first: sort general products and base cases by K, descending
+    std::stable_sort(pl.gemm.begin(), pl.gemm.end(),
+                     [](const GemmTask& a, const GemmTask& b) { return a.K > b.K; });
+    int tiles = 0;
+    for (auto& g : pl.gemm) {
+        g.tile_begin = tiles;
+        tiles += g.syrk ? g.tiles_m * (g.tiles_m + 1) / 2 : g.tiles_m * g.tiles_n;
+    }
+    pl.total_tiles = tiles;
+}
+
+// Adds one problem's conditioning and recursion tree to the plan.
+int add_problem(Plan& pl, Builder& B, const Problem& pr, int levels, bool allow_direct)
+{
+    const int ktile = pl.carrier == CAR_F64 ? KTILE_F64 : KTILE_I8;
+    const int64_t npad = round_up(pr.n, (int64_t)1 << levels);
+    const int64_t kpad = round_up(pr.k, (int64_t)ktile << levels);
+    if (npad >= (1ll << 31) || kpad >= (1ll << 31)) return FFA_EINVAL;
+    if (pl.npad == 0) {
+        pl.npad = npad;
+        pl.kpad = kpad;
+    }
+    const int in_size = dtype_size(pr.dA);
+    const bool in_matches = (pl.carrier == CAR_I8 && pl.nl == 1 && !pl.cplx && pr.dA == FFA_I8_CENTRED) ||
+                            (pl.carrier == CAR_F64 && pr.dA == FFA_F64);
+    const bool direct = allow_direct && in_matches && !pl.check_inputs && npad == pr.n &&
+                        kpad == pr.k && pr.aligned && ((pr.lda * in_size) % 16 == 0) &&
+                        ((pr.a_off * in_size) % 16 == 0);
+    CarRef a;
+    if (direct) {
+        a.buf = BUF_A;
+        a.off = pr.a_off * in_size;
+        a.ps = 0;
+        a.ld = (int32_t)pr.lda;
+        pl.direct = true;
+    } else {
+        a = B.new_car(npad, kpad);
+        CondTask ct{};
+        ct.n = (int32_t)pr.n;
+        ct.k = (int32_t)pr.k;
+        ct.npad = (int32_t)npad;
+        ct.kpad = (int32_t)kpad;
+        ct.lda = (int32_t)pr.lda;
+        ct.dt_in = pr.dA;
+        ct.buf_re = BUF_A;
+        ct.buf_im = BUF_A2;
+        ct.off_re = ct.off_im = pr.a_off * in_size;
+        ct.out = a;
+        pl.cond.push_back(ct);
+        const int64_t vec = pl.carrier == CAR_F64 ? 1 : 16;
+        const int64_t blocks = (npad * (kpad / vec) + 255) / 256;
+        if (blocks >= (1ll << 31)) return FFA_EINVAL;
+        pl.cond_max_blocks = (int)std::max<int64_t>(pl.cond_max_blocks, blocks);
+    }
+    // largest operand magnitude: centred carriers, except direct canonical fp64
+    if (pl.carrier == CAR_F64) pl.max_abs = std::max<int>(pl.max_abs, direct ? (int)pl.fp.p - 1 : pl.fp.half);
+    else pl.max_abs = std::max<int>(pl.max_abs, pl.nl == 1 ? pl.fp.half : 32896);
+    ResRef c;
+    c.buf = BUF_C;
+    c.buf2 = BUF_C2;
+    c.off = c.off2 = pr.c_off * dtype_size(pr.dC);
+    c.ld = (int32_t)pr.ldc;
+    c.dt = pr.dC;
+    if (levels == 0) {
+        B.add_gemm(a, a, c, pr.n, pr.n, kpad, true);
+    } else {
+        B.node(0, a, npad, kpad, c, pr.n);
+    }
+    return FFA_OK;
+}
+
+Builder make_builder(Plan& pl)
+{
+    Builder B{pl};
+    B.esize = pl.carrier == CAR_F64 ? 8 : 1;
+    B.npo = pl.cplx ? 3 : 1;
+    B.rdt = pl.fp.p < 256 ? DT_U8 : (pl.fp.p < 65536 ? DT_U16 : DT_I32);
+    B.rsize = dtype_size(B.rdt);
+    B.bt = pl.carrier == CAR_F64 ? gemm_tile_f64() : gemm_tile_i8(pl.nl, pl.cplx);
+    return B;
+}
+
+}  // namespace
+
+Plan make_plan(const Problem& pr)
+{
+    Plan pl;
+    const ffa_opts& o = pr.opts;
+    if (pr.n < 0 || pr.k < 0) { pl.status = FFA_EINVAL; return pl; }
+    Common cm = common_setup(pr.p, pr.herm, pr.dA, pr.dC, o);
+    if (cm.status) { pl.status = cm.status; return pl; }
+    if (pr.n > 0 && pr.k > 0 && pr.lda < pr.k) { pl.status = FFA_EINVAL; return pl; }
+    if (pr.n > 0 && pr.ldc < pr.n) { pl.status = FFA_EINVAL; return pl; }
+    if (pr.lda >= (1ll << 31) || pr.ldc >= (1ll << 31) || pr.n >= (1ll << 30)) { pl.status = FFA_EINVAL; return pl; }
+    pl.carrier = cm.carrier;
+    pl.nl = cm.nl;
+    pl.cplx = pr.herm ? 1 : 0;
+    pl.fp = cm.fp;
+    pl.check_inputs = o.check_inputs ? 1 : 0;
+    if (pr.n == 0) return pl;
+    pl.levels = choose_levels(pr.n, pr.k, o, pl.carrier, pl.nl, pl.cplx);
+    pl.pre.assign(pl.levels, {});
+    pl.post.assign(pl.levels, {});
+    Builder B = make_builder(pl);
+    int st = add_problem(pl, B, pr, pl.levels, true);
+    if (st) { pl.status = st; return pl; }
+    pl.ws_bytes = B.ws;
+    pl.status = check_bound(pl);
+    pl.zero_fill = pr.k == 0;
+    size_grids(pl);
+    return pl;
+}
+
+Plan make_batch_plan(const std::vector<Problem>& prs)
+{
+    Plan pl;
+    if (prs.empty()) { pl.status = FFA_EINVAL; return pl; }
+    const Problem& p0 = prs[0];
+    Common cm = common_setup(p0.p, p0.herm, p0.dA, p0.dC, p0.opts);
+    if (cm.status) { pl.status = cm.status; return pl; }
+    pl.carrier = cm.carrier;
+    pl.nl = cm.nl;
+    pl.cplx = p0.herm ? 1 : 0;
+    pl.fp = cm.fp;
+    pl.check_inputs = p0.opts.check_inputs ? 1 : 0;
+    int maxL = 0;
+    std::vector<int> L(prs.size());
+    for (size_t i = 0; i < prs.size(); ++i) {
+        if (prs[i].n < 0 || prs[i].k < 0 || prs[i].n >= (1ll << 30) || prs[i].k >= (1ll << 30)) {
+            pl.status = FFA_EINVAL;
+            return pl;
+        }
+        L[i] = choose_levels(prs[i].n, prs[i].k, p0.opts, pl.carrier, pl.nl, pl.cplx);
+        maxL = std::max(maxL, L[i]);
+    }
+    pl.levels = maxL;
+    pl.pre.assign(maxL, {});
+    pl.post.assign(maxL, {});
+    Builder B = make_builder(pl);
+    int64_t aoff = 0, coff = 0;
+    const int ain = dtype_size(p0.dA), cout = dtype_size(p0.dC);
+    for (size_t i = 0; i < prs.size(); ++i) {
+        Problem q = prs[i];
+        q.lda = std::max<int64_t>(q.k, 1);
+        q.ldc = std::max<int64_t>(q.n, 1);
+        // keep every problem's A and C 16-byte aligned in the packed buffers
+        q.a_off = aoff;
+        q.c_off = coff;
+        pl.a_off.push_back(aoff);
+        pl.c_off.push_back(coff);
+        aoff += round_up(q.n * q.k * ain, 16) / ain;
+        coff += round_up(q.n * q.n * cout, 16) / cout;
+        if (q.n == 0) continue;
+        // problems of one batch share one set of levels per problem; the
+        // Builder keeps per-level task lists across problems
+        const int saved = pl.levels;
+        pl.levels = L[i];
+        int st = add_problem(pl, B, q, L[i], true);
+        pl.levels = saved;
+        if (st) { pl.status = st; return pl; }
+    }
+    pl.a_total = aoff;
+    pl.c_total = coff;
+    pl.ws_bytes = B.ws;
+    pl.status = check_bound(pl);
+    size_grids(pl);
+    return pl;
+}
+
+std::vector<char> pack_tables(Plan& pl)
+{
+    std::vector<char> blob;
+    auto put = [&](const void* src, size_t bytes) -> int64_t {
+        const int64_t off = round_up((int64_t)blob.size(), 256);
+        blob.resize(off + bytes);
+        if (bytes) std::copy((const char*)src, (const char*)src + bytes, blob.begin() + off);
+        return off;
+    };
+    pl.off_cond = put(pl.cond.data(), pl.cond.size() * sizeof(CondTask));
+    pl.off_pre.assign(pl.levels, 0);
+    pl.off_post.assign(pl.levels, 0);
+    for (int l = 0; l < pl.levels; ++l) {
+        pl.off_pre[l] = put(pl.pre[l].data(), pl.pre[l].size() * sizeof(PreaddTask));
+        pl.off_post[l] = put(pl.post[l].data(), pl.post[l].size() * sizeof(PostaddTask));
+    }
+    pl.off_gemm = put(pl.gemm.data(), pl.gemm.size() * sizeof(GemmTask));
+    pl.blob_bytes = (int64_t)blob.size();
+    return blob;
+}
+
+std::string describe(const Plan& pl)
+{
+    char buf[1024];
+    std::string pre = "[", post = "[";
+    for (int l = 0; l < pl.levels; ++l) {
+        pre += std::to_string(pl.pre[l].size()) + (l + 1 < pl.levels ? "," : "");
+        post += std::to_string(pl.post[l].size()) + (l + 1 < pl.levels ? "," : "");
+    }
+    pre += "]";
+    post += "]";
+    snprintf(buf, sizeof(buf),
+             "{\"status\":%d,\"levels\":%d,\"carrier\":\"%s\",\"limbs\":%d,\"complex\":%d,"
+             "\"npad\":%lld,\"kpad\":%lld,\"direct\":%d,\"max_abs\":%d,\"max_k\":%lld,"
+             "\"ws_bytes\":%lld,\"conditioning\":%zu,\"preadd_tasks\":%s,\"postadd_tasks\":%s,"
+             "\"gemm_tasks\":%zu,\"tiles\":%d,\"macs\":%lld,\"ykind\":%d,\"ya\":%d,\"yb\":%d}",
+             pl.status, pl.levels, pl.carrier == CAR_F64 ? "f64" : "int8", pl.nl, pl.cplx,
+             (long long)pl.npad, (long long)pl.kpad, pl.direct ? 1 : 0, pl.max_abs,
+             (long long)pl.max_k, (long long)pl.ws_bytes, pl.cond.size(), pre.c_str(), post.c_str(),
+             pl.gemm.size(), pl.total_tiles, (long long)pl.products_macs, pl.fp.ykind, pl.fp.ya,
+             pl.fp.yb);
+    return buf;
+}
+
+}  // namespace ffa

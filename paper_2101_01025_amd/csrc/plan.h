@@ -1,0 +1,65 @@
+// Host planner: turns one call (or a batch of calls) into the launch sequence
+// of the level-synchronous schedule and the workspace layout.  No device is
+// touched here, so plans can be built and inspected on a host without a GPU.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ffa.h"
+#include "ffa_internal.h"
+
+namespace ffa {
+
+struct Problem {
+    int64_t n = 0, k = 0, lda = 0, ldc = 0;
+    uint32_t p = 0;
+    int herm = 0;
+    int dA = 0, dC = 0;
+    ffa_opts opts{};
+    bool aligned = true;       // caller's A pointer is 16-byte aligned
+    int64_t a_off = 0;         // element offsets in the caller's buffers (batches)
+    int64_t c_off = 0;
+};
+
+struct Plan {
+    int status = FFA_OK;
+    int carrier = CAR_I8, nl = 1, cplx = 0, levels = 0;
+    int64_t npad = 0, kpad = 0;        // first problem (single calls)
+    bool direct = false;               // products read the caller's A without conditioning
+    int max_abs = 0;                   // largest operand magnitude fed to the products
+    int64_t max_k = 0;                 // longest accumulation (carrier elements)
+    FieldParams fp{};
+    int check_inputs = 0;
+    int zero_fill = 0;                 // k == 0: the output is Low(0)
+    // task tables
+    std::vector<CondTask> cond;
+    int cond_max_blocks = 0;
+    std::vector<std::vector<PreaddTask>> pre;   // per level, top-down
+    std::vector<std::vector<PostaddTask>> post; // per level
+    std::vector<int> pre_max_hw, post_max_h;    // grid sizing per level
+    std::vector<int> pre_max_h, pre_max_w;
+    std::vector<GemmTask> gemm;
+    int total_tiles = 0;
+    int64_t ws_bytes = 0;
+    int64_t products_macs = 0;         // multiply-accumulates of the products (per limb product)
+    std::vector<int64_t> a_off, c_off; // packed batch layout (elements)
+    int64_t a_total = 0, c_total = 0;
+    // device copy of the tables (filled by the API layer)
+    void* d_blob = nullptr;
+    int64_t blob_bytes = 0;
+    int64_t off_cond = 0, off_gemm = 0;
+    std::vector<int64_t> off_pre, off_post;
+};
+
+// Validates and plans one call.  status != FFA_OK means the call must fail
+// with that status before launching anything.
+Plan make_plan(const Problem& pr);
+// Plans a batch of independent problems sharing p and the formats.
+Plan make_batch_plan(const std::vector<Problem>& prs);
+std::string describe(const Plan& pl);
+// Serialises the task tables into one blob with the offsets recorded in pl.
+std::vector<char> pack_tables(Plan& pl);
+
+}  // namespace ffa

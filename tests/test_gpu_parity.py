@@ -1,0 +1,265 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+Integer results, so the bar is bit-exact.  Small and medium cases compare the
+whole lower triangle (several tiles and a ragged tail) and check that the
+strict upper triangle is untouched; the full-size cases compare sampled
+entries computed one by one by the oracle plus a Freivalds check.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SENTINEL = {torch.uint8: 0xA5, torch.int64: -7, torch.int32: -7, torch.float64: -7.0}
+if hasattr(torch, "uint16"):
+    SENTINEL[torch.uint16] = 0xBEEF
+
+
+def _ffa():
+    import paper_2101_01025_amd as ffa
+    return ffa
+
+
+def _dev(a, dtype):
+    if dtype == torch.uint16:
+        return torch.from_numpy(a.astype(np.int32)).to("cuda").to(torch.uint16)
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda").to(dtype)
+
+
+def _host(t):
+    if t.dtype == torch.uint16:
+        t = t.to(torch.int32)
+    return t.cpu().numpy().astype(np.int64)
+
+
+def _sentinel_c(n, dtype):
+    return torch.full((n, n), SENTINEL[dtype], dtype=dtype, device="cuda")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def check_syrk(A_res, p, dA, dC, **kw):
+    """A_res: canonical residues (int64 host).  Runs the GPU call, compares to the oracle."""
+    ffa = _ffa()
+    n, k = A_res.shape
+    _say("syrk", n, k, p, dA, dC, kw)
+    if dA == torch.int8:
+        A = _dev(si.to_centred(A_res, p).astype(np.int8), torch.int8)
+    else:
+        A = _dev(A_res, dA)
+    C = _sentinel_c(n, dC)
+    ffa.syrk_modp(A, p, C=C, **kw)
+    torch.cuda.synchronize()
+    got = _host(C)
+    exp = oracle.syrk_modp(A_res, p)
+    low = np.tril(np.ones((n, n), dtype=bool))
+    assert np.array_equal(got[low], exp[low]), f"lower triangle differs ({n}x{k}, p={p}, {kw})"
+    if n > 1:
+        up = _host(C)[~low]
+        assert (up == np.int64(SENTINEL[dC])).all(), "strict upper triangle was written"
+    return got
+
+
+# ------------------------------------------------------------------ INT8, one limb (p < 256)
+
+@pytest.mark.parametrize("levels", [0, 1, 2, 3])
+@pytest.mark.parametrize("shape", [(1, 1), (7, 13), (100, 64), (257, 300), (600, 520)])
+def test_int8_p251_centred(levels, shape):
+    n, k = shape
+    A = si.uniform_residues(n, k, 251, 100 + n + k)
+    check_syrk(A, 251, torch.int8, torch.uint8, levels=levels)
+
+
+@pytest.mark.parametrize("p", [3, 5, 13, 241])
+def test_int8_small_primes(p):
+    # p = 3 and 251 use Y = [[a,b],[-b,a]] (x) I; p = 5, 13, 241 use Y = sqrt(-1) I
+    A = si.uniform_residues(150, 190, p, p)
+    for levels in (0, 1, 3):
+        check_syrk(A, p, torch.uint8, torch.int64, levels=levels)
+
+
+def test_int8_extremes():
+    # all entries at the largest centred magnitude, at a large K: stresses int32 accumulation
+    p, n, k = 251, 256, 65536
+    for val in (125, 126):  # +125 and -125
+        A = np.full((n, k), val, dtype=np.int64)
+        check_syrk(A, p, torch.int8, torch.uint8, algo=1)
+        check_syrk(A, p, torch.int8, torch.uint8, levels=2)
+
+
+# ------------------------------------------------------------------ INT8, two limbs (p < 2^16)
+
+@pytest.mark.parametrize("levels", [0, 1, 2, 3])
+@pytest.mark.parametrize("shape", [(130, 70), (300, 257), (513, 600)])
+def test_int8x2_p65521(levels, shape):
+    n, k = shape
+    A = si.uniform_residues(n, k, 65521, 200 + n)
+    check_syrk(A, 65521, torch.uint16, torch.uint16, levels=levels)
+
+
+def test_int8x2_extreme_limbs():
+    p = 65521
+    n, k = 200, 30000
+    # representatives with the largest limb magnitudes: -32881 (hi = -128) and 32639 (hi = 127)
+    for v in (p - 32881, 32639, p - 1):
+        A = np.full((n, k), v, dtype=np.int64)
+        check_syrk(A, p, torch.uint16, torch.uint16, algo=1)
+        check_syrk(A, p, torch.int32, torch.int64, levels=1)
+
+
+# ------------------------------------------------------------------ FP64 carrier
+
+@pytest.mark.parametrize("levels", [0, 1, 2, 4])
+def test_f64_p65521(levels):
+    A = si.uniform_residues(300, 333, 65521, 300)
+    check_syrk(A.astype(np.float64), 65521, torch.float64, torch.float64, levels=levels)
+
+
+def test_f64_p131071_and_131041():
+    # the paper's two primes (Section 7): Y blocks for 131071, Y = sqrt(-1) I for 131041
+    for p in (131071, 131041):
+        A = si.uniform_residues(200, 150, p, p)
+        for levels in (0, 2):
+            check_syrk(A, p, torch.int64, torch.int64, levels=levels, carrier=2)
+
+
+# ------------------------------------------------------------------ Hermitian product over F_p[i]
+
+def check_herk(Ar, Ai, p, dt, **kw):
+    ffa = _ffa()
+    n, k = Ar.shape
+    _say("herk", n, k, p, dt, kw)
+    Cr, Ci = _sentinel_c(n, dt), _sentinel_c(n, dt)
+    ffa.herk_modp2(_dev(Ar, dt), _dev(Ai, dt), p, C_re=Cr, C_im=Ci, **kw)
+    torch.cuda.synchronize()
+    er, ei = oracle.herk_modp2(Ar, Ai, p)
+    low = np.tril(np.ones((n, n), dtype=bool))
+    gr, gi = _host(Cr), _host(Ci)
+    assert np.array_equal(gr[low], er[low]) and np.array_equal(gi[low], ei[low])
+    if n > 1:
+        assert (gr[~low] == np.int64(SENTINEL[dt])).all() and (gi[~low] == np.int64(SENTINEL[dt])).all()
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("shape", [(130, 70), (257, 200)])
+def test_herk_p65519(levels, shape):
+    n, k = shape
+    Ar, Ai = si.complex_residues(n, k, 65519, 400 + n)
+    check_herk(Ar, Ai, 65519, torch.uint16, levels=levels)
+
+
+@pytest.mark.parametrize("p", [251, 7])
+def test_herk_single_limb(p):
+    Ar, Ai = si.complex_residues(200, 130, p, 500 + p)
+    for levels in (0, 1, 2):
+        check_herk(Ar, Ai, p, torch.int64, levels=levels)
+
+
+# ------------------------------------------------------------------ degenerate cases, errors
+
+def test_degenerate_shapes():
+    ffa = _ffa()
+    # n = 0: nothing to do
+    A = torch.zeros((0, 5), dtype=torch.int64, device="cuda")
+    C = ffa.syrk_modp(A, 251)
+    assert C.shape == (0, 0)
+    # k = 0: Low(C) = 0, upper untouched
+    A = torch.zeros((6, 0), dtype=torch.int64, device="cuda")
+    C = _sentinel_c(6, torch.int64)
+    ffa.syrk_modp(A, 251, C=C)
+    got = _host(C)
+    low = np.tril(np.ones((6, 6), dtype=bool))
+    assert (got[low] == 0).all() and (got[~low] == -7).all()
+    # one row, one column
+    check_syrk(np.array([[250]], dtype=np.int64), 251, torch.int64, torch.int64)
+    check_syrk(np.arange(9, dtype=np.int64).reshape(9, 1), 251, torch.int64, torch.int64, levels=2)
+
+
+def test_input_range_check_forced_from_host():
+    ffa = _ffa()
+    A = np.full((40, 40), 3, dtype=np.int64)
+    A[17, 5] = 251  # outside [0, p)
+    C = _sentinel_c(40, torch.int64)
+    with pytest.raises(ffa.FfaError) as e:
+        ffa.syrk_modp(_dev(A, torch.int64), 251, C=C, check_inputs=True)
+    assert e.value.status == ffa.ERANGE
+    assert (_host(C) == -7).all()  # nothing written
+
+
+def test_deterministic_repeats():
+    ffa = _ffa()
+    A = _dev(si.centred_int8(700, 650, 251, 9), torch.int8)
+    outs = []
+    for _ in range(3):
+        C = ffa.syrk_modp(A, 251, levels=2)
+        torch.cuda.synchronize()
+        outs.append(_host(C))
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+# ------------------------------------------------------------------ batched
+
+def test_batched_uneven_problems():
+    ffa = _ffa()
+    p = 65521
+    ns, ks = si.batch_shapes(24, 77, nmin=1, nmax=300)
+    mats = si.batch_residues(ns, ks, p, 77)
+    _say("batch", len(ns))
+    for opts in (dict(), dict(levels=1)):
+        B = ffa.BatchSyrk(ns, ks, p, ffa.U16, ffa.U16, **opts)
+        Ap = np.zeros(B.a_total, dtype=np.int64)
+        for i, M in enumerate(mats):
+            Ap[B.a_off[i]:B.a_off[i] + M.size] = M.ravel()
+        Cp = torch.zeros(B.c_total, dtype=torch.int32, device="cuda").to(torch.uint16)
+        B.run(_dev(Ap, torch.uint16), Cp)
+        torch.cuda.synchronize()
+        Ch = _host(Cp)
+        for i, M in enumerate(mats):
+            n = int(ns[i])
+            got = Ch[B.c_off[i]:B.c_off[i] + n * n].reshape(n, n)
+            exp = oracle.syrk_modp(M, p)
+            assert np.array_equal(np.tril(got), exp), f"problem {i} ({n}x{ks[i]})"
+        B.close()
+
+
+# ------------------------------------------------------------------ full size, sampled
+
+def _sample_pairs(n, rng, count=3000):
+    i = rng.integers(0, n, count)
+    j = rng.integers(0, n, count)
+    i, j = np.maximum(i, j), np.minimum(i, j)
+    edges = np.array([0, 1, 255, 256, 257, n // 2 - 1, n // 2, n - 2, n - 1])
+    ei, ej = np.meshgrid(edges, edges)
+    m = ei >= ej
+    return np.concatenate([i, ei[m]]), np.concatenate([j, ej[m]])
+
+
+@pytest.mark.parametrize("algo", ["recursive", "classical"])
+def test_full_size_p251_sampled_and_freivalds(algo):
+    """n = k = 16384, p = 251, int8-centred input: the benchmark's configuration."""
+    ffa = _ffa()
+    n = k = 16384
+    p = 251
+    A8 = si.centred_int8(n, k, p, si.config_seed(2))
+    _say("full", n, k, p, algo)
+    dA = torch.from_numpy(A8).to("cuda")
+    kw = dict(algo=1) if algo == "classical" else dict()
+    C = ffa.syrk_modp(dA, p, **kw)
+    torch.cuda.synchronize()
+    Ch = C.cpu().numpy().astype(np.int64)
+    Ares = np.mod(A8.astype(np.int64), p)
+    rng = np.random.default_rng(5)
+    ii, jj = _sample_pairs(n, rng)
+    exp = oracle.syrk_entries(Ares, p, ii, jj)
+    assert np.array_equal(Ch[ii, jj], exp)
+    Cl = np.tril(Ch)
+    for _ in range(2):
+        x = rng.integers(0, p, n)
+        yc, ya = oracle.freivalds_syrk(Ares, Cl, p, x)
+        assert np.array_equal(yc, ya)

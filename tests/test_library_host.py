@@ -1,0 +1,123 @@
+"""Host-side tests of the C-ABI library: it loads, exports every declared
+symbol, and its planner validates and plans calls without touching a GPU."""
+import os
+import re
+
+import pytest
+
+import oracle
+import paper_2101_01025_amd as ffa
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "ffa.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(ffa_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ffa.lib()
+    names = declared_symbols()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(ffa.SYMBOLS) == names
+
+
+def test_no_oracle_in_library_sources():
+    csrc = os.path.join(ROOT, "paper_2101_01025_amd", "csrc")
+    for f in os.listdir(csrc):
+        if f.endswith((".hip", ".cpp", ".h")):
+            txt = open(os.path.join(csrc, f)).read()
+            assert "oracle" not in txt.lower(), f
+    pkg = open(os.path.join(ROOT, "paper_2101_01025_amd", "__init__.py")).read()
+    assert "import oracle" not in pkg
+
+
+@pytest.mark.parametrize("p,herm", [(251, 0), (65521, 0), (65519, 1), (65519, 0), (3, 0), (7, 1),
+                                    (131071, 0), (131041, 0)])
+def test_skew_unitary_matches_independent_field_code(p, herm):
+    a, b, kind = ffa.skew_unitary(p, herm)
+    oa, ob, _ = oracle.sos(p, -1)
+    assert (a, b) == (oa, ob)
+    assert (a * a + b * b) % p == p - 1
+    assert kind == (2 if herm else (0 if b == 0 else 1))
+
+
+def test_skew_unitary_errors():
+    with pytest.raises(ffa.FfaError):
+        ffa.skew_unitary(9)
+    with pytest.raises(ffa.FfaError):
+        ffa.skew_unitary(65521, hermitian=True)
+
+
+def test_plan_levels_padding_and_carriers():
+    st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8)
+    assert st == 0 and d["carrier"] == "int8" and d["limbs"] == 1 and d["direct"] == 1
+    assert d["levels"] >= 1 and d["npad"] == 16384 and d["kpad"] == 16384
+    assert d["ykind"] == 1 and (d["ya"], d["yb"]) == (80, 80)
+    st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
+                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
+    assert d["levels"] == 0 and d["gemm_tasks"] == 1 and d["tiles"] == 64 * 65 // 2
+    st, d = ffa.plan_describe(1000, 333, 65521, dA=ffa.U16, dC=ffa.U16, opts=ffa.make_opts(levels=3))
+    assert st == 0 and d["limbs"] == 2 and d["levels"] == 3 and d["direct"] == 0
+    assert d["npad"] % 8 == 0 and d["kpad"] % (64 * 8) == 0 and d["kpad"] >= 333
+    assert d["preadd_tasks"] == [1, 3, 9] and d["postadd_tasks"] == [1, 3, 9]
+    assert d["gemm_tasks"] == 27 + 2 * (1 + 3 + 9)
+    st, d = ffa.plan_describe(8192, 8192, 65521, dA=ffa.F64, dC=ffa.F64)
+    assert st == 0 and d["carrier"] == "f64" and d["levels"] == 4 and d["direct"] == 1
+    st, d = ffa.plan_describe(4096, 8192, 65519, hermitian=True, dA=ffa.U16, dC=ffa.U16)
+    assert st == 0 and d["complex"] == 1 and d["ykind"] == 2
+
+
+def test_plan_macs_follow_recursion():
+    # products MACs = 3^l leaf SYRKs + 2 * 3^i general products of level i
+    for L in range(0, 4):
+        n = k = 4096
+        st, d = ffa.plan_describe(n, k, 251, dA=ffa.I8_CENTRED, dC=ffa.U8, opts=ffa.make_opts(levels=L))
+        nl, kl = n >> L, k >> L
+        exp = 3 ** L * nl * (nl + 1) // 2 * kl + sum(2 * 3 ** i * (n >> (i + 1)) ** 2 * (k >> (i + 1))
+                                                   for i in range(L))
+        assert d["macs"] == exp
+
+
+def test_plan_errors():
+    assert ffa.plan_describe(10, 10, 9)[0] == ffa.EPRIME            # not prime
+    assert ffa.plan_describe(10, 10, 2)[0] == ffa.EPRIME            # even
+    assert ffa.plan_describe(10, 10, 65521, hermitian=True)[0] == ffa.EUNSUPPORTED
+    assert ffa.plan_describe(10, 10, 251, lda=5)[0] == ffa.EINVAL   # lda < k
+    assert ffa.plan_describe(10, 10, 251, ldc=5)[0] == ffa.EINVAL   # ldc < n
+    assert ffa.plan_describe(-1, 10, 251)[0] == ffa.EINVAL
+    assert ffa.plan_describe(10, 10, 65521, dA=ffa.U8, dC=ffa.U16)[0] == ffa.EINVAL  # p > 255 in u8
+    assert ffa.plan_describe(10, 10, 65521, dA=ffa.U16, dC=ffa.U8)[0] == ffa.EINVAL
+    assert ffa.plan_describe(10, 10, 65521, dA=ffa.I8_CENTRED, dC=ffa.U16)[0] == ffa.EINVAL
+    assert ffa.plan_describe(10, 10, 131071, dA=ffa.I64, dC=ffa.I64,
+                             opts=ffa.make_opts(carrier=ffa.CARRIER_INT8))[0] == ffa.EPRIME
+    assert ffa.plan_describe(10, 10, 65519, hermitian=True, dA=ffa.F64, dC=ffa.F64)[0] == 0
+    assert ffa.plan_describe(10, 10, 65519, hermitian=True, dA=ffa.F64, dC=ffa.F64,
+                             opts=ffa.make_opts(carrier=ffa.CARRIER_F64))[0] == ffa.EUNSUPPORTED
+    # exact-accumulation bounds: int8 single limb p=251: k * 125^2 < 2^31
+    assert ffa.plan_describe(4, 137408, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
+                             opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))[0] == 0
+    assert ffa.plan_describe(4, 137472, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
+                             opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))[0] == ffa.EBOUND
+    # two limbs: 2 * k * 128^2 < 2^31
+    assert ffa.plan_describe(4, 65472, 65521, dA=ffa.U16, dC=ffa.U16,
+                             opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))[0] == 0
+    assert ffa.plan_describe(4, 65536, 65521, dA=ffa.U16, dC=ffa.U16,
+                             opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))[0] == ffa.EBOUND
+    # fp64: k (p-1)^2 < 2^53 for canonical direct input
+    assert ffa.plan_describe(4, 2098176, 65521, dA=ffa.F64, dC=ffa.F64,
+                             opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))[0] == 0
+    assert ffa.plan_describe(4, 2098192, 65521, dA=ffa.F64, dC=ffa.F64,
+                             opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))[0] == ffa.EBOUND
+
+
+def test_degenerate_plans():
+    st, d = ffa.plan_describe(0, 10, 251)
+    assert st == 0 and d["gemm_tasks"] == 0
+    st, d = ffa.plan_describe(5, 0, 251)
+    assert st == 0 and d["levels"] == 0 and d["gemm_tasks"] == 1
+    st, d = ffa.plan_describe(1, 7, 251, opts=ffa.make_opts(levels=3))
+    assert st == 0 and d["levels"] == 0
