@@ -193,17 +193,20 @@ int run_plan(ffa_ctx* c, Plan& pl, Bases b)
     if (!pl.gemm.empty()) {
         ev = phase_begin(c);
         const GemmTask* g = (const GemmTask*)(blob + pl.off_gemm);
-        e = pl.carrier == CAR_F64
-                ? launch_gemm_f64(g, (int)pl.gemm.size(), pl.total_tiles, b, pl.fp, s)
-                : launch_gemm_i8(g, (int)pl.gemm.size(), pl.total_tiles, b, pl.fp, s);
+        const TileEnt* sc = (const TileEnt*)(blob + pl.off_sched);
+        const int nb = (int)pl.sched.size();
+        e = pl.carrier == CAR_F64 ? launch_gemm_f64(g, sc, nb, b, pl.fp, s)
+                                  : launch_gemm_i8(pl.gemm_cfg, g, sc, nb, b, pl.fp, s);
         if (e) return dev_fail(c, e);
         phase_end(c, ev, 2);
     }
     ev = pl.levels > 0 ? phase_begin(c) : nullptr;
     for (int l = pl.levels - 1; l >= 0; --l) {
         if (pl.post[l].empty()) continue;
+        // every task of a level writes the same format: the caller's C at level 0,
+        // product residues below
         e = launch_postadd((const PostaddTask*)(blob + pl.off_post[l]), (int)pl.post[l].size(),
-                           pl.post_max_h[l], b, pl.fp, s);
+                           pl.post_max_h[l], pl.post[l][0].c.dt, b, pl.fp, s);
         if (e) return dev_fail(c, e);
     }
     phase_end(c, ev, 3);

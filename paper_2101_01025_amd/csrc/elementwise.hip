@@ -8,6 +8,8 @@
 // Every value is reduced mod p where it is produced.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.h"
 #include "ffa_internal.h"
 
@@ -119,12 +121,19 @@ __device__ __forceinline__ int32_t car_val(const int8_t* hi, const int8_t* lo, i
     return NL == 1 ? (int32_t)hi[e] : 256 * (int32_t)hi[e] + (int32_t)lo[e];
 }
 
-// Reduce an exact integer to the carrier representative of its residue.
+// Reduce an exact integer to the carrier representative of its residue.  One
+// limb (p < 256): every intermediate is below 2^20 and int32 / fp32 arithmetic is
+// exact; two limbs: products reach 2^32 and are formed in fp64 (exact below 2^53).
 template <int NL>
-__device__ __forceinline__ int32_t to_rep(double v, const FieldParams& fp)
+struct PreArith {
+    typedef typename std::conditional<NL == 1, int32_t, double>::type T;
+};
+
+template <int NL>
+__device__ __forceinline__ int32_t to_rep(typename PreArith<NL>::T v, const FieldParams& fp)
 {
     if (NL == 1) return mod_centred_small((int32_t)v, fp.p, (float)fp.inv_p);
-    return rep2(mod_canon(v, fp.p, fp.inv_p), fp.p);
+    return rep2(mod_canon((double)v, fp.p, fp.inv_p), fp.p);
 }
 
 template <int NL>
@@ -181,7 +190,8 @@ __global__ void __launch_bounds__(256) preadd_i8(const PreaddTask* tasks, Bases 
     }
     alignas(16) vec_t out[4][2][NPO][NL];
     const int32_t p = fp.p;
-    const double ya = fp.ya, yb = fp.yb;
+    typedef typename PreArith<NL>::T AT;
+    const AT ya = (AT)fp.ya, yb = (AT)fp.yb;
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
         // x[blk][half][plane]
@@ -198,34 +208,34 @@ __global__ void __launch_bounds__(256) preadd_i8(const PreaddTask* tasks, Bases 
         int32_t s[4][2][2];  // S1..S4, half, plane
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
-            double d[2], a21y[2];  // (A21 - A11) Y and A21 Y on this half
+            AT d[2], a21y[2];  // (A21 - A11) Y and A21 Y on this half
             if (fp.ykind == Y_BLOCKS) {
                 // [X_L | X_R] Y = [a X_L - b X_R | b X_L + a X_R]
-                const double dl = x[2][0][0] - x[0][0][0], dr = x[2][1][0] - x[0][1][0];
-                const double el = x[2][0][0], er = x[2][1][0];
+                const AT dl = x[2][0][0] - x[0][0][0], dr = x[2][1][0] - x[0][1][0];
+                const AT el = x[2][0][0], er = x[2][1][0];
                 d[0] = half == 0 ? ya * dl - yb * dr : yb * dl + ya * dr;
                 a21y[0] = half == 0 ? ya * el - yb * er : yb * el + ya * er;
                 d[1] = a21y[1] = 0;
             } else if (fp.ykind == Y_GAUSS) {
                 // (u + iv)(a + ib) = (au - bv) + i(bu + av)
-                const double du = x[2][half][0] - x[0][half][0];
-                const double dv = x[2][half][1] - x[0][half][1];
-                const double eu = x[2][half][0], ev = x[2][half][1];
+                const AT du = x[2][half][0] - x[0][half][0];
+                const AT dv = x[2][half][1] - x[0][half][1];
+                const AT eu = x[2][half][0], ev = x[2][half][1];
                 d[0] = ya * du - yb * dv;
                 d[1] = yb * du + ya * dv;
                 a21y[0] = ya * eu - yb * ev;
                 a21y[1] = yb * eu + ya * ev;
             } else {
-                d[0] = ya * (double)(x[2][half][0] - x[0][half][0]);
-                a21y[0] = ya * (double)x[2][half][0];
+                d[0] = ya * (AT)(x[2][half][0] - x[0][half][0]);
+                a21y[0] = ya * (AT)x[2][half][0];
                 d[1] = a21y[1] = 0;
             }
 #pragma unroll
             for (int q = 0; q < NPI; ++q) {
                 const int32_t s1 = to_rep<NL>(d[q], fp);
-                const int32_t s2 = to_rep<NL>((double)x[3][half][q] - a21y[q], fp);
-                const int32_t s3 = to_rep<NL>((double)(s1 - x[3][half][q]), fp);
-                const int32_t s4 = to_rep<NL>((double)(s3 + x[1][half][q]), fp);
+                const int32_t s2 = to_rep<NL>((AT)x[3][half][q] - a21y[q], fp);
+                const int32_t s3 = to_rep<NL>((AT)(s1 - x[3][half][q]), fp);
+                const int32_t s4 = to_rep<NL>((AT)(s3 + x[1][half][q]), fp);
                 s[0][half][q] = s1;
                 s[1][half][q] = s2;
                 s[2][half][q] = s3;
@@ -343,9 +353,30 @@ __device__ __forceinline__ void load_row16(const char* base, int ld, int row, in
     }
 }
 
+// Stores 16 consecutive elements of a row: one or more 16-byte vector stores
+// when all are wanted and the address is aligned, element stores otherwise.
+template <typename OT>
+__device__ __forceinline__ void store_row16(char* base, int64_t idx, const int32_t* v, int nwant)
+{
+    OT* dst = reinterpret_cast<OT*>(base) + idx;
+    if (nwant >= 16 && ((uintptr_t)dst & 15) == 0) {
+        alignas(16) OT tmp[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) tmp[e] = (OT)v[e];
+#pragma unroll
+        for (int q = 0; q < (int)(16 * sizeof(OT) / 16); ++q)
+            reinterpret_cast<int4*>(dst)[q] = reinterpret_cast<const int4*>(tmp)[q];
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            if (e < nwant) dst[e] = (OT)v[e];
+    }
+}
+
 // Lower tile pairs (R, C), R >= C, of 64 x 64 tiles of the h x h blocks; one
-// workgroup of 256 threads per pair; thread = (row tr, 16-column group).
-template <typename RT, int CPLX>
+// workgroup of 256 threads per pair; thread = (row tr, 16-column group).  All
+// loads and stores move 16 consecutive elements of a row.
+template <typename RT, typename OT, int CPLX>
 __global__ void __launch_bounds__(256) postadd(const PostaddTask* tasks, Bases b, FieldParams fp)
 {
     constexpr int TS = 64;
@@ -378,9 +409,8 @@ __global__ void __launch_bounds__(256) postadd(const PostaddTask* tasks, Bases b
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
+        for (int e = 0; e < 16; ++e)
             P1[q][e] = P2[q][e] = P3[q][e] = P4[q][e] = P5[q][e] = Q3[q][e] = Q4[q][e] = 0;
-        }
         if (gi < h && gj0 < h) {
             load_row16<RT>(plane(T.p[0], q), T.p[0].ld, gi, gj0, P1[q]);
             load_row16<RT>(plane(T.p[1], q), T.p[1].ld, gi, gj0, P2[q]);
@@ -405,48 +435,53 @@ __global__ void __launch_bounds__(256) postadd(const PostaddTask* tasks, Bases b
         }
     __syncthreads();
 
-    // output plane pointers and the node's C layout: C11 at (0,0), C21 at (h,0), C22 at (h,h)
-    const int nv = T.nvalid, ldc = T.c.ld, dt = T.c.dt;
+    // the node's C: C11 at (0,0), C21 at (h,0), C22 at (h,h); rows/cols >= nvalid not written
+    const int nv = T.nvalid;
+    const int64_t ldc = T.c.ld;
     char* cpl[2] = {b.p[T.c.buf] + T.c.off, b.p[T.c.buf2] + T.c.off2};
-    auto put = [&](int q, int row, int col, int32_t v) {
-        if (row < nv && col < nv) store_res(cpl[q], dt, (int64_t)row * ldc + col, v);
-    };
-    // conjugation sign of the imaginary plane under phi
+    // conjugation of the imaginary plane under phi
     auto conjv = [&](int q, int32_t v) { return q == 1 ? neg_mod(v, p) : v; };
+    // number of the 16 columns starting at col that are inside [0, lim)
+    auto cnt = [](int col, int lim) { return max(0, min(16, lim - col)); };
 
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int gj = gj0 + e;
-        if (gi >= h || gj >= h) continue;
-        const int lc = tc + e;
+    if (gi < h) {
+        const int wantC = cnt(gj0, min(h, nv));            // C11 columns
+        const int wantH = cnt(h + gj0, nv);                // C21 / C22 columns (offset h)
+        const int lowlen = diag ? min(16, max(0, tr - tc + 1)) : 16;  // entries with col <= row
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            // phi(Low(U1)) above the diagonal of the diagonal tile; P4^phi at (gi, gj)
-            int32_t u1full = U1[q][e];
-            if (diag && lc > tr) u1full = conjv(q, u1s[q][lc][tr]);
-            const int32_t p4t = conjv(q, p4s[q][lc][tr]);
-            const int32_t u2 = add_mod(u1full, P4[q][e], p);
-            // C21 = U4 = U2 + P3 (full block)
-            put(q, h + gi, gj, add_mod(u2, P3[q][e], p));
-            if (!diag || lc <= tr) {
-                // C11 = Low(U3) = Low(P1 + P2); C22 = Low(U5) = Low(U2 + phi(P4))
-                put(q, gi, gj, add_mod(P1[q][e], P2[q][e], p));
-                put(q, h + gi, h + gj, add_mod(u2, p4t, p));
+            int32_t c11[16], c21[16], c22[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int lc = tc + e;
+                // phi(Low(U1)) above the diagonal of the diagonal tile; P4^phi at (gi, gj)
+                int32_t u1full = U1[q][e];
+                if (diag && lc > tr) u1full = conjv(q, u1s[q][lc][tr]);
+                const int32_t p4t = conjv(q, p4s[q][lc][tr]);
+                const int32_t u2 = add_mod(u1full, P4[q][e], p);
+                c21[e] = add_mod(u2, P3[q][e], p);     // U4 = U2 + P3
+                c11[e] = add_mod(P1[q][e], P2[q][e], p);  // U3 = P1 + P2
+                c22[e] = add_mod(u2, p4t, p);          // U5 = U2 + phi(P4)
+            }
+            if (gi < nv) store_row16<OT>(cpl[q], (int64_t)gi * ldc + gj0, c11, min(wantC, lowlen));
+            if (h + gi < nv) {
+                store_row16<OT>(cpl[q], (int64_t)(h + gi) * ldc + gj0, c21, wantC);
+                store_row16<OT>(cpl[q], (int64_t)(h + gi) * ldc + h + gj0, c22, min(wantH, lowlen));
             }
         }
     }
-    if (!diag) {
+    if (!diag && mi < h && h + mi < nv) {
         // tile (C, R) of C21: U1 there is phi of the staged lower tile (R, C)
+        const int want = cnt(mj0, min(h, nv));
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int gj = mj0 + e;
-            if (mi >= h || gj >= h) continue;
-            const int lc = tc + e;
+        for (int q = 0; q < NP; ++q) {
+            int32_t c21[16];
 #pragma unroll
-            for (int q = 0; q < NP; ++q) {
-                const int32_t u1 = conjv(q, u1s[q][lc][tr]);
-                put(q, h + mi, gj, add_mod(add_mod(u1, Q4[q][e], p), Q3[q][e], p));
+            for (int e = 0; e < 16; ++e) {
+                const int32_t u1 = conjv(q, u1s[q][tc + e][tr]);
+                c21[e] = add_mod(add_mod(u1, Q4[q][e], p), Q3[q][e], p);
             }
+            store_row16<OT>(cpl[q], (int64_t)(h + mi) * ldc + mj0, c21, want);
         }
     }
 }
@@ -505,7 +540,21 @@ int launch_preadd(const PreaddTask* d_tasks, int ntasks, int h, int w, const Bas
     return (int)hipGetLastError();
 }
 
-int launch_postadd(const PostaddTask* d_tasks, int ntasks, int h, const Bases& b,
+template <typename RT, int CPLX>
+static void launch_post_rt(dim3 g, hipStream_t s, const PostaddTask* d_tasks, const Bases& b,
+                           const FieldParams& fp, int out_dt)
+{
+    switch (out_dt) {
+    case DT_U8: hipLaunchKernelGGL((postadd<RT, uint8_t, CPLX>), g, dim3(256), 0, s, d_tasks, b, fp); break;
+    case DT_U16: hipLaunchKernelGGL((postadd<RT, uint16_t, CPLX>), g, dim3(256), 0, s, d_tasks, b, fp); break;
+    case DT_I32: hipLaunchKernelGGL((postadd<RT, int32_t, CPLX>), g, dim3(256), 0, s, d_tasks, b, fp); break;
+    case DT_I64: hipLaunchKernelGGL((postadd<RT, int64_t, CPLX>), g, dim3(256), 0, s, d_tasks, b, fp); break;
+    case DT_F64: hipLaunchKernelGGL((postadd<RT, double, CPLX>), g, dim3(256), 0, s, d_tasks, b, fp); break;
+    default: break;
+    }
+}
+
+int launch_postadd(const PostaddTask* d_tasks, int ntasks, int h, int out_dt, const Bases& b,
                    const FieldParams& fp, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
@@ -513,14 +562,14 @@ int launch_postadd(const PostaddTask* d_tasks, int ntasks, int h, const Bases& b
     const int nt = (h + 63) / 64;
     dim3 g(nt * (nt + 1) / 2, ntasks);
     if (fp.p < 256) {
-        if (fp.cplx) hipLaunchKernelGGL((postadd<uint8_t, 1>), g, dim3(256), 0, s, d_tasks, b, fp);
-        else hipLaunchKernelGGL((postadd<uint8_t, 0>), g, dim3(256), 0, s, d_tasks, b, fp);
+        if (fp.cplx) launch_post_rt<uint8_t, 1>(g, s, d_tasks, b, fp, out_dt);
+        else launch_post_rt<uint8_t, 0>(g, s, d_tasks, b, fp, out_dt);
     } else if (fp.p < 65536) {
-        if (fp.cplx) hipLaunchKernelGGL((postadd<uint16_t, 1>), g, dim3(256), 0, s, d_tasks, b, fp);
-        else hipLaunchKernelGGL((postadd<uint16_t, 0>), g, dim3(256), 0, s, d_tasks, b, fp);
+        if (fp.cplx) launch_post_rt<uint16_t, 1>(g, s, d_tasks, b, fp, out_dt);
+        else launch_post_rt<uint16_t, 0>(g, s, d_tasks, b, fp, out_dt);
     } else {
-        if (fp.cplx) hipLaunchKernelGGL((postadd<int32_t, 1>), g, dim3(256), 0, s, d_tasks, b, fp);
-        else hipLaunchKernelGGL((postadd<int32_t, 0>), g, dim3(256), 0, s, d_tasks, b, fp);
+        if (fp.cplx) launch_post_rt<int32_t, 1>(g, s, d_tasks, b, fp, out_dt);
+        else launch_post_rt<int32_t, 0>(g, s, d_tasks, b, fp, out_dt);
     }
     return (int)hipGetLastError();
 }

@@ -128,8 +128,12 @@ struct GemmTask {
     int32_t M, N, K;       // K in carrier elements, a multiple of the k-tile
     int32_t syrk;
     int32_t tiles_m, tiles_n;
-    int32_t tile_begin;
-    int32_t pad_;
+};
+
+// One entry of a product launch's schedule: x = task index (-1: idle entry),
+// y = tile row | tile column << 16.
+struct TileEnt {
+    int32_t x, y;
 };
 
 // Conditioning: caller's A (n x k, format dt_in) into a carrier matrix of
@@ -149,17 +153,22 @@ int launch_condition(const CondTask* d_tasks, int ntasks, int max_blocks, const 
                      const FieldParams& fp, int carrier, int32_t* d_err, void* stream);
 int launch_preadd(const PreaddTask* d_tasks, int ntasks, int h, int w, const Bases& b,
                   const FieldParams& fp, int carrier, void* stream);
-int launch_postadd(const PostaddTask* d_tasks, int ntasks, int h, const Bases& b,
+// out_dt: format of the outputs of this level (every task of a launch shares it)
+int launch_postadd(const PostaddTask* d_tasks, int ntasks, int h, int out_dt, const Bases& b,
                    const FieldParams& fp, void* stream);
-int launch_gemm_i8(const GemmTask* d_tasks, int ntasks, int total_tiles, const Bases& b,
-                   const FieldParams& fp, void* stream);
-int launch_gemm_f64(const GemmTask* d_tasks, int ntasks, int total_tiles, const Bases& b,
+// Product launches read the task table and a schedule: entry blockIdx = (task,
+// tile row | tile column << 16), or task = -1 for an idle padding entry.
+int launch_gemm_i8(int cfg, const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks,
+                   const Bases& b, const FieldParams& fp, void* stream);
+int launch_gemm_f64(const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks, const Bases& b,
                     const FieldParams& fp, void* stream);
-// tile edge (rows and columns) of the product kernels
-int gemm_tile_i8(int nl, int cplx);
+// INT8 product kernel configurations (tile shapes, pipeline depth)
+int gemm_i8_config_tile(int cfg);
+int gemm_i8_config_ktile(int cfg);
+int gemm_i8_config_valid(int cfg, int nl, int cplx);
+int gemm_i8_default_config(int nl, int cplx, int64_t max_dim);
 int gemm_tile_f64();
-// k-tile of the product kernels, in carrier elements
-constexpr int KTILE_I8 = 64;
+// k-tile of the FP64 product kernel, in carrier elements
 constexpr int KTILE_F64 = 16;
 
 }  // namespace ffa

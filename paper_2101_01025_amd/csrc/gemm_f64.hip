@@ -20,15 +20,10 @@ typedef double v2d __attribute__((ext_vector_type(2)));
 
 constexpr int KTD = 16;  // doubles of K per pipeline stage
 
-__device__ __forceinline__ int xcd_remap_d(int b, int G)
-{
-    const int xcd = b & 7, loc = b >> 3, per = G >> 3, rem = G & 7;
-    return (xcd < rem) ? xcd * (per + 1) + loc : rem * (per + 1) + (xcd - rem) * per + loc;
-}
-
 template <int BT, int WGM, int WGN>
 __global__ void __launch_bounds__(WGM* WGN * 64)
-    gemm_f64(Bases bases, const GemmTask* __restrict__ tasks, int ntasks, FieldParams fp)
+    gemm_f64(Bases bases, const GemmTask* __restrict__ tasks, const TileEnt* __restrict__ sched,
+             FieldParams fp)
 {
     constexpr int NT = WGM * WGN * 64;
     constexpr int WM = BT / WGM, WN = BT / WGN;
@@ -41,27 +36,10 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     extern __shared__ __attribute__((aligned(16))) char lds_raw[];
     double* lds = reinterpret_cast<double*>(lds_raw);
 
-    const int lid = xcd_remap_d(blockIdx.x, gridDim.x);
-    int lo = 0, hi = ntasks - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tasks[mid].tile_begin <= lid) lo = mid;
-        else hi = mid - 1;
-    }
-    const GemmTask T = tasks[lo];
-    const int t = lid - T.tile_begin;
-    int ti, tj;
-    if (T.syrk) {
-        int r = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
-        while ((r + 1) * (r + 2) / 2 <= t) ++r;
-        while (r * (r + 1) / 2 > t) --r;
-        ti = r;
-        tj = t - r * (r + 1) / 2;
-    } else {
-        ti = t / T.tiles_n;
-        tj = t - ti * T.tiles_n;
-    }
-    const int row0 = ti * BT, col0 = tj * BT;
+    const TileEnt ent = sched[blockIdx.x];
+    if (ent.x < 0) return;  // padding entry of the XCD-balanced schedule
+    const GemmTask T = tasks[ent.x];
+    const int row0 = (ent.y & 0xffff) * BT, col0 = (ent.y >> 16) * BT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
 
@@ -160,10 +138,10 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
 
 constexpr int BT_F64 = 128;
 
-int launch_gemm_f64(const GemmTask* d_tasks, int ntasks, int total_tiles, const Bases& b,
+int launch_gemm_f64(const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks, const Bases& b,
                     const FieldParams& fp, void* stream)
 {
-    if (ntasks <= 0 || total_tiles <= 0) return 0;
+    if (nblocks <= 0) return 0;
     constexpr int lds_bytes = 2 * 2 * BT_F64 * KTD * 8;
     auto kern = gemm_f64<BT_F64, 2, 2>;
     static bool attr_set = false;
@@ -173,8 +151,8 @@ int launch_gemm_f64(const GemmTask* d_tasks, int ntasks, int total_tiles, const 
         if (e != hipSuccess) return (int)e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(kern, dim3(total_tiles), dim3(256), lds_bytes, (hipStream_t)stream, b,
-                       d_tasks, ntasks, fp);
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(256), lds_bytes, (hipStream_t)stream, b,
+                       d_tasks, d_sched, fp);
     return (int)hipGetLastError();
 }
 

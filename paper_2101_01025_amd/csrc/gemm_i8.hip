@@ -3,23 +3,25 @@
 // Computes, for every task of a table, C = X * phi(Z) mod p on square tiles:
 // the general products P3 = A22 phi(S4), P4 = S1 phi(S2) of every recursion
 // level and the base-case products Low(X phi(X)) (Algorithm 1, Section 3) in
-// ONE launch.  A task with syrk = 1 only enumerates tiles on or below the
-// diagonal and writes row >= col.
+// ONE launch.  A task with syrk = 1 only has tiles on or below the diagonal
+// and writes row >= col.
 //
 // Exactness: operands are balanced int8 limbs of residues, accumulation is in
 // int32 and exact (the planner bounds K * max|x| * max|y| below 2^31 for each
 // accumulator); with two limbs x = 256 hi + lo the tile keeps three
-// accumulators hh, (hl + lh), ll and recombines 65536 hh + 256 mid + ll exactly
-// in fp64 before the reduction mod p.
+// accumulators hh, (hl + lh), ll and recombines 65536 hh + 256 mid + ll
+// exactly before the reduction mod p.
 // Complex operands (F_p[i], phi = conjugate transpose) use planes re, im and
 // -re:  Re(X Z^H) = Xr Zr^T + Xi Zi^T,  Im(X Z^H) = Xi Zr^T + (-Xr) Zi^T, i.e.
 // two K-segments that share the B operand (Zr, then Zi) and two A roles.
 //
-// Data movement: global -> registers (prefetch of the next k-tile while the
-// current one is multiplied) -> LDS (double buffer, XOR-swizzled 16-byte
-// segments so that the ds_read_b128 of 32 consecutive rows is conflict free)
-// -> MFMA.  Workgroups are remapped so that consecutive tiles run on the same
-// XCD (round-robin dispatch over the 8 XCDs, each with its own L2).
+// Data movement: global -> registers (a ring of PF k-tiles in flight) -> LDS
+// (double buffer, XOR-swizzled 16-byte segments so that the ds_read_b128 of
+// consecutive rows hits distinct banks) -> MFMA.  Which tile a workgroup
+// computes comes from a host-built schedule indexed by blockIdx: tiles are
+// grouped into L2-friendly blocks and the blocks are dealt to the 8 XCDs
+// (workgroup b runs on XCD b mod 8) so that each XCD's L2 serves a compact set
+// of operand panels and every XCD gets the same amount of work.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -30,31 +32,31 @@ namespace ffa {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int KT8 = 64;  // bytes of K per pipeline stage
-
-__device__ __forceinline__ int swz(int row, int seg)
+// LDS byte offset of 16-byte segment seg of row r in a tile with KT-byte rows.
+template <int KT>
+__device__ __forceinline__ int swz(int r, int seg)
 {
-    return row * KT8 + ((seg ^ ((row >> 2) & 3)) << 4);
+    constexpr int NSEG = KT / 16;
+    constexpr int RPB = 256 / KT;  // rows per 256-byte bank row
+    return r * KT + ((seg ^ ((r / RPB) & (NSEG - 1))) << 4);
 }
 
-__device__ __forceinline__ int xcd_remap(int b, int G)
+// Canonical residue of an int32 for any odd p < 2^16 (|x| < 2^31 - 2^16).
+__device__ __forceinline__ int32_t mod_i32(int32_t x, int32_t p, float inv_p)
 {
-    const int xcd = b & 7, loc = b >> 3, per = G >> 3, rem = G & 7;
-    return (xcd < rem) ? xcd * (per + 1) + loc : rem * (per + 1) + (xcd - rem) * per + loc;
+    int32_t q = (int32_t)floorf((float)x * inv_p);
+    int32_t r = (int32_t)((uint32_t)x - (uint32_t)q * (uint32_t)p);
+    q = (int32_t)floorf((float)r * inv_p);
+    r -= q * p;
+    r += (r < 0) ? p : 0;
+    r -= (r >= p) ? p : 0;
+    return r;
 }
 
-__device__ __forceinline__ void tri_decode(int t, int& ti, int& tj)
-{
-    int r = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
-    while ((r + 1) * (r + 2) / 2 <= t) ++r;
-    while (r * (r + 1) / 2 > t) --r;
-    ti = r;
-    tj = t - r * (r + 1) / 2;
-}
-
-template <int NL, int CPLX, int BT, int WGM, int WGN>
+template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF>
 __global__ void __launch_bounds__(WGM* WGN * 64)
-    gemm_i8(Bases bases, const GemmTask* __restrict__ tasks, int ntasks, FieldParams fp)
+    gemm_i8(Bases bases, const GemmTask* __restrict__ tasks, const TileEnt* __restrict__ sched,
+            FieldParams fp)
 {
     constexpr int NT = WGM * WGN * 64;
     constexpr int NROLE = CPLX ? 2 : 1;
@@ -64,8 +66,9 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     constexpr int WM = BT / WGM, WN = BT / WGN;
     constexpr int FM = WM / 32, FN = WN / 32;
     constexpr int NACC = NL == 1 ? 1 : 3;
-    constexpr int TILE = BT * KT8;
+    constexpr int TILE = BT * KT;
     constexpr int STAGE = (NA + NB) * TILE;
+    constexpr int SPR = KT / 16;  // 16-byte segments per row
     constexpr int ACH = NA * TILE / 16 / NT;
     constexpr int BCH = NB * TILE / 16 / NT;
     static_assert(NA * TILE % (16 * NT) == 0 && NB * TILE % (16 * NT) == 0, "chunking");
@@ -73,69 +76,57 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
 
     extern __shared__ __attribute__((aligned(16))) char lds[];
 
-    // ---- which tile of which task
-    const int lid = xcd_remap(blockIdx.x, gridDim.x);
-    int lo = 0, hi = ntasks - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tasks[mid].tile_begin <= lid) lo = mid;
-        else hi = mid - 1;
-    }
-    const GemmTask T = tasks[lo];
-    const int t = lid - T.tile_begin;
-    int ti, tj;
-    if (T.syrk) tri_decode(t, ti, tj);
-    else {
-        ti = t / T.tiles_n;
-        tj = t - ti * T.tiles_n;
-    }
-    const int row0 = ti * BT, col0 = tj * BT;
+    const TileEnt ent = sched[blockIdx.x];
+    if (ent.x < 0) return;  // padding entry of the XCD-balanced schedule
+    const GemmTask& T = tasks[ent.x];
+    const int row0 = (ent.y & 0xffff) * BT, col0 = (ent.y >> 16) * BT;
+    const int M = T.M, N = T.N, K = T.K;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
 
-    // ---- per-thread global source pointers (segment 0, k = 0)
+    // ---- per-thread global source pointers (segment 0, k = 0) and LDS slots
     const char* aptr[ACH];
     const char* bptr[BCH];
     int alds[ACH], blds[BCH];
 #pragma unroll
     for (int i = 0; i < ACH; ++i) {
         const int c = tid + i * NT;
-        const int sub = c / (BT * 4), r = (c >> 2) % BT, s = c & 3;
-        const int role = sub / NL, limb = sub % NL;
-        const int grow = min(row0 + r, T.M - 1);
-        aptr[i] = bases.p[T.x.buf] + T.x.off + (int64_t)(role * NL + limb) * T.x.ps +
-                  (int64_t)grow * T.x.ld + s * 16;
-        alds[i] = sub * TILE + swz(r, s);
+        const int sub = c / (BT * SPR), r = (c / SPR) % BT, s = c % SPR;
+        const int grow = min(row0 + r, M - 1);
+        aptr[i] = bases.p[T.x.buf] + T.x.off + (int64_t)sub * T.x.ps + (int64_t)grow * T.x.ld + s * 16;
+        alds[i] = sub * TILE + swz<KT>(r, s);
     }
 #pragma unroll
     for (int i = 0; i < BCH; ++i) {
         const int c = tid + i * NT;
-        const int sub = c / (BT * 4), r = (c >> 2) % BT, s = c & 3;
-        const int grow = min(col0 + r, T.N - 1);
-        bptr[i] = bases.p[T.z.buf] + T.z.off + (int64_t)sub * T.z.ps + (int64_t)grow * T.z.ld +
-                  s * 16;
-        blds[i] = (NA + sub) * TILE + swz(r, s);
+        const int sub = c / (BT * SPR), r = (c / SPR) % BT, s = c % SPR;
+        const int grow = min(col0 + r, N - 1);
+        bptr[i] = bases.p[T.z.buf] + T.z.off + (int64_t)sub * T.z.ps + (int64_t)grow * T.z.ld + s * 16;
+        blds[i] = (NA + sub) * TILE + swz<KT>(r, s);
     }
-    const int nkc = T.K / KT8;
+    // Complex: A sub-tile index sub = role * NL + limb reads plane role (segment 0) and
+    // plane role + 1 (segment 1); B reads plane 0 then plane 1.
+    const int nkc = K / KT;
     const int nst = NSEG * nkc;
     const int64_t seg_a = (int64_t)NL * T.x.ps, seg_b = (int64_t)NL * T.z.ps;
 
-    v4i ra[ACH], rb[BCH];
-    auto gload = [&](int st) {
-        const int seg = st / nkc, kc = st - seg * nkc;
-        const int64_t oa = seg * seg_a + (int64_t)kc * KT8;
-        const int64_t ob = seg * seg_b + (int64_t)kc * KT8;
+    v4i ra[PF][ACH], rb[PF][BCH];
+    auto gload = [&](int st, v4i* a, v4i* b) {
+        const int seg = st >= nkc ? 1 : 0;
+        const int kc = st - seg * nkc;
+        const int64_t oa = seg * seg_a + (int64_t)kc * KT;
+        const int64_t ob = seg * seg_b + (int64_t)kc * KT;
 #pragma unroll
-        for (int i = 0; i < ACH; ++i) ra[i] = *reinterpret_cast<const v4i*>(aptr[i] + oa);
+        for (int i = 0; i < ACH; ++i) a[i] = *reinterpret_cast<const v4i*>(aptr[i] + oa);
 #pragma unroll
-        for (int i = 0; i < BCH; ++i) rb[i] = *reinterpret_cast<const v4i*>(bptr[i] + ob);
+        for (int i = 0; i < BCH; ++i) b[i] = *reinterpret_cast<const v4i*>(bptr[i] + ob);
     };
-    auto sstore = [&](int buf) {
+    auto sstore = [&](int buf, const v4i* a, const v4i* b) {
         char* base = lds + buf * STAGE;
 #pragma unroll
-        for (int i = 0; i < ACH; ++i) *reinterpret_cast<v4i*>(base + alds[i]) = ra[i];
+        for (int i = 0; i < ACH; ++i) *reinterpret_cast<v4i*>(base + alds[i]) = a[i];
 #pragma unroll
-        for (int i = 0; i < BCH; ++i) *reinterpret_cast<v4i*>(base + blds[i]) = rb[i];
+        for (int i = 0; i < BCH; ++i) *reinterpret_cast<v4i*>(base + blds[i]) = b[i];
     };
 
     v16i acc[NROLE][NACC][FM][FN];
@@ -150,31 +141,24 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
 #pragma unroll
                     for (int v = 0; v < 16; ++v) acc[r][a][m][n][v] = 0;
 
-    if (nst > 0) {
-        gload(0);
-        sstore(0);
-    }
-    __syncthreads();
     const int lrow = lane & 31, lseg = lane >> 5;
-    for (int st = 0; st < nst; ++st) {
-        const int buf = st & 1;
-        if (st + 1 < nst) gload(st + 1);
+    auto compute = [&](int buf) {
         const char* base = lds + buf * STAGE;
 #pragma unroll
-        for (int ks = 0; ks < KT8 / 32; ++ks) {
+        for (int ks = 0; ks < KT / 32; ++ks) {
             v4i af[NA][FM], bf[NB][FN];
 #pragma unroll
             for (int a = 0; a < NA; ++a)
 #pragma unroll
                 for (int m = 0; m < FM; ++m)
                     af[a][m] = *reinterpret_cast<const v4i*>(
-                        base + a * TILE + swz(wm0 + m * 32 + lrow, ks * 2 + lseg));
+                        base + a * TILE + swz<KT>(wm0 + m * 32 + lrow, ks * 2 + lseg));
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
                 for (int n = 0; n < FN; ++n)
                     bf[b][n] = *reinterpret_cast<const v4i*>(
-                        base + (NA + b) * TILE + swz(wn0 + n * 32 + lrow, ks * 2 + lseg));
+                        base + (NA + b) * TILE + swz<KT>(wn0 + n * 32 + lrow, ks * 2 + lseg));
             if (NL == 1) {
 #pragma unroll
                 for (int r = 0; r < NROLE; ++r)
@@ -185,8 +169,8 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
                             acc[r][0][m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
                                 af[r][m], bf[0][n], acc[r][0][m][n], 0, 0, 0);
             } else {
-                // limb products: (hi,hi) -> 0, (hi,lo) and (lo,hi) -> 1, (lo,lo) -> 2;
-                // ordered so that consecutive MFMAs do not share an accumulator
+                // limb products (hi,hi) -> 0, (hi,lo) and (lo,hi) -> 1, (lo,lo) -> 2, ordered
+                // so that consecutive MFMAs do not share an accumulator
 #pragma unroll
                 for (int pr = 0; pr < 4; ++pr) {
                     const int la = pr >> 1, lb = pr & 1;
@@ -202,51 +186,130 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
                 }
             }
         }
-        if (st + 1 < nst) sstore(buf ^ 1);
-        __syncthreads();
+    };
+
+    // ---- pipeline: PF k-tiles in flight in registers, two LDS buffers
+#pragma unroll
+    for (int u = 0; u < PF; ++u)
+        if (u < nst) gload(u, ra[u], rb[u]);
+    if (nst > 0) sstore(0, ra[0], rb[0]);
+    __syncthreads();
+    for (int st0 = 0; st0 < nst; st0 += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int st = st0 + u;
+            if (st < nst) {
+                // register slot u held stage st (already in LDS): refill it with stage st + PF
+                if (st + PF < nst) gload(st + PF, ra[u], rb[u]);
+                compute(st & 1);
+                if (st + 1 < nst) sstore((st + 1) & 1, ra[(u + 1) % PF], rb[(u + 1) % PF]);
+                __syncthreads();
+            }
+        }
     }
 
-    // ---- epilogue: exact recombination, reduction mod p, store
+    // ---- epilogue: exact recombination, reduction mod p, store.  The output format is
+    // switched on once, outside the fully unrolled fragment loops.
+    // Output layout of the 32x32 MFMA: lane -> column (lane & 31), register v -> row
+    // 8 (v / 4) + 4 (lane / 32) + v % 4 of the fragment.
     const int p = fp.p;
-    const double inv_p = fp.inv_p;
+    const float inv_pf = (float)fp.inv_p;
+    const int i0 = row0 + wm0 + 4 * (lane >> 5), j0 = col0 + wn0 + (lane & 31);
+    const bool syrk = T.syrk != 0;
+    const int64_t ldc = T.c.ld;
+    auto epilogue = [&](auto tag) {
+        using OT = decltype(tag);
 #pragma unroll
-    for (int r = 0; r < NROLE; ++r) {
-        char* cbase = (r == 0) ? bases.p[T.c.buf] + T.c.off : bases.p[T.c.buf2] + T.c.off2;
+        for (int r = 0; r < NROLE; ++r) {
+            OT* cp = reinterpret_cast<OT*>(r == 0 ? bases.p[T.c.buf] + T.c.off
+                                                  : bases.p[T.c.buf2] + T.c.off2);
 #pragma unroll
-        for (int m = 0; m < FM; ++m)
+            for (int m = 0; m < FM; ++m)
 #pragma unroll
-            for (int n = 0; n < FN; ++n)
+                for (int n = 0; n < FN; ++n)
 #pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    const int i = row0 + wm0 + m * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                    const int j = col0 + wn0 + n * 32 + (lane & 31);
-                    if (i < T.M && j < T.N && (!T.syrk || i >= j)) {
-                        double val;
-                        if (NL == 1) val = (double)acc[r][0][m][n][v];
-                        else
-                            val = 65536.0 * (double)acc[r][0][m][n][v] +
-                                  256.0 * (double)acc[r][1][m][n][v] + (double)acc[r][2][m][n][v];
-                        store_res(cbase, T.c.dt, (int64_t)i * T.c.ld + j, mod_canon(val, p, inv_p));
+                    for (int v = 0; v < 16; ++v) {
+                        int32_t res;
+                        if (NL == 1) {
+                            res = mod_i32(acc[r][0][m][n][v], p, inv_pf);
+                        } else {
+                            const double val = 65536.0 * (double)acc[r][0][m][n][v] +
+                                               256.0 * (double)acc[r][NACC - 2][m][n][v] +
+                                               (double)acc[r][NACC - 1][m][n][v];
+                            res = mod_canon(val, p, fp.inv_p);
+                        }
+                        const int i = i0 + m * 32 + 8 * (v >> 2) + (v & 3);
+                        const int j = j0 + n * 32;
+                        if (i < M && j < N && (!syrk || i >= j)) cp[(int64_t)i * ldc + j] = (OT)res;
+                        // keep the scheduler from hoisting the reads of every accumulator
+                        if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
                     }
-                }
+        }
+    };
+    switch (T.c.dt) {
+    case DT_U8: epilogue(uint8_t{}); break;
+    case DT_U16: epilogue(uint16_t{}); break;
+    case DT_I32: epilogue(int32_t{}); break;
+    case DT_I64: epilogue(int64_t{}); break;
+    case DT_F64: epilogue(double{}); break;
+    default: break;
     }
 }
 
-// ---- configurations --------------------------------------------------------
-// (limbs, complex) -> tile edge BT and wave grid; accumulator registers per lane
-// are NROLE * NACC * (BT/WGM/32) * (BT/WGN/32) * 16.
-#define CFG_R1 1, 0, 256, 2, 4   // 128 acc regs, 8 waves
-#define CFG_R2 2, 0, 128, 2, 2   // 192 acc regs, 4 waves
-#define CFG_C1 1, 1, 128, 2, 2   // 128 acc regs, 4 waves
-#define CFG_C2 2, 1, 128, 2, 4   // 192 acc regs, 8 waves
+// ---- configurations ---------------------------------------------------------
+// id -> (limbs, complex, tile edge, wave grid, k-tile bytes, prefetch depth).
+// Accumulator registers per lane: NROLE * NACC * (BT/WGM/32) * (BT/WGN/32) * 16.
+struct CfgInfo {
+    int nl, cplx, bt, kt, nthreads, lds;
+};
 
-template <int NL, int CPLX, int BT, int WGM, int WGN>
-static int launch_cfg(const GemmTask* d_tasks, int ntasks, int total_tiles, const Bases& b,
+#define FFA_I8_CONFIGS(X)                 \
+    X(0, 1, 0, 256, 2, 2, 128, 2)         \
+    X(1, 1, 0, 256, 2, 4, 64, 2)          \
+    X(2, 1, 0, 128, 2, 2, 128, 2)         \
+    X(3, 2, 0, 128, 2, 2, 128, 2)         \
+    X(4, 1, 1, 128, 2, 2, 128, 2)         \
+    X(5, 2, 1, 128, 2, 4, 64, 1)          \
+    X(6, 2, 0, 128, 2, 2, 64, 2)          \
+    X(7, 1, 0, 256, 2, 2, 64, 2)          \
+    X(8, 2, 1, 64, 2, 2, 128, 2)          \
+    X(9, 2, 0, 128, 2, 2, 128, 1)         \
+    X(10, 1, 0, 256, 2, 4, 128, 2)        \
+    X(11, 1, 0, 256, 2, 4, 64, 3)         \
+    X(12, 1, 0, 256, 4, 2, 64, 2)
+
+static CfgInfo cfg_info(int id)
+{
+#define FFA_INFO(ID, NL, CP, BT, WM, WN, KT, PF) \
+    if (id == ID) return CfgInfo{NL, CP, BT, KT, WM * WN * 64, 2 * ((CP ? 2 : 1) * NL + NL) * BT * KT};
+    FFA_I8_CONFIGS(FFA_INFO)
+#undef FFA_INFO
+    return CfgInfo{0, 0, 0, 0, 0, 0};
+}
+
+int gemm_i8_config_tile(int cfg) { return cfg_info(cfg).bt; }
+int gemm_i8_config_ktile(int cfg) { return cfg_info(cfg).kt; }
+
+int gemm_i8_config_valid(int cfg, int nl, int cplx)
+{
+    const CfgInfo ci = cfg_info(cfg);
+    return ci.bt > 0 && ci.nl == nl && ci.cplx == cplx;
+}
+
+int gemm_i8_default_config(int nl, int cplx, int64_t max_dim)
+{
+    if (cplx) return nl == 1 ? 4 : 8;
+    if (nl == 2) return 9;
+    return max_dim >= 2048 ? 1 : 2;
+}
+
+template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF>
+static int launch_cfg(const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks, const Bases& b,
                       const FieldParams& fp, hipStream_t s)
 {
     constexpr int NA = (CPLX ? 2 : 1) * NL, NB = NL;
-    constexpr int lds_bytes = 2 * (NA + NB) * BT * KT8;
-    auto kern = gemm_i8<NL, CPLX, BT, WGM, WGN>;
+    constexpr int lds_bytes = 2 * (NA + NB) * BT * KT;
+    auto kern = gemm_i8<NL, CPLX, BT, WGM, WGN, KT, PF>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -254,26 +317,21 @@ static int launch_cfg(const GemmTask* d_tasks, int ntasks, int total_tiles, cons
         if (e != hipSuccess) return (int)e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(kern, dim3(total_tiles), dim3(WGM * WGN * 64), lds_bytes, s, b, d_tasks,
-                       ntasks, fp);
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(WGM * WGN * 64), lds_bytes, s, b, d_tasks,
+                       d_sched, fp);
     return (int)hipGetLastError();
 }
 
-int gemm_tile_i8(int nl, int cplx)
-{
-    if (nl == 1 && !cplx) return 256;
-    return 128;
-}
-
-int launch_gemm_i8(const GemmTask* d_tasks, int ntasks, int total_tiles, const Bases& b,
-                   const FieldParams& fp, void* stream)
+int launch_gemm_i8(int cfg, const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks,
+                   const Bases& b, const FieldParams& fp, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
-    if (ntasks <= 0 || total_tiles <= 0) return 0;
-    if (fp.nl == 1 && !fp.cplx) return launch_cfg<CFG_R1>(d_tasks, ntasks, total_tiles, b, fp, s);
-    if (fp.nl == 2 && !fp.cplx) return launch_cfg<CFG_R2>(d_tasks, ntasks, total_tiles, b, fp, s);
-    if (fp.nl == 1) return launch_cfg<CFG_C1>(d_tasks, ntasks, total_tiles, b, fp, s);
-    return launch_cfg<CFG_C2>(d_tasks, ntasks, total_tiles, b, fp, s);
+    if (nblocks <= 0) return 0;
+#define FFA_LAUNCH(ID, NL, CP, BT, WM, WN, KT, PF) \
+    if (cfg == ID) return launch_cfg<NL, CP, BT, WM, WN, KT, PF>(d_tasks, d_sched, nblocks, b, fp, s);
+    FFA_I8_CONFIGS(FFA_LAUNCH)
+#undef FFA_LAUNCH
+    return (int)hipErrorInvalidValue;
 }
 
 }  // namespace ffa

@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 
 #include "field.h"
 
@@ -216,10 +217,63 @@ int check_bound(const Plan& pl)
     }
     if (pl.nl == 1) {
         const double m = (double)pl.max_abs;
-        return terms * m * m < 2147483648.0 ? FFA_OK : FFA_EBOUND;
+        // the int32 epilogue reduction needs a little headroom below 2^31
+        return terms * m * m < 2147483648.0 - 131072.0 ? FFA_OK : FFA_EBOUND;
     }
     // two limbs: the middle accumulator sums hi*lo + lo*hi, each at most 128^2
     return 2.0 * terms * 16384.0 < 2147483648.0 ? FFA_OK : FFA_EBOUND;
+}
+
+// Tile schedule of the grouped product launch.  Tiles of each task are cut
+// into blocks of GR x GC tiles (rows x columns; only the lower triangle for
+// base cases) so that the workgroups running together on one XCD share few
+// operand panels in that XCD's L2.  Blocks are dealt, costliest first, to the
+// XCD with the least work so far (workgroup b runs on XCD b mod 8), and the
+// schedule interleaves the eight per-XCD lists; shorter lists are padded with
+// idle entries.
+void build_schedule(Plan& pl)
+{
+    constexpr int GR = 4, GC = 8, NX = 8;
+    struct Group {
+        double cost;
+        std::vector<TileEnt> tiles;
+    };
+    std::vector<Group> groups;
+    int tiles = 0;
+    for (size_t t = 0; t < pl.gemm.size(); ++t) {
+        const GemmTask& g = pl.gemm[t];
+        const double kcost = (double)g.K * (pl.cplx ? 2 : 1) + 64.0;
+        for (int bi = 0; bi < g.tiles_m; bi += GR) {
+            const int bj_end = g.syrk ? std::min(bi + GR, g.tiles_n) : g.tiles_n;
+            for (int bj = 0; bj < bj_end; bj += GC) {
+                Group gr;
+                for (int ti = bi; ti < std::min(bi + GR, g.tiles_m); ++ti)
+                    for (int tj = bj; tj < std::min(bj + GC, g.tiles_n); ++tj)
+                        if (!g.syrk || tj <= ti) gr.tiles.push_back({(int32_t)t, ti | (tj << 16)});
+                if (gr.tiles.empty()) continue;
+                gr.cost = kcost * (double)gr.tiles.size();
+                tiles += (int)gr.tiles.size();
+                groups.push_back(std::move(gr));
+            }
+        }
+    }
+    pl.total_tiles = tiles;
+    std::stable_sort(groups.begin(), groups.end(),
+                     [](const Group& a, const Group& b) { return a.cost > b.cost; });
+    std::vector<std::vector<TileEnt>> bins(NX);
+    double load[NX] = {0};
+    for (const Group& gr : groups) {
+        int x = 0;
+        for (int i = 1; i < NX; ++i)
+            if (load[i] < load[x]) x = i;
+        load[x] += gr.cost;
+        bins[x].insert(bins[x].end(), gr.tiles.begin(), gr.tiles.end());
+    }
+    size_t len = 0;
+    for (const auto& b : bins) len = std::max(len, b.size());
+    pl.sched.assign(len * NX, TileEnt{-1, 0});
+    for (int x = 0; x < NX; ++x)
+        for (size_t i = 0; i < bins[x].size(); ++i) pl.sched[i * NX + x] = bins[x][i];
 }
 
 void size_grids(Plan& pl)
@@ -234,21 +288,13 @@ void size_grids(Plan& pl)
         }
         for (const auto& t : pl.post[l]) pl.post_max_h[l] = std::max(pl.post_max_h[l], t.h);
     }
-    // longest tiles first: sort general products and base cases by K, descending
-    std::stable_sort(pl.gemm.begin(), pl.gemm.end(),
-                     [](const GemmTask& a, const GemmTask& b) { return a.K > b.K; });
-    int tiles = 0;
-    for (auto& g : pl.gemm) {
-        g.tile_begin = tiles;
-        tiles += g.syrk ? g.tiles_m * (g.tiles_m + 1) / 2 : g.tiles_m * g.tiles_n;
-    }
-    pl.total_tiles = tiles;
+    build_schedule(pl);
 }
 
 // Adds one problem's conditioning and recursion tree to the plan.
 int add_problem(Plan& pl, Builder& B, const Problem& pr, int levels, bool allow_direct)
 {
-    const int ktile = pl.carrier == CAR_F64 ? KTILE_F64 : KTILE_I8;
+    const int ktile = pl.ktile;
     const int64_t npad = round_up(pr.n, (int64_t)1 << levels);
     const int64_t kpad = round_up(pr.k, (int64_t)ktile << levels);
     if (npad >= (1ll << 31) || kpad >= (1ll << 31)) return FFA_EINVAL;
@@ -305,6 +351,25 @@ int add_problem(Plan& pl, Builder& B, const Problem& pr, int levels, bool allow_
     return FFA_OK;
 }
 
+// Product kernel configuration: built-in choice by size, or FFA_I8_CFG (tuning).
+void choose_kernel(Plan& pl, int64_t max_dim)
+{
+    if (pl.carrier == CAR_F64) {
+        pl.gemm_cfg = 0;
+        pl.tile = gemm_tile_f64();
+        pl.ktile = KTILE_F64;
+        return;
+    }
+    int cfg = gemm_i8_default_config(pl.nl, pl.cplx, max_dim);
+    if (const char* e = std::getenv("FFA_I8_CFG")) {
+        const int c = std::atoi(e);
+        if (gemm_i8_config_valid(c, pl.nl, pl.cplx)) cfg = c;
+    }
+    pl.gemm_cfg = cfg;
+    pl.tile = gemm_i8_config_tile(cfg);
+    pl.ktile = gemm_i8_config_ktile(cfg);
+}
+
 Builder make_builder(Plan& pl)
 {
     Builder B{pl};
@@ -312,7 +377,7 @@ Builder make_builder(Plan& pl)
     B.npo = pl.cplx ? 3 : 1;
     B.rdt = pl.fp.p < 256 ? DT_U8 : (pl.fp.p < 65536 ? DT_U16 : DT_I32);
     B.rsize = dtype_size(B.rdt);
-    B.bt = pl.carrier == CAR_F64 ? gemm_tile_f64() : gemm_tile_i8(pl.nl, pl.cplx);
+    B.bt = pl.tile;
     return B;
 }
 
@@ -337,6 +402,7 @@ Plan make_plan(const Problem& pr)
     pl.levels = choose_levels(pr.n, pr.k, o, pl.carrier, pl.nl, pl.cplx);
     pl.pre.assign(pl.levels, {});
     pl.post.assign(pl.levels, {});
+    choose_kernel(pl, pr.n >> pl.levels);
     Builder B = make_builder(pl);
     int st = add_problem(pl, B, pr, pl.levels, true);
     if (st) { pl.status = st; return pl; }
@@ -372,6 +438,9 @@ Plan make_batch_plan(const std::vector<Problem>& prs)
     pl.levels = maxL;
     pl.pre.assign(maxL, {});
     pl.post.assign(maxL, {});
+    int64_t maxn = 0;
+    for (const auto& q : prs) maxn = std::max(maxn, q.n);
+    choose_kernel(pl, maxn);
     Builder B = make_builder(pl);
     int64_t aoff = 0, coff = 0;
     const int ain = dtype_size(p0.dA), cout = dtype_size(p0.dC);
@@ -420,6 +489,7 @@ std::vector<char> pack_tables(Plan& pl)
         pl.off_post[l] = put(pl.post[l].data(), pl.post[l].size() * sizeof(PostaddTask));
     }
     pl.off_gemm = put(pl.gemm.data(), pl.gemm.size() * sizeof(GemmTask));
+    pl.off_sched = put(pl.sched.data(), pl.sched.size() * sizeof(TileEnt));
     pl.blob_bytes = (int64_t)blob.size();
     return blob;
 }
@@ -438,11 +508,13 @@ std::string describe(const Plan& pl)
              "{\"status\":%d,\"levels\":%d,\"carrier\":\"%s\",\"limbs\":%d,\"complex\":%d,"
              "\"npad\":%lld,\"kpad\":%lld,\"direct\":%d,\"max_abs\":%d,\"max_k\":%lld,"
              "\"ws_bytes\":%lld,\"conditioning\":%zu,\"preadd_tasks\":%s,\"postadd_tasks\":%s,"
-             "\"gemm_tasks\":%zu,\"tiles\":%d,\"macs\":%lld,\"ykind\":%d,\"ya\":%d,\"yb\":%d}",
+             "\"gemm_tasks\":%zu,\"tiles\":%d,\"blocks\":%zu,\"cfg\":%d,\"tile\":%d,"
+             "\"macs\":%lld,\"ykind\":%d,\"ya\":%d,\"yb\":%d}",
              pl.status, pl.levels, pl.carrier == CAR_F64 ? "f64" : "int8", pl.nl, pl.cplx,
              (long long)pl.npad, (long long)pl.kpad, pl.direct ? 1 : 0, pl.max_abs,
              (long long)pl.max_k, (long long)pl.ws_bytes, pl.cond.size(), pre.c_str(), post.c_str(),
-             pl.gemm.size(), pl.total_tiles, (long long)pl.products_macs, pl.fp.ykind, pl.fp.ya,
+             pl.gemm.size(), pl.total_tiles, pl.sched.size(), pl.gemm_cfg, pl.tile,
+             (long long)pl.products_macs, pl.fp.ykind, pl.fp.ya,
              pl.fp.yb);
     return buf;
 }

@@ -42,6 +42,10 @@ struct Plan {
     std::vector<int> pre_max_h, pre_max_w;
     std::vector<GemmTask> gemm;
     int total_tiles = 0;
+    int gemm_cfg = 0;                  // INT8 product kernel configuration
+    int tile = 0;                      // product tile edge
+    int ktile = 0;                     // product k-tile (carrier elements); K is padded to it
+    std::vector<TileEnt> sched;         // XCD-balanced tile schedule, one entry per workgroup
     int64_t ws_bytes = 0;
     int64_t products_macs = 0;         // multiply-accumulates of the products (per limb product)
     std::vector<int64_t> a_off, c_off; // packed batch layout (elements)
@@ -49,7 +53,7 @@ struct Plan {
     // device copy of the tables (filled by the API layer)
     void* d_blob = nullptr;
     int64_t blob_bytes = 0;
-    int64_t off_cond = 0, off_gemm = 0;
+    int64_t off_cond = 0, off_gemm = 0, off_sched = 0;
     std::vector<int64_t> off_pre, off_post;
 };
 

@@ -97,13 +97,13 @@ def test_plan_errors():
     assert ffa.plan_describe(10, 10, 65519, hermitian=True, dA=ffa.F64, dC=ffa.F64)[0] == 0
     assert ffa.plan_describe(10, 10, 65519, hermitian=True, dA=ffa.F64, dC=ffa.F64,
                              opts=ffa.make_opts(carrier=ffa.CARRIER_F64))[0] == ffa.EUNSUPPORTED
-    # exact-accumulation bounds: int8 single limb p=251: k * 125^2 < 2^31
-    assert ffa.plan_describe(4, 137408, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
+    # exact-accumulation bounds (k a multiple of the k-tile): one limb p=251: k 125^2 < 2^31 - 2^17
+    assert ffa.plan_describe(4, 137344, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))[0] == 0
     assert ffa.plan_describe(4, 137472, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))[0] == ffa.EBOUND
     # two limbs: 2 * k * 128^2 < 2^31
-    assert ffa.plan_describe(4, 65472, 65521, dA=ffa.U16, dC=ffa.U16,
+    assert ffa.plan_describe(4, 65408, 65521, dA=ffa.U16, dC=ffa.U16,
                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))[0] == 0
     assert ffa.plan_describe(4, 65536, 65521, dA=ffa.U16, dC=ffa.U16,
                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))[0] == ffa.EBOUND
