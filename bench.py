@@ -45,7 +45,55 @@ def parse():
     ap.add_argument("--no-classical", action="store_true", help="skip the classical comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 256 MiB buffer three times (scale for FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device copy of known size, profiled to scale the HBM byte counters."""
+    import torch
+    x = torch.empty(256 * 1024 * 1024, dtype=torch.uint8, device="cuda")
+    x.fill_(3)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": 256 * 1024 * 1024, "copies": 3}))
+
+
+PROFILE_FILE = os.path.join(ROOT, "profiles", "gemm_i8_syrk_p251_n16384.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2101_01025_amd", "csrc", f)
+                  for f in ("gemm_i8.hip", "device_common.h", "ffa_internal.h")]
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, levels):
+    """HBM bytes per product launch from the committed rocprofv3 counters, or None
+    when the kernel sources changed since they were taken (or no record matches)."""
+    import re
+    try:
+        text = open(PROFILE_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("kernel_sources_sha256_16") != kernel_hash():
+        return None
+    if rec.get("workload") != workload or rec.get("levels") != levels:
+        return None
+    return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
 
 
 def make_input(w, torch):
@@ -67,33 +115,55 @@ def make_input(w, torch):
     return torch.from_numpy(a).to("cuda"), None
 
 
-def run_steps(ffa, torch, w, A, Ai, C, Ci, opts, steps, warmup):
-    def one():
+def timed_steps(ffa, torch, w, A, Ai, C, Ci, plans, steps, warmup, blocks=5):
+    """Times `steps` calls of each plan (recursive, then classical if given).
+
+    The plans run in alternating blocks so that clock and thermal drift during
+    the run affects both alike.  Phase durations come from HIP events the
+    library records around each phase on the same stream.
+    Returns per plan: (ms per step, {phase: ms per call}).
+    """
+    def one(opts):
         if Ai is None:
             ffa.syrk_modp(A, w["p"], C=C, opts=opts)
         else:
             ffa.herk_modp2(A, Ai, w["p"], C_re=C, C_im=Ci, opts=opts)
-    for _ in range(warmup):
-        one()
+    for opts in plans:
+        for _ in range(warmup):
+            one(opts)
     torch.cuda.synchronize()
-    ffa.profile_reset(0)
-    ffa.profile_enable(0, True)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(steps):
-        one()
-    stop.record()
-    torch.cuda.synchronize()
-    ffa.profile_enable(0, False)
-    total_ms = start.elapsed_time(stop)
-    phases = {}
-    for ph, name in ((ffa.PHASE_COND, "conditioning"), (ffa.PHASE_PRE, "preadd"),
-                     (ffa.PHASE_PRODUCTS, "products"), (ffa.PHASE_POST, "postadd")):
-        ms, calls = ffa.profile_read(0, ph)
-        phases[name] = round(ms / calls, 4) if calls else 0.0
-    return total_ms / steps, phases
+    total = [0.0] * len(plans)
+    phase_ms = [dict() for _ in plans]
+    phase_calls = [dict() for _ in plans]
+    names = ((ffa.PHASE_COND, "conditioning"), (ffa.PHASE_PRE, "preadd"),
+             (ffa.PHASE_PRODUCTS, "products"), (ffa.PHASE_POST, "postadd"))
+    per_block = [steps // blocks + (1 if b < steps % blocks else 0) for b in range(blocks)]
+    for nb in per_block:
+        if nb == 0:
+            continue
+        for i, opts in enumerate(plans):
+            ffa.profile_reset(0)
+            ffa.profile_enable(0, True)
+            start = torch.cuda.Event(enable_timing=True)
+            stop = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            start.record()
+            for _ in range(nb):
+                one(opts)
+            stop.record()
+            torch.cuda.synchronize()
+            ffa.profile_enable(0, False)
+            total[i] += start.elapsed_time(stop)
+            for ph, name in names:
+                ms, calls = ffa.profile_read(0, ph)
+                phase_ms[i][name] = phase_ms[i].get(name, 0.0) + ms
+                phase_calls[i][name] = phase_calls[i].get(name, 0) + calls
+    out = []
+    for i in range(len(plans)):
+        ph = {name: round(phase_ms[i][name] / phase_calls[i][name], 4) if phase_calls[i][name] else 0.0
+              for _, name in names}
+        out.append((total[i] / steps, ph))
+    return out
 
 
 def cpu_baseline(w, seconds):
@@ -129,6 +199,9 @@ def cpu_baseline(w, seconds):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not "
                                    "part of this build (use --gpus 1)"}))
@@ -150,7 +223,9 @@ def main():
     dA_code = ffa._dtype_code(A)
     _, plan = ffa.plan_describe(n, k, p, hermitian=herm, dA=dA_code, dC=ffa._dtype_code(C, True),
                                 opts=opts)
-    ms, phases = run_steps(ffa, torch, w, A, Ai, C, Ci, opts, args.steps, args.warmup)
+    plans = [opts] if args.no_classical else [opts, ffa.make_opts(algo=ffa.ALGO_CLASSICAL)]
+    res = timed_steps(ffa, torch, w, A, Ai, C, Ci, plans, args.steps, args.warmup)
+    ms, phases = res[0]
     value = n * n * k / (ms * 1e-3)
 
     out = {
@@ -180,7 +255,8 @@ def main():
         achieved = ops / (prod_ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "mfma", "kernel": "gemm_i8 (grouped products)",
                            "achieved": achieved, "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
-                           "frac": achieved / PEAK_INT8_TOPS, "traffic": None,
+                           "frac": achieved / PEAK_INT8_TOPS,
+                           "traffic": measured_traffic(args.workload, plan["levels"]),
                            "ops_per_launch": ops}
     else:
         achieved = ops / (prod_ms * 1e-3) / 1e12
@@ -189,8 +265,7 @@ def main():
                            "frac": achieved / PEAK_F64_TFLOPS, "traffic": None,
                            "ops_per_launch": ops}
     if not args.no_classical:
-        copts = ffa.make_opts(algo=ffa.ALGO_CLASSICAL)
-        cms, cph = run_steps(ffa, torch, w, A, Ai, C, Ci, copts, args.steps, args.warmup)
+        cms, cph = res[1]
         out["classical_gpu"] = {"value": n * n * k / (cms * 1e-3), "unit": "n^2k/s",
                                 "ms_per_step": cms, "products_ms": cph["products"]}
         out["speedup_vs_classical"] = cms / ms

@@ -170,7 +170,7 @@ int run_plan(ffa_ctx* c, Plan& pl, Bases b)
         if (pl.check_inputs && (e = launch_zero_flag(c->d_err, s))) return dev_fail(c, e);
         hipEvent_t ev = phase_begin(c);
         e = launch_condition((const CondTask*)(blob + pl.off_cond), (int)pl.cond.size(),
-                             pl.cond_max_blocks, b, pl.fp, pl.carrier, c->d_err, s);
+                             pl.cond_max_blocks, pl.cond[0].dt_in, b, pl.fp, pl.carrier, c->d_err, s);
         if (e) return dev_fail(c, e);
         phase_end(c, ev, 0);
         if (pl.check_inputs) {

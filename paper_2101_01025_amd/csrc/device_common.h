@@ -30,6 +30,32 @@ __device__ __forceinline__ int32_t mod_centred_small(int32_t x, int32_t p, float
     return x - q * p;
 }
 
+// Canonical residue of an unsigned 32-bit integer for odd p < 2^16, with two
+// fp32 quotient estimates (the first is within a few hundred of x / p, the
+// second exact to within one) and a final correction.
+__device__ __forceinline__ int32_t mod_u32(uint32_t x, int32_t p, float inv_p)
+{
+    int32_t q = (int32_t)((float)x * inv_p);
+    int32_t r = (int32_t)(x - (uint32_t)q * (uint32_t)p);
+    q = (int32_t)floorf((float)r * inv_p);
+    r -= q * p;
+    r += (r < 0) ? p : 0;
+    r -= (r >= p) ? p : 0;
+    return r;
+}
+
+// a * b mod p for canonical a, b (p < 2^16: the product fits in 32 bits).
+__device__ __forceinline__ int32_t mul_mod(int32_t a, int32_t b, int32_t p, float inv_p)
+{
+    return mod_u32((uint32_t)a * (uint32_t)b, p, inv_p);
+}
+
+__device__ __forceinline__ int32_t sub_mod(int32_t a, int32_t b, int32_t p)
+{
+    const int32_t d = a - b;
+    return d < 0 ? d + p : d;
+}
+
 // a + b mod p for canonical a, b.
 __device__ __forceinline__ int32_t add_mod(int32_t a, int32_t b, int32_t p)
 {

@@ -8,8 +8,6 @@
 // Every value is reduced mod p where it is produced.
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
-
 #include "device_common.h"
 #include "ffa_internal.h"
 
@@ -46,8 +44,43 @@ __device__ __forceinline__ bool read_input(const char* base, int dt, int64_t idx
     return false;
 }
 
-// One thread converts VEC consecutive columns of one row.
-template <int NL, int CPLX>
+// Loads 16 consecutive input elements of a row as canonical residues; vector
+// loads when the 16 are inside the row and aligned.  Returns false if an entry
+// is outside its residue range.
+template <typename IT>
+__device__ __forceinline__ bool load_input16(const char* base, int64_t idx, int valid, int32_t p,
+                                             int32_t half, bool centred, int32_t* v)
+{
+    const IT* src = reinterpret_cast<const IT*>(base) + idx;
+    alignas(16) IT raw[16];
+    if (valid >= 16 && ((uintptr_t)src & 15) == 0) {
+#pragma unroll
+        for (int q = 0; q < (int)(16 * sizeof(IT) / 16); ++q)
+            reinterpret_cast<int4*>(raw)[q] = reinterpret_cast<const int4*>(src)[q];
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) raw[e] = e < valid ? src[e] : (IT)0;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        if (centred) {
+            const int32_t x = (int32_t)raw[e];
+            ok &= (x >= -half) & (x <= half);
+            v[e] = x < 0 ? x + p : x;
+        } else {
+            const double xd = (double)raw[e];
+            const int32_t x = (int32_t)raw[e];
+            ok &= (xd >= 0.0) & (xd < (double)p) & ((double)x == xd);
+            v[e] = x;
+        }
+    }
+    return ok;
+}
+
+// One thread converts 16 consecutive columns of one row into every carrier
+// sub-plane (limbs of re, and of im and -re for F_p[i]).
+template <typename IT, int NL, int CPLX>
 __global__ void __launch_bounds__(256) condition_i8(const CondTask* tasks, Bases b, FieldParams fp,
                                                     int32_t* err)
 {
@@ -58,19 +91,24 @@ __global__ void __launch_bounds__(256) condition_i8(const CondTask* tasks, Bases
     if (idx >= (int64_t)t.npad * gpr) return;
     const int r = (int)(idx / gpr), c0 = (int)(idx % gpr) * VEC;
     const int p = fp.p;
+    const bool centred = t.dt_in == DT_I8C;
     constexpr int NPL = CPLX ? 3 : 1;
+    int32_t vr[16], vi[16];
+    bool ok = true;
+    const int valid = (r < t.n) ? max(0, min(VEC, t.k - c0)) : 0;
+    const int64_t off = (int64_t)r * t.lda + c0;
+    if (valid > 0) {
+        ok &= load_input16<IT>(b.p[t.buf_re] + t.off_re, off, valid, p, fp.half, centred, vr);
+        if (CPLX) ok &= load_input16<IT>(b.p[t.buf_im] + t.off_im, off, valid, p, fp.half, centred, vi);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) vr[e] = vi[e] = 0;
+    }
+    if (!ok) err[0] = 1;
     alignas(16) int8_t out[NPL][NL][VEC];
-    bool bad = false;
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
-        const int c = c0 + e;
-        int32_t vr = 0, vi = 0;
-        if (r < t.n && c < t.k) {
-            const int64_t off = (int64_t)r * t.lda + c;
-            bad |= !read_input(b.p[t.buf_re] + t.off_re, t.dt_in, off, p, fp.half, vr);
-            if (CPLX) bad |= !read_input(b.p[t.buf_im] + t.off_im, t.dt_in, off, p, fp.half, vi);
-        }
-        int32_t vals[3] = {vr, vi, neg_mod(vr, p)};
+        const int32_t vals[3] = {vr[e], CPLX ? vi[e] : 0, neg_mod(vr[e], p)};
 #pragma unroll
         for (int q = 0; q < NPL; ++q) {
             if (NL == 1) {
@@ -83,7 +121,6 @@ __global__ void __launch_bounds__(256) condition_i8(const CondTask* tasks, Bases
             }
         }
     }
-    if (bad) err[0] = 1;
     char* ob = b.p[t.out.buf] + t.out.off + (int64_t)r * t.out.ld + c0;
 #pragma unroll
     for (int q = 0; q < NPL; ++q)
@@ -114,36 +151,24 @@ __global__ void __launch_bounds__(256) condition_f64(const CondTask* tasks, Base
 // pre-additions with the skew-unitary Y
 // ============================================================================
 
-// Value of one element of a carrier plane group (NL limbs).
+// Canonical residue of one element of a carrier plane group (NL limbs).
 template <int NL>
-__device__ __forceinline__ int32_t car_val(const int8_t* hi, const int8_t* lo, int e)
+__device__ __forceinline__ int32_t car_canon(const int8_t* hi, const int8_t* lo, int e, int32_t p)
 {
-    return NL == 1 ? (int32_t)hi[e] : 256 * (int32_t)hi[e] + (int32_t)lo[e];
+    const int32_t r = NL == 1 ? (int32_t)hi[e] : 256 * (int32_t)hi[e] + (int32_t)lo[e];
+    return r < 0 ? r + p : r;
 }
 
-// Reduce an exact integer to the carrier representative of its residue.  One
-// limb (p < 256): every intermediate is below 2^20 and int32 / fp32 arithmetic is
-// exact; two limbs: products reach 2^32 and are formed in fp64 (exact below 2^53).
+// Writes the carrier encoding of a canonical residue.
 template <int NL>
-struct PreArith {
-    typedef typename std::conditional<NL == 1, int32_t, double>::type T;
-};
-
-template <int NL>
-__device__ __forceinline__ int32_t to_rep(typename PreArith<NL>::T v, const FieldParams& fp)
-{
-    if (NL == 1) return mod_centred_small((int32_t)v, fp.p, (float)fp.inv_p);
-    return rep2(mod_canon((double)v, fp.p, fp.inv_p), fp.p);
-}
-
-template <int NL>
-__device__ __forceinline__ void put_rep(int32_t r, int8_t* hi, int8_t* lo, int e)
+__device__ __forceinline__ void put_canon(int32_t c, int32_t p, int32_t half, int8_t* hi, int8_t* lo,
+                                          int e)
 {
     if (NL == 1) {
-        hi[e] = (int8_t)r;
+        hi[e] = (int8_t)(c > half ? c - p : c);
     } else {
         int8_t h, l;
-        split2(r, h, l);
+        split2(rep2(c, p), h, l);
         hi[e] = h;
         lo[e] = l;
     }
@@ -151,7 +176,8 @@ __device__ __forceinline__ void put_rep(int32_t r, int8_t* hi, int8_t* lo, int e
 
 // Each thread handles VEC columns c.. of the left column half of a block and
 // the matching columns c + w/2 of the right half (the block-structured Y mixes
-// exactly these two).
+// exactly these two).  All arithmetic is on canonical residues in 32-bit
+// integers: products of two residues stay below 2^32 for p < 2^16.
 template <int NL, int CPLX, int VEC>
 __global__ void __launch_bounds__(256) preadd_i8(const PreaddTask* tasks, Bases b, FieldParams fp)
 {
@@ -190,71 +216,106 @@ __global__ void __launch_bounds__(256) preadd_i8(const PreaddTask* tasks, Bases 
     }
     alignas(16) vec_t out[4][2][NPO][NL];
     const int32_t p = fp.p;
-    typedef typename PreArith<NL>::T AT;
-    const AT ya = (AT)fp.ya, yb = (AT)fp.yb;
+    const float ip = (float)fp.inv_p;
+    const int32_t ya = fp.ya, yb = fp.yb, nyb = neg_mod(fp.yb, p);
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
-        // x[blk][half][plane]
-        int32_t x[4][2][2];
+        int32_t x[4][2][2];  // [block][half][plane], canonical
 #pragma unroll
         for (int blk = 0; blk < 4; ++blk)
 #pragma unroll
             for (int half = 0; half < 2; ++half)
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
-                    x[blk][half][q] = (q < NPI) ? car_val<NL>(in[blk][half][q][0],
-                                                               in[blk][half][q][NL - 1], e)
-                                                : 0;
+                    x[blk][half][q] =
+                        (q < NPI) ? car_canon<NL>(in[blk][half][q][0], in[blk][half][q][NL - 1], e, p) : 0;
         int32_t s[4][2][2];  // S1..S4, half, plane
-#pragma unroll
-        for (int half = 0; half < 2; ++half) {
-            AT d[2], a21y[2];  // (A21 - A11) Y and A21 Y on this half
+        int32_t d[2][2], g[2][2];  // (A21 - A11) Y and A21 Y, per half and plane
+        if (NL == 1) {
+            // p < 256: every combination below is an exact int32 below 2^17 in magnitude;
+            // one centred reduction per value
+            auto cen = [&](int32_t v) {
+                const int32_t m = mod_centred_small(v, p, ip);
+                return m < 0 ? m + p : m;
+            };
             if (fp.ykind == Y_BLOCKS) {
-                // [X_L | X_R] Y = [a X_L - b X_R | b X_L + a X_R]
-                const AT dl = x[2][0][0] - x[0][0][0], dr = x[2][1][0] - x[0][1][0];
-                const AT el = x[2][0][0], er = x[2][1][0];
-                d[0] = half == 0 ? ya * dl - yb * dr : yb * dl + ya * dr;
-                a21y[0] = half == 0 ? ya * el - yb * er : yb * el + ya * er;
-                d[1] = a21y[1] = 0;
-            } else if (fp.ykind == Y_GAUSS) {
-                // (u + iv)(a + ib) = (au - bv) + i(bu + av)
-                const AT du = x[2][half][0] - x[0][half][0];
-                const AT dv = x[2][half][1] - x[0][half][1];
-                const AT eu = x[2][half][0], ev = x[2][half][1];
-                d[0] = ya * du - yb * dv;
-                d[1] = yb * du + ya * dv;
-                a21y[0] = ya * eu - yb * ev;
-                a21y[1] = yb * eu + ya * ev;
+                const int32_t dl = x[2][0][0] - x[0][0][0], dr = x[2][1][0] - x[0][1][0];
+                const int32_t el = x[2][0][0], er = x[2][1][0];
+                d[0][0] = cen(ya * dl - yb * dr);
+                d[1][0] = cen(yb * dl + ya * dr);
+                g[0][0] = cen(ya * el - yb * er);
+                g[1][0] = cen(yb * el + ya * er);
+                d[0][1] = d[1][1] = g[0][1] = g[1][1] = 0;
             } else {
-                d[0] = ya * (AT)(x[2][half][0] - x[0][half][0]);
-                a21y[0] = ya * (AT)x[2][half][0];
-                d[1] = a21y[1] = 0;
+#pragma unroll
+                for (int half = 0; half < 2; ++half) {
+                    if (fp.ykind == Y_GAUSS) {
+                        const int32_t du = x[2][half][0] - x[0][half][0];
+                        const int32_t dv = x[2][half][1] - x[0][half][1];
+                        const int32_t eu = x[2][half][0], ev = x[2][half][1];
+                        d[half][0] = cen(ya * du - yb * dv);
+                        d[half][1] = cen(yb * du + ya * dv);
+                        g[half][0] = cen(ya * eu - yb * ev);
+                        g[half][1] = cen(yb * eu + ya * ev);
+                    } else {
+                        d[half][0] = cen(ya * (x[2][half][0] - x[0][half][0]));
+                        g[half][0] = cen(ya * x[2][half][0]);
+                        d[half][1] = g[half][1] = 0;
+                    }
+                }
             }
+        } else if (fp.ykind == Y_BLOCKS) {
+            // [X_L | X_R] Y = [a X_L - b X_R | b X_L + a X_R]
+            const int32_t dl = sub_mod(x[2][0][0], x[0][0][0], p), dr = sub_mod(x[2][1][0], x[0][1][0], p);
+            const int32_t el = x[2][0][0], er = x[2][1][0];
+            d[0][0] = add_mod(mul_mod(ya, dl, p, ip), mul_mod(nyb, dr, p, ip), p);
+            d[1][0] = add_mod(mul_mod(yb, dl, p, ip), mul_mod(ya, dr, p, ip), p);
+            g[0][0] = add_mod(mul_mod(ya, el, p, ip), mul_mod(nyb, er, p, ip), p);
+            g[1][0] = add_mod(mul_mod(yb, el, p, ip), mul_mod(ya, er, p, ip), p);
+            d[0][1] = d[1][1] = g[0][1] = g[1][1] = 0;
+        } else {
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                if (fp.ykind == Y_GAUSS) {
+                    // (u + iv)(a + ib) = (au - bv) + i(bu + av)
+                    const int32_t du = sub_mod(x[2][half][0], x[0][half][0], p);
+                    const int32_t dv = sub_mod(x[2][half][1], x[0][half][1], p);
+                    const int32_t eu = x[2][half][0], ev = x[2][half][1];
+                    d[half][0] = add_mod(mul_mod(ya, du, p, ip), mul_mod(nyb, dv, p, ip), p);
+                    d[half][1] = add_mod(mul_mod(yb, du, p, ip), mul_mod(ya, dv, p, ip), p);
+                    g[half][0] = add_mod(mul_mod(ya, eu, p, ip), mul_mod(nyb, ev, p, ip), p);
+                    g[half][1] = add_mod(mul_mod(yb, eu, p, ip), mul_mod(ya, ev, p, ip), p);
+                } else {
+                    d[half][0] = mul_mod(ya, sub_mod(x[2][half][0], x[0][half][0], p), p, ip);
+                    g[half][0] = mul_mod(ya, x[2][half][0], p, ip);
+                    d[half][1] = g[half][1] = 0;
+                }
+            }
+        }
+#pragma unroll
+        for (int half = 0; half < 2; ++half)
 #pragma unroll
             for (int q = 0; q < NPI; ++q) {
-                const int32_t s1 = to_rep<NL>(d[q], fp);
-                const int32_t s2 = to_rep<NL>((AT)x[3][half][q] - a21y[q], fp);
-                const int32_t s3 = to_rep<NL>((AT)(s1 - x[3][half][q]), fp);
-                const int32_t s4 = to_rep<NL>((AT)(s3 + x[1][half][q]), fp);
+                const int32_t s1 = d[half][q];
+                const int32_t s2 = sub_mod(x[3][half][q], g[half][q], p);
+                const int32_t s3 = sub_mod(s1, x[3][half][q], p);
+                const int32_t s4 = add_mod(s3, x[1][half][q], p);
                 s[0][half][q] = s1;
                 s[1][half][q] = s2;
                 s[2][half][q] = s3;
                 s[3][half][q] = s4;
             }
-        }
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
 #pragma unroll
                 for (int q = 0; q < NPI; ++q)
-                    put_rep<NL>(s[j][half][q], out[j][half][q][0], out[j][half][q][NL - 1], e);
-                if (CPLX) {
-                    // the "-re" plane used by the imaginary part of complex products
-                    int32_t v = s[j][half][0];
-                    int32_t nv = NL == 1 ? -v : rep2(neg_mod(v < 0 ? v + p : v, p), p);
-                    put_rep<NL>(nv, out[j][half][NPO - 1][0], out[j][half][NPO - 1][NL - 1], e);
-                }
+                    put_canon<NL>(s[j][half][q], p, fp.half, out[j][half][q][0], out[j][half][q][NL - 1], e);
+                // the "-re" plane used by the imaginary part of complex products
+                if (CPLX)
+                    put_canon<NL>(neg_mod(s[j][half][0], p), p, fp.half, out[j][half][NPO - 1][0],
+                                  out[j][half][NPO - 1][NL - 1], e);
             }
     }
 #pragma unroll
@@ -327,59 +388,70 @@ __global__ void __launch_bounds__(256) preadd_f64(const PreaddTask* tasks, Bases
 // post-additions
 // ============================================================================
 
-template <typename RT>
-__device__ __forceinline__ void load_row16(const char* base, int ld, int row, int col, int32_t* v)
-{
-    const RT* src = reinterpret_cast<const RT*>(base) + (int64_t)row * ld + col;
-    if (sizeof(RT) == 1) {
-        int4 q = *reinterpret_cast<const int4*>(src);
-        const uint8_t* u = reinterpret_cast<const uint8_t*>(&q);
-#pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = u[e];
-    } else if (sizeof(RT) == 2) {
-        int4 q[2];
-        q[0] = reinterpret_cast<const int4*>(src)[0];
-        q[1] = reinterpret_cast<const int4*>(src)[1];
-        const uint16_t* u = reinterpret_cast<const uint16_t*>(q);
-#pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = u[e];
-    } else {
-        int4 q[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) q[i] = reinterpret_cast<const int4*>(src)[i];
-        const int32_t* u = reinterpret_cast<const int32_t*>(q);
-#pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = u[e];
-    }
-}
-
-// Stores 16 consecutive elements of a row: one or more 16-byte vector stores
-// when all are wanted and the address is aligned, element stores otherwise.
-template <typename OT>
-__device__ __forceinline__ void store_row16(char* base, int64_t idx, const int32_t* v, int nwant)
+// Stores V consecutive elements of a row: vector stores when all are wanted
+// and the address is aligned, element stores otherwise.
+template <typename OT, int V>
+__device__ __forceinline__ void store_rowv(char* base, int64_t idx, const int32_t* v, int nwant)
 {
     OT* dst = reinterpret_cast<OT*>(base) + idx;
-    if (nwant >= 16 && ((uintptr_t)dst & 15) == 0) {
-        alignas(16) OT tmp[16];
+    constexpr int BYTES = V * (int)sizeof(OT);
+    if (nwant >= V && ((uintptr_t)dst & (BYTES >= 16 ? 15 : BYTES - 1)) == 0) {
+        alignas(16) OT tmp[V];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) tmp[e] = (OT)v[e];
+        for (int e = 0; e < V; ++e) tmp[e] = (OT)v[e];
+        if (BYTES >= 16) {
 #pragma unroll
-        for (int q = 0; q < (int)(16 * sizeof(OT) / 16); ++q)
-            reinterpret_cast<int4*>(dst)[q] = reinterpret_cast<const int4*>(tmp)[q];
+            for (int q = 0; q < BYTES / 16; ++q)
+                reinterpret_cast<int4*>(dst)[q] = reinterpret_cast<const int4*>(tmp)[q];
+        } else if (BYTES == 8) {
+            *reinterpret_cast<int2*>(dst) = *reinterpret_cast<const int2*>(tmp);
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) dst[e] = tmp[e];
+        }
     } else {
 #pragma unroll
-        for (int e = 0; e < 16; ++e)
+        for (int e = 0; e < V; ++e)
             if (e < nwant) dst[e] = (OT)v[e];
     }
 }
 
+// V consecutive residues of a row, kept packed as loaded (V * sizeof(RT) bytes).
+template <typename RT, int V>
+struct RowV {
+    static constexpr int BYTES = V * (int)sizeof(RT);
+    static constexpr int NQ = BYTES >= 16 ? BYTES / 16 : 1;
+    int4 q[NQ];
+    __device__ __forceinline__ void load(const char* base, int ld, int row, int col)
+    {
+        const RT* src = reinterpret_cast<const RT*>(base) + (int64_t)row * ld + col;
+        if (BYTES >= 16) {
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) q[i] = reinterpret_cast<const int4*>(src)[i];
+        } else {
+            const int2 v = *reinterpret_cast<const int2*>(src);
+            q[0] = int4{v.x, v.y, 0, 0};
+        }
+    }
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) q[i] = int4{0, 0, 0, 0};
+    }
+    __device__ __forceinline__ int32_t operator[](int e) const
+    {
+        return (int32_t)reinterpret_cast<const RT*>(q)[e];
+    }
+};
+
 // Lower tile pairs (R, C), R >= C, of 64 x 64 tiles of the h x h blocks; one
-// workgroup of 256 threads per pair; thread = (row tr, 16-column group).  All
-// loads and stores move 16 consecutive elements of a row.
+// workgroup of 512 threads per pair; thread = (row tr, 8-column group).  All
+// loads and stores move 8 consecutive elements of a row; loaded rows stay
+// packed in registers.
 template <typename RT, typename OT, int CPLX>
-__global__ void __launch_bounds__(256) postadd(const PostaddTask* tasks, Bases b, FieldParams fp)
+__global__ void __launch_bounds__(512) postadd(const PostaddTask* tasks, Bases b, FieldParams fp)
 {
-    constexpr int TS = 64;
+    constexpr int TS = 64, V = 8;
     constexpr int NP = CPLX ? 2 : 1;
     __shared__ int32_t u1s[NP][TS][TS + 1];
     __shared__ int32_t p4s[NP][TS][TS + 1];
@@ -393,7 +465,7 @@ __global__ void __launch_bounds__(256) postadd(const PostaddTask* tasks, Bases b
     const int C = t - R * (R + 1) / 2;
     if (R >= nt) return;
     const int p = fp.p;
-    const int tr = threadIdx.x >> 2, tc = (threadIdx.x & 3) * 16;
+    const int tr = threadIdx.x >> 3, tc = (threadIdx.x & 7) * V;
     const bool diag = (R == C);
 
     const int gi = R * TS + tr;          // row (within the h x h block) of tile (R, C)
@@ -404,33 +476,31 @@ __global__ void __launch_bounds__(256) postadd(const PostaddTask* tasks, Bases b
     auto plane = [&](const ResRef& rr, int q) -> const char* {
         return q == 0 ? b.p[rr.buf] + rr.off : b.p[rr.buf2] + rr.off2;
     };
-    int32_t P1[NP][16], P2[NP][16], P3[NP][16], P4[NP][16], P5[NP][16];
-    int32_t Q3[NP][16], Q4[NP][16];  // tiles (C, R) of P3 and P4
+    RowV<RT, V> P1[NP], P2[NP], P3[NP], P4[NP], P5[NP], Q3[NP], Q4[NP];  // Q: tiles (C, R)
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
-#pragma unroll
-        for (int e = 0; e < 16; ++e)
-            P1[q][e] = P2[q][e] = P3[q][e] = P4[q][e] = P5[q][e] = Q3[q][e] = Q4[q][e] = 0;
         if (gi < h && gj0 < h) {
-            load_row16<RT>(plane(T.p[0], q), T.p[0].ld, gi, gj0, P1[q]);
-            load_row16<RT>(plane(T.p[1], q), T.p[1].ld, gi, gj0, P2[q]);
-            load_row16<RT>(plane(T.p[2], q), T.p[2].ld, gi, gj0, P3[q]);
-            load_row16<RT>(plane(T.p[3], q), T.p[3].ld, gi, gj0, P4[q]);
-            load_row16<RT>(plane(T.p[4], q), T.p[4].ld, gi, gj0, P5[q]);
+            P1[q].load(plane(T.p[0], q), T.p[0].ld, gi, gj0);
+            P2[q].load(plane(T.p[1], q), T.p[1].ld, gi, gj0);
+            P3[q].load(plane(T.p[2], q), T.p[2].ld, gi, gj0);
+            P4[q].load(plane(T.p[3], q), T.p[3].ld, gi, gj0);
+            P5[q].load(plane(T.p[4], q), T.p[4].ld, gi, gj0);
+        } else {
+            P1[q].zero(); P2[q].zero(); P3[q].zero(); P4[q].zero(); P5[q].zero();
         }
         if (!diag && mi < h && mj0 < h) {
-            load_row16<RT>(plane(T.p[2], q), T.p[2].ld, mi, mj0, Q3[q]);
-            load_row16<RT>(plane(T.p[3], q), T.p[3].ld, mi, mj0, Q4[q]);
+            Q3[q].load(plane(T.p[2], q), T.p[2].ld, mi, mj0);
+            Q4[q].load(plane(T.p[3], q), T.p[3].ld, mi, mj0);
+        } else {
+            Q3[q].zero(); Q4[q].zero();
         }
     }
     // U1 = P1 + P5 on tile (R, C); stage U1 and the tile whose transpose is needed
-    int32_t U1[NP][16];
 #pragma unroll
     for (int q = 0; q < NP; ++q)
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            U1[q][e] = add_mod(P1[q][e], P5[q][e], p);
-            u1s[q][tr][tc + e] = U1[q][e];
+        for (int e = 0; e < V; ++e) {
+            u1s[q][tr][tc + e] = add_mod(P1[q][e], P5[q][e], p);
             p4s[q][tr][tc + e] = diag ? P4[q][e] : Q4[q][e];
         }
     __syncthreads();
@@ -441,32 +511,32 @@ __global__ void __launch_bounds__(256) postadd(const PostaddTask* tasks, Bases b
     char* cpl[2] = {b.p[T.c.buf] + T.c.off, b.p[T.c.buf2] + T.c.off2};
     // conjugation of the imaginary plane under phi
     auto conjv = [&](int q, int32_t v) { return q == 1 ? neg_mod(v, p) : v; };
-    // number of the 16 columns starting at col that are inside [0, lim)
-    auto cnt = [](int col, int lim) { return max(0, min(16, lim - col)); };
+    // number of the V columns starting at col that are inside [0, lim)
+    auto cnt = [](int col, int lim) { return max(0, min(V, lim - col)); };
 
     if (gi < h) {
         const int wantC = cnt(gj0, min(h, nv));            // C11 columns
         const int wantH = cnt(h + gj0, nv);                // C21 / C22 columns (offset h)
-        const int lowlen = diag ? min(16, max(0, tr - tc + 1)) : 16;  // entries with col <= row
+        const int lowlen = diag ? min(V, max(0, tr - tc + 1)) : V;  // entries with col <= row
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            int32_t c11[16], c21[16], c22[16];
+            int32_t c11[V], c21[V], c22[V];
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
+            for (int e = 0; e < V; ++e) {
                 const int lc = tc + e;
                 // phi(Low(U1)) above the diagonal of the diagonal tile; P4^phi at (gi, gj)
-                int32_t u1full = U1[q][e];
+                int32_t u1full = add_mod(P1[q][e], P5[q][e], p);
                 if (diag && lc > tr) u1full = conjv(q, u1s[q][lc][tr]);
                 const int32_t p4t = conjv(q, p4s[q][lc][tr]);
                 const int32_t u2 = add_mod(u1full, P4[q][e], p);
-                c21[e] = add_mod(u2, P3[q][e], p);     // U4 = U2 + P3
+                c21[e] = add_mod(u2, P3[q][e], p);        // U4 = U2 + P3
                 c11[e] = add_mod(P1[q][e], P2[q][e], p);  // U3 = P1 + P2
-                c22[e] = add_mod(u2, p4t, p);          // U5 = U2 + phi(P4)
+                c22[e] = add_mod(u2, p4t, p);             // U5 = U2 + phi(P4)
             }
-            if (gi < nv) store_row16<OT>(cpl[q], (int64_t)gi * ldc + gj0, c11, min(wantC, lowlen));
+            if (gi < nv) store_rowv<OT, V>(cpl[q], (int64_t)gi * ldc + gj0, c11, min(wantC, lowlen));
             if (h + gi < nv) {
-                store_row16<OT>(cpl[q], (int64_t)(h + gi) * ldc + gj0, c21, wantC);
-                store_row16<OT>(cpl[q], (int64_t)(h + gi) * ldc + h + gj0, c22, min(wantH, lowlen));
+                store_rowv<OT, V>(cpl[q], (int64_t)(h + gi) * ldc + gj0, c21, wantC);
+                store_rowv<OT, V>(cpl[q], (int64_t)(h + gi) * ldc + h + gj0, c22, min(wantH, lowlen));
             }
         }
     }
@@ -475,13 +545,13 @@ __global__ void __launch_bounds__(256) postadd(const PostaddTask* tasks, Bases b
         const int want = cnt(mj0, min(h, nv));
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            int32_t c21[16];
+            int32_t c21[V];
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
+            for (int e = 0; e < V; ++e) {
                 const int32_t u1 = conjv(q, u1s[q][tc + e][tr]);
                 c21[e] = add_mod(add_mod(u1, Q4[q][e], p), Q3[q][e], p);
             }
-            store_row16<OT>(cpl[q], (int64_t)(h + mi) * ldc + mj0, c21, want);
+            store_rowv<OT, V>(cpl[q], (int64_t)(h + mi) * ldc + mj0, c21, want);
         }
     }
 }
@@ -498,22 +568,39 @@ int launch_zero_flag(int32_t* d_flag, void* stream)
     return (int)hipGetLastError();
 }
 
-int launch_condition(const CondTask* d_tasks, int ntasks, int max_blocks, const Bases& b,
+template <typename IT>
+static void launch_cond_typed(dim3 g, hipStream_t s, const CondTask* d_tasks, const Bases& b,
+                              const FieldParams& fp, int32_t* d_err)
+{
+    if (fp.nl == 1 && !fp.cplx)
+        hipLaunchKernelGGL((condition_i8<IT, 1, 0>), g, dim3(256), 0, s, d_tasks, b, fp, d_err);
+    else if (fp.nl == 2 && !fp.cplx)
+        hipLaunchKernelGGL((condition_i8<IT, 2, 0>), g, dim3(256), 0, s, d_tasks, b, fp, d_err);
+    else if (fp.nl == 1)
+        hipLaunchKernelGGL((condition_i8<IT, 1, 1>), g, dim3(256), 0, s, d_tasks, b, fp, d_err);
+    else
+        hipLaunchKernelGGL((condition_i8<IT, 2, 1>), g, dim3(256), 0, s, d_tasks, b, fp, d_err);
+}
+
+int launch_condition(const CondTask* d_tasks, int ntasks, int max_blocks, int dt_in, const Bases& b,
                      const FieldParams& fp, int carrier, int32_t* d_err, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
     if (ntasks <= 0 || max_blocks <= 0) return 0;
     dim3 g(max_blocks, ntasks);
-    if (carrier == CAR_F64)
+    if (carrier == CAR_F64) {
         hipLaunchKernelGGL(condition_f64, g, dim3(256), 0, s, d_tasks, b, fp, d_err);
-    else if (fp.nl == 1 && !fp.cplx)
-        hipLaunchKernelGGL((condition_i8<1, 0>), g, dim3(256), 0, s, d_tasks, b, fp, d_err);
-    else if (fp.nl == 2 && !fp.cplx)
-        hipLaunchKernelGGL((condition_i8<2, 0>), g, dim3(256), 0, s, d_tasks, b, fp, d_err);
-    else if (fp.nl == 1)
-        hipLaunchKernelGGL((condition_i8<1, 1>), g, dim3(256), 0, s, d_tasks, b, fp, d_err);
-    else
-        hipLaunchKernelGGL((condition_i8<2, 1>), g, dim3(256), 0, s, d_tasks, b, fp, d_err);
+    } else {
+        switch (dt_in) {
+        case DT_I8C: launch_cond_typed<int8_t>(g, s, d_tasks, b, fp, d_err); break;
+        case DT_U8: launch_cond_typed<uint8_t>(g, s, d_tasks, b, fp, d_err); break;
+        case DT_U16: launch_cond_typed<uint16_t>(g, s, d_tasks, b, fp, d_err); break;
+        case DT_I32: launch_cond_typed<int32_t>(g, s, d_tasks, b, fp, d_err); break;
+        case DT_I64: launch_cond_typed<int64_t>(g, s, d_tasks, b, fp, d_err); break;
+        case DT_F64: launch_cond_typed<double>(g, s, d_tasks, b, fp, d_err); break;
+        default: return (int)hipErrorInvalidValue;
+        }
+    }
     return (int)hipGetLastError();
 }
 
@@ -529,8 +616,15 @@ int launch_preadd(const PreaddTask* d_tasks, int ntasks, int h, int w, const Bas
     } else if (!fp.cplx) {
         const int64_t total = (int64_t)h * (w / 2 / 16);
         dim3 g((unsigned)((total + 255) / 256), ntasks);
-        if (fp.nl == 1) hipLaunchKernelGGL((preadd_i8<1, 0, 16>), g, dim3(256), 0, s, d_tasks, b, fp);
-        else hipLaunchKernelGGL((preadd_i8<2, 0, 16>), g, dim3(256), 0, s, d_tasks, b, fp);
+        if (fp.nl == 1) {
+            const int64_t t8 = (int64_t)h * (w / 2 / 8);
+            hipLaunchKernelGGL((preadd_i8<1, 0, 8>), dim3((unsigned)((t8 + 255) / 256), ntasks),
+                               dim3(256), 0, s, d_tasks, b, fp);
+        } else {
+            const int64_t t8 = (int64_t)h * (w / 2 / 8);
+            hipLaunchKernelGGL((preadd_i8<2, 0, 8>), dim3((unsigned)((t8 + 255) / 256), ntasks),
+                               dim3(256), 0, s, d_tasks, b, fp);
+        }
     } else {
         const int64_t total = (int64_t)h * (w / 2 / 8);
         dim3 g((unsigned)((total + 255) / 256), ntasks);
@@ -545,11 +639,11 @@ static void launch_post_rt(dim3 g, hipStream_t s, const PostaddTask* d_tasks, co
                            const FieldParams& fp, int out_dt)
 {
     switch (out_dt) {
-    case DT_U8: hipLaunchKernelGGL((postadd<RT, uint8_t, CPLX>), g, dim3(256), 0, s, d_tasks, b, fp); break;
-    case DT_U16: hipLaunchKernelGGL((postadd<RT, uint16_t, CPLX>), g, dim3(256), 0, s, d_tasks, b, fp); break;
-    case DT_I32: hipLaunchKernelGGL((postadd<RT, int32_t, CPLX>), g, dim3(256), 0, s, d_tasks, b, fp); break;
-    case DT_I64: hipLaunchKernelGGL((postadd<RT, int64_t, CPLX>), g, dim3(256), 0, s, d_tasks, b, fp); break;
-    case DT_F64: hipLaunchKernelGGL((postadd<RT, double, CPLX>), g, dim3(256), 0, s, d_tasks, b, fp); break;
+    case DT_U8: hipLaunchKernelGGL((postadd<RT, uint8_t, CPLX>), g, dim3(512), 0, s, d_tasks, b, fp); break;
+    case DT_U16: hipLaunchKernelGGL((postadd<RT, uint16_t, CPLX>), g, dim3(512), 0, s, d_tasks, b, fp); break;
+    case DT_I32: hipLaunchKernelGGL((postadd<RT, int32_t, CPLX>), g, dim3(512), 0, s, d_tasks, b, fp); break;
+    case DT_I64: hipLaunchKernelGGL((postadd<RT, int64_t, CPLX>), g, dim3(512), 0, s, d_tasks, b, fp); break;
+    case DT_F64: hipLaunchKernelGGL((postadd<RT, double, CPLX>), g, dim3(512), 0, s, d_tasks, b, fp); break;
     default: break;
     }
 }

@@ -149,7 +149,8 @@ struct CondTask {
 // ---- launch wrappers (defined in the .hip files) ---------------------------
 // All return a hipError_t value cast to int.
 int launch_zero_flag(int32_t* d_flag, void* stream);
-int launch_condition(const CondTask* d_tasks, int ntasks, int max_blocks, const Bases& b,
+// dt_in: the caller's input format (every task of a launch shares it)
+int launch_condition(const CondTask* d_tasks, int ntasks, int max_blocks, int dt_in, const Bases& b,
                      const FieldParams& fp, int carrier, int32_t* d_err, void* stream);
 int launch_preadd(const PreaddTask* d_tasks, int ntasks, int h, int w, const Bases& b,
                   const FieldParams& fp, int carrier, void* stream);

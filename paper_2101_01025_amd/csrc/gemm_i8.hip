@@ -53,6 +53,20 @@ __device__ __forceinline__ int32_t mod_i32(int32_t x, int32_t p, float inv_p)
     return r;
 }
 
+// Canonical residue of an int32 for p < 2^8 with full-rate 24-bit arithmetic:
+// x = hi 2^16 + lo, v = hi (2^16 mod p) + lo has |v| < 2^24 (exact in fp32), one
+// fp32 quotient within one of v / p, then a correction.  c16 = 2^16 mod p.
+__device__ __forceinline__ int32_t mod_small_p(int32_t x, int32_t p, int32_t c16, float inv_p)
+{
+    const int32_t hi = x >> 16, lo = x & 0xffff;
+    const int32_t v = __mul24(hi, c16) + lo;
+    const int32_t q = (int32_t)floorf((float)v * inv_p);
+    int32_t r = v - __mul24(q, p);
+    r += (r < 0) ? p : 0;
+    r -= (r >= p) ? p : 0;
+    return r;
+}
+
 template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF>
 __global__ void __launch_bounds__(WGM* WGN * 64)
     gemm_i8(Bases bases, const GemmTask* __restrict__ tasks, const TileEnt* __restrict__ sched,
@@ -84,42 +98,47 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
 
-    // ---- per-thread global source pointers (segment 0, k = 0) and LDS slots
-    const char* aptr[ACH];
-    const char* bptr[BCH];
-    int alds[ACH], blds[BCH];
+    // ---- operand panels as buffer resources: every load is (constant per-thread
+    // offset, stage offset in a scalar register).  Rows past the matrix are clamped
+    // to its last row; the resource extent covers exactly the rows of this tile.
+    constexpr int NSUB = (CPLX ? 3 : 1) * NL;  // carrier sub-planes an operand may touch
+    const int rows_a = min(BT, M - row0), rows_b = min(BT, N - col0);
+    const char* abase = bases.p[T.x.buf] + T.x.off + (int64_t)row0 * T.x.ld;
+    const char* bbase = bases.p[T.z.buf] + T.z.off + (int64_t)col0 * T.z.ld;
+    const int ext_a = (int)((NSUB - 1) * T.x.ps + (int64_t)rows_a * T.x.ld);
+    const int ext_b = (int)((NSUB - 1) * T.z.ps + (int64_t)rows_b * T.z.ld);
+    const __amdgpu_buffer_rsrc_t rsa = __builtin_amdgcn_make_buffer_rsrc((void*)abase, (short)0, ext_a, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsb = __builtin_amdgcn_make_buffer_rsrc((void*)bbase, (short)0, ext_b, 0x00020000);
+    int aoff[ACH], boff[BCH], alds[ACH], blds[BCH];
 #pragma unroll
     for (int i = 0; i < ACH; ++i) {
         const int c = tid + i * NT;
         const int sub = c / (BT * SPR), r = (c / SPR) % BT, s = c % SPR;
-        const int grow = min(row0 + r, M - 1);
-        aptr[i] = bases.p[T.x.buf] + T.x.off + (int64_t)sub * T.x.ps + (int64_t)grow * T.x.ld + s * 16;
+        aoff[i] = (int)(sub * T.x.ps + (int64_t)min(r, rows_a - 1) * T.x.ld) + s * 16;
         alds[i] = sub * TILE + swz<KT>(r, s);
     }
 #pragma unroll
     for (int i = 0; i < BCH; ++i) {
         const int c = tid + i * NT;
         const int sub = c / (BT * SPR), r = (c / SPR) % BT, s = c % SPR;
-        const int grow = min(col0 + r, N - 1);
-        bptr[i] = bases.p[T.z.buf] + T.z.off + (int64_t)sub * T.z.ps + (int64_t)grow * T.z.ld + s * 16;
+        boff[i] = (int)(sub * T.z.ps + (int64_t)min(r, rows_b - 1) * T.z.ld) + s * 16;
         blds[i] = (NA + sub) * TILE + swz<KT>(r, s);
     }
     // Complex: A sub-tile index sub = role * NL + limb reads plane role (segment 0) and
     // plane role + 1 (segment 1); B reads plane 0 then plane 1.
     const int nkc = K / KT;
     const int nst = NSEG * nkc;
-    const int64_t seg_a = (int64_t)NL * T.x.ps, seg_b = (int64_t)NL * T.z.ps;
+    const int seg_a = (int)(NL * T.x.ps), seg_b = (int)(NL * T.z.ps);
 
     v4i ra[PF][ACH], rb[PF][BCH];
     auto gload = [&](int st, v4i* a, v4i* b) {
         const int seg = st >= nkc ? 1 : 0;
         const int kc = st - seg * nkc;
-        const int64_t oa = seg * seg_a + (int64_t)kc * KT;
-        const int64_t ob = seg * seg_b + (int64_t)kc * KT;
+        const int oa = seg * seg_a + kc * KT, ob = seg * seg_b + kc * KT;
 #pragma unroll
-        for (int i = 0; i < ACH; ++i) a[i] = *reinterpret_cast<const v4i*>(aptr[i] + oa);
+        for (int i = 0; i < ACH; ++i) a[i] = __builtin_amdgcn_raw_buffer_load_b128(rsa, aoff[i], oa, 0);
 #pragma unroll
-        for (int i = 0; i < BCH; ++i) b[i] = *reinterpret_cast<const v4i*>(bptr[i] + ob);
+        for (int i = 0; i < BCH; ++i) b[i] = __builtin_amdgcn_raw_buffer_load_b128(rsb, boff[i], ob, 0);
     };
     auto sstore = [&](int buf, const v4i* a, const v4i* b) {
         char* base = lds + buf * STAGE;
@@ -142,49 +161,59 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
                     for (int v = 0; v < 16; ++v) acc[r][a][m][n][v] = 0;
 
     const int lrow = lane & 31, lseg = lane >> 5;
-    auto compute = [&](int buf) {
-        const char* base = lds + buf * STAGE;
+    // fragment reads of k-step ks (32 bytes of K) from an LDS stage
+    auto load_frags = [&](const char* base, int ks, v4i (*af)[FM], v4i (*bf)[FN]) {
 #pragma unroll
-        for (int ks = 0; ks < KT / 32; ++ks) {
-            v4i af[NA][FM], bf[NB][FN];
+        for (int a = 0; a < NA; ++a)
 #pragma unroll
-            for (int a = 0; a < NA; ++a)
+            for (int m = 0; m < FM; ++m)
+                af[a][m] = *reinterpret_cast<const v4i*>(
+                    base + a * TILE + swz<KT>(wm0 + m * 32 + lrow, ks * 2 + lseg));
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int n = 0; n < FN; ++n)
+                bf[b][n] = *reinterpret_cast<const v4i*>(
+                    base + (NA + b) * TILE + swz<KT>(wn0 + n * 32 + lrow, ks * 2 + lseg));
+    };
+    auto mfmas = [&](v4i (*af)[FM], v4i (*bf)[FN]) {
+        if (NL == 1) {
+#pragma unroll
+            for (int r = 0; r < NROLE; ++r)
 #pragma unroll
                 for (int m = 0; m < FM; ++m)
-                    af[a][m] = *reinterpret_cast<const v4i*>(
-                        base + a * TILE + swz<KT>(wm0 + m * 32 + lrow, ks * 2 + lseg));
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
+                    for (int n = 0; n < FN; ++n)
+                        acc[r][0][m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                            af[r][m], bf[0][n], acc[r][0][m][n], 0, 0, 0);
+        } else {
+            // limb products (hi,hi) -> 0, (hi,lo) and (lo,hi) -> 1, (lo,lo) -> 2, ordered
+            // so that consecutive MFMAs do not share an accumulator
 #pragma unroll
-                for (int n = 0; n < FN; ++n)
-                    bf[b][n] = *reinterpret_cast<const v4i*>(
-                        base + (NA + b) * TILE + swz<KT>(wn0 + n * 32 + lrow, ks * 2 + lseg));
-            if (NL == 1) {
+            for (int pr = 0; pr < 4; ++pr) {
+                const int la = pr >> 1, lb = pr & 1;
+                const int ai = (pr == 0) ? 0 : (pr == 3 ? 2 : 1);
 #pragma unroll
                 for (int r = 0; r < NROLE; ++r)
 #pragma unroll
                     for (int m = 0; m < FM; ++m)
 #pragma unroll
                         for (int n = 0; n < FN; ++n)
-                            acc[r][0][m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                                af[r][m], bf[0][n], acc[r][0][m][n], 0, 0, 0);
-            } else {
-                // limb products (hi,hi) -> 0, (hi,lo) and (lo,hi) -> 1, (lo,lo) -> 2, ordered
-                // so that consecutive MFMAs do not share an accumulator
-#pragma unroll
-                for (int pr = 0; pr < 4; ++pr) {
-                    const int la = pr >> 1, lb = pr & 1;
-                    const int ai = (pr == 0) ? 0 : (pr == 3 ? 2 : 1);
-#pragma unroll
-                    for (int r = 0; r < NROLE; ++r)
-#pragma unroll
-                        for (int m = 0; m < FM; ++m)
-#pragma unroll
-                            for (int n = 0; n < FN; ++n)
-                                acc[r][ai][m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                                    af[r * NL + la][m], bf[lb][n], acc[r][ai][m][n], 0, 0, 0);
-                }
+                            acc[r][ai][m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                af[r * NL + la][m], bf[lb][n], acc[r][ai][m][n], 0, 0, 0);
             }
+        }
+    };
+    // the fragments of k-step ks + 1 are read while the MFMAs of k-step ks run
+    constexpr int NKS = KT / 32;
+    auto compute = [&](int buf) {
+        const char* base = lds + buf * STAGE;
+        v4i af[2][NA][FM], bf[2][NB][FN];
+        load_frags(base, 0, af[0], bf[0]);
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+            if (ks + 1 < NKS) load_frags(base, ks + 1, af[(ks + 1) & 1], bf[(ks + 1) & 1]);
+            mfmas(af[ks & 1], bf[ks & 1]);
         }
     };
 
@@ -214,9 +243,12 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     // 8 (v / 4) + 4 (lane / 32) + v % 4 of the fragment.
     const int p = fp.p;
     const float inv_pf = (float)fp.inv_p;
+    const int32_t c16 = (int32_t)(65536 % p);
     const int i0 = row0 + wm0 + 4 * (lane >> 5), j0 = col0 + wn0 + (lane & 31);
     const bool syrk = T.syrk != 0;
     const int64_t ldc = T.c.ld;
+    // interior tiles (inside the matrix and strictly below the diagonal) need no checks
+    const bool interior = row0 + BT <= M && col0 + BT <= N && (!syrk || row0 >= col0 + BT);
     auto epilogue = [&](auto tag) {
         using OT = decltype(tag);
 #pragma unroll
@@ -231,7 +263,8 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
                     for (int v = 0; v < 16; ++v) {
                         int32_t res;
                         if (NL == 1) {
-                            res = mod_i32(acc[r][0][m][n][v], p, inv_pf);
+                            res = p < 256 ? mod_small_p(acc[r][0][m][n][v], p, c16, inv_pf)
+                                          : mod_i32(acc[r][0][m][n][v], p, inv_pf);
                         } else {
                             const double val = 65536.0 * (double)acc[r][0][m][n][v] +
                                                256.0 * (double)acc[r][NACC - 2][m][n][v] +
@@ -240,7 +273,8 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
                         }
                         const int i = i0 + m * 32 + 8 * (v >> 2) + (v & 3);
                         const int j = j0 + n * 32;
-                        if (i < M && j < N && (!syrk || i >= j)) cp[(int64_t)i * ldc + j] = (OT)res;
+                        if (interior || (i < M && j < N && (!syrk || i >= j)))
+                            cp[(int64_t)i * ldc + j] = (OT)res;
                         // keep the scheduler from hoisting the reads of every accumulator
                         if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
                     }
@@ -300,7 +334,7 @@ int gemm_i8_default_config(int nl, int cplx, int64_t max_dim)
 {
     if (cplx) return nl == 1 ? 4 : 8;
     if (nl == 2) return 9;
-    return max_dim >= 2048 ? 1 : 2;
+    return max_dim >= 2048 ? 10 : 2;
 }
 
 template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF>

@@ -55,7 +55,7 @@ def test_skew_unitary_errors():
 def test_plan_levels_padding_and_carriers():
     st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8)
     assert st == 0 and d["carrier"] == "int8" and d["limbs"] == 1 and d["direct"] == 1
-    assert d["levels"] >= 1 and d["npad"] == 16384 and d["kpad"] == 16384
+    assert d["levels"] == 1 and d["npad"] == 16384 and d["kpad"] == 16384
     assert d["ykind"] == 1 and (d["ya"], d["yb"]) == (80, 80)
     st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
                               opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
@@ -121,3 +121,10 @@ def test_degenerate_plans():
     assert st == 0 and d["levels"] == 0 and d["gemm_tasks"] == 1
     st, d = ffa.plan_describe(1, 7, 251, opts=ffa.make_opts(levels=3))
     assert st == 0 and d["levels"] == 0
+
+
+def test_plan_refuses_operands_beyond_32bit_offsets():
+    # two-limb carrier: two planes of n*k bytes must stay addressable with 32-bit offsets
+    assert ffa.plan_describe(16384, 16384, 65521, dA=ffa.U16, dC=ffa.U16)[0] == 0
+    assert ffa.plan_describe(50000, 50000, 65521, dA=ffa.U16, dC=ffa.U16,
+                             opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))[0] == ffa.EUNSUPPORTED
