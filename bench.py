@@ -121,7 +121,8 @@ def timed_steps(ffa, torch, w, A, Ai, C, Ci, plans, steps, warmup, blocks=5):
     The plans run in alternating blocks so that clock and thermal drift during
     the run affects both alike.  Phase durations come from HIP events the
     library records around each phase on the same stream.
-    Returns per plan: (ms per step, {phase: ms per call}).
+    Returns per plan: (ms per step, {phase: summed ms of its launches per call},
+    {phase: launches per call}).
     """
     def one(opts):
         if Ai is None:
@@ -160,9 +161,9 @@ def timed_steps(ffa, torch, w, A, Ai, C, Ci, plans, steps, warmup, blocks=5):
                 phase_calls[i][name] = phase_calls[i].get(name, 0) + calls
     out = []
     for i in range(len(plans)):
-        ph = {name: round(phase_ms[i][name] / phase_calls[i][name], 4) if phase_calls[i][name] else 0.0
-              for _, name in names}
-        out.append((total[i] / steps, ph))
+        ph = {name: round(phase_ms[i][name] / steps, 4) for _, name in names}
+        nl = {name: phase_calls[i][name] / steps for _, name in names}
+        out.append((total[i] / steps, ph, nl))
     return out
 
 
@@ -225,7 +226,7 @@ def main():
                                 opts=opts)
     plans = [opts] if args.no_classical else [opts, ffa.make_opts(algo=ffa.ALGO_CLASSICAL)]
     res = timed_steps(ffa, torch, w, A, Ai, C, Ci, plans, args.steps, args.warmup)
-    ms, phases = res[0]
+    ms, phases, launches = res[0]
     value = n * n * k / (ms * 1e-3)
 
     out = {
@@ -246,8 +247,10 @@ def main():
                    "n": n, "k": k, "p": p, "levels": plan["levels"], "limbs": plan["limbs"],
                    "parallelism": "single GPU"},
         "phases_ms": phases,
+        "product_launches_per_step": launches["products"],
     }
-    # roofline of the dominant kernel: the grouped product launch
+    # roofline of the dominant kernel, the grouped product kernel: algorithmic ops of
+    # its launches in one step over their summed durations (HIP events per launch)
     limb2 = plan["limbs"] ** 2 * (4 if herm else 1)
     ops = 2.0 * plan["macs"] * limb2
     prod_ms = phases["products"]
@@ -257,15 +260,15 @@ def main():
                            "achieved": achieved, "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
                            "frac": achieved / PEAK_INT8_TOPS,
                            "traffic": measured_traffic(args.workload, plan["levels"]),
-                           "ops_per_launch": ops}
+                           "ops_per_step": ops}
     else:
         achieved = ops / (prod_ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "mfma", "kernel": "gemm_f64 (grouped products)",
                            "achieved": achieved, "peak": PEAK_F64_TFLOPS, "unit": "TFLOP/s",
                            "frac": achieved / PEAK_F64_TFLOPS, "traffic": None,
-                           "ops_per_launch": ops}
+                           "ops_per_step": ops}
     if not args.no_classical:
-        cms, cph = res[1]
+        cms, cph, _ = res[1]
         out["classical_gpu"] = {"value": n * n * k / (cms * 1e-3), "unit": "n^2k/s",
                                 "ms_per_step": cms, "products_ms": cph["products"]}
         out["speedup_vs_classical"] = cms / ms

@@ -65,20 +65,29 @@ enum {
 enum { FFA_ALGO_AUTO = 0, FFA_ALGO_CLASSICAL = 1, FFA_ALGO_RECURSIVE = 2 };
 enum { FFA_CARRIER_AUTO = 0, FFA_CARRIER_INT8 = 1, FFA_CARRIER_F64 = 2 };
 
-/* Options; pass NULL for the defaults (all fields zero except levels = -1, cutoff = 0).
+/* Options; pass NULL for the defaults (all fields zero except levels = -1, cutoff = 0),
+ * or the autotuned choice for the shape when ffa_autotune_syrk has recorded one.
  *   algo          FFA_ALGO_*; CLASSICAL = no recursion (the plain modular SYRK)
  *   levels        recursion depth of Algorithm 1 when >= 0; -1 = from cutoff
  *   cutoff        recurse while the sub-problem has more than cutoff rows (0 = built-in default)
  *   carrier       FFA_CARRIER_*: INT8 = balanced int8 limbs on INT8 MFMA (1 limb for p < 256,
  *                 2 limbs for p < 2^16); F64 = doubles on FP64 MFMA (p < 2^26, real only)
- *   check_inputs  nonzero: verify every entry of A (synchronises the stream; FFA_ERANGE) */
+ *   check_inputs  nonzero: verify every entry of A (synchronises the stream; FFA_ERANGE)
+ *   kernel        INT8 product-kernel configuration + 1 (tile shape, k-tile, pipeline depth);
+ *                 0 = built-in choice; a configuration that does not fit the carrier is ignored
+ *   launch        batched execution only: FFA_LAUNCH_GRAPH (default) replays the plan's
+ *                 launch sequence as one captured hipGraph; FFA_LAUNCH_DIRECT enqueues
+ *                 the kernels one by one */
+enum { FFA_LAUNCH_GRAPH = 0, FFA_LAUNCH_DIRECT = 1 };
 typedef struct {
     int32_t algo;
     int32_t levels;
     int32_t cutoff;
     int32_t carrier;
     int32_t check_inputs;
-    int32_t reserved[3];
+    int32_t kernel;
+    int32_t launch;
+    int32_t reserved;
 } ffa_opts;
 
 /* Context bound to a HIP device and stream (stream NULL = the null stream).
@@ -116,8 +125,16 @@ int ffa_herk_modp2(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA,
 /* Batched C_i = Low(A_i A_i^T) mod p for independent problems (one p).
  * Problems use a PACKED layout: A_i starts at element a_off[i] of one buffer with
  * lda = k_i, C_i at element c_off[i] of another with ldc = n_i; the offsets are
- * fixed by the plan (ffa_batch_offsets).  The plan (host work, may allocate) is
- * made once; ffa_batch_syrk_exec then only enqueues kernels (no allocation). */
+ * fixed by the plan (ffa_batch_offsets); both buffers must be 16-byte aligned.
+ * The plan (host work: tables, its own device workspace) is made once and owns
+ * that workspace, so later single calls on the context never move it.
+ * ffa_batch_syrk_exec allocates nothing.  With opts.launch = FFA_LAUNCH_GRAPH it
+ * captures the plan's launch sequence into a hipGraph on a private stream the
+ * first time it sees a pair of buffers (and again when the pair changes) and
+ * then enqueues one hipGraphLaunch on the context's stream; it falls back to
+ * direct launches while phase profiling is on, with check_inputs, and when the
+ * context's stream is itself being captured (the kernels then join the caller's
+ * graph).  One plan must not be executed from two threads at once. */
 int ffa_batch_syrk_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int64_t* k,
                         uint32_t p, int dA, int dC, const ffa_opts* opts, ffa_batch** out);
 int ffa_batch_offsets(const ffa_batch* b, int64_t* a_off, int64_t* c_off,
@@ -133,6 +150,33 @@ int ffa_batch_destroy(ffa_batch* b);
 int ffa_profile_enable(ffa_ctx* ctx, int on);
 int ffa_profile_read(ffa_ctx* ctx, int phase, double* total_ms, int64_t* calls);
 int ffa_profile_reset(ffa_ctx* ctx);
+
+/* Autotuner.  Times every candidate plan for this call (recursion depth 0..4 that
+ * the sizes allow x carrier (INT8 limbs, and FP64 where its bound holds) x every
+ * INT8 product-kernel configuration of the carrier) on the caller's own buffers
+ * with HIP events, `reps` timed calls each, and records the fastest for the shape
+ * (n, k, p, formats) in the context: later calls with opts = NULL use it, and
+ * so do other shapes of the same size class (n and k within the same half-octave)
+ * that have no record of their own.  C receives the (identical) result of every
+ * candidate.  best (optional) receives the chosen options, best_ms its time per
+ * call.  Synchronises the stream. */
+int ffa_autotune_syrk(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p,
+                      int dA, const void* A, int64_t lda, int dC, void* C, int64_t ldc,
+                      int reps, ffa_opts* best, double* best_ms);
+/* Same for a batch plan: re-plans with each carrier, product-kernel configuration
+ * and recursion cutoff (classical, 256, 384), keeps the fastest in the plan. */
+int ffa_batch_autotune(ffa_batch* b, const void* A_packed, void* C_packed, int reps,
+                       ffa_opts* best, double* best_ms);
+
+/* The context's autotuner records as JSON text
+ *   {"arch":"gfx950","records":[{"n":..,"k":..,"p":..,"herm":..,"dA":..,"dC":..,
+ *    "algo":..,"levels":..,"cutoff":..,"carrier":..,"kernel":..}, ...]}
+ * ffa_tune_export writes it into buf (NUL-terminated; nothing written when size is
+ * too small) and returns the length it needs without the NUL, or a negative status.
+ * ffa_tune_import adds the records of such a text (records for another arch are
+ * skipped) and returns how many it took, or FFA_EINVAL for text it cannot read. */
+int64_t ffa_tune_export(const ffa_ctx* ctx, char* buf, int64_t size);
+int ffa_tune_import(ffa_ctx* ctx, const char* json);
 
 /* Host-only description of the plan ffa_syrk_modp / ffa_herk_modp2 would use
  * (no device needed): writes a JSON object (levels, padded sizes, carrier,

@@ -67,6 +67,8 @@ def lib():
         L.oracle_herk_entries.restype = ctypes.c_int
         L.oracle_freivalds_syrk.argtypes = [i64, i64, i64, P, i64, P, i64, P, P, P]
         L.oracle_freivalds_syrk.restype = ctypes.c_int
+        L.oracle_freivalds_herk.argtypes = [i64, i64, i64, P, P, i64, P, P, i64, P, P, P, P, P, P]
+        L.oracle_freivalds_herk.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -163,6 +165,17 @@ def freivalds_syrk(A, C, p, x):
     _chk(lib().oracle_freivalds_syrk(n, k, p, _ptr(A), max(k, 1), _ptr(C), max(n, 1), _ptr(x),
                                      _ptr(yc), _ptr(ya)))
     return yc, ya
+
+
+def freivalds_herk(Ar, Ai, Cr, Ci, p, xr, xi):
+    """((Re, Im) of Herm(C) x, (Re, Im) of A (A^H x)) mod p; equal for a correct C."""
+    Ar, Ai, Cr, Ci = _i64(Ar), _i64(Ai), _i64(Cr), _i64(Ci)
+    xr, xi = _i64(xr), _i64(xi)
+    n, k = Ar.shape
+    out = [np.zeros(n, dtype=np.int64) for _ in range(4)]
+    _chk(lib().oracle_freivalds_herk(n, k, p, _ptr(Ar), _ptr(Ai), max(k, 1), _ptr(Cr), _ptr(Ci),
+                                     max(n, 1), _ptr(xr), _ptr(xi), *[_ptr(v) for v in out]))
+    return (out[0], out[1]), (out[2], out[3])
 
 
 def num_threads():

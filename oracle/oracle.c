@@ -289,6 +289,56 @@ int oracle_freivalds_syrk(int64_t n, int64_t k, int64_t p, const int64_t* A, int
     return ORC_OK;
 }
 
+/* Hermitian Freivalds over F_p[i]: with S the Hermitian matrix whose lower
+ * triangle is C (S_ij = C_ij for j <= i, S_ij = conj(C_ji) above) and a
+ * complex x, y_c = S x and y_a = A (A^H x), both mod p, planar re/im. */
+int oracle_freivalds_herk(int64_t n, int64_t k, int64_t p, const int64_t* Ar, const int64_t* Ai,
+                          int64_t lda, const int64_t* Cr, const int64_t* Ci, int64_t ldc,
+                          const int64_t* xr, const int64_t* xi, int64_t* ycr, int64_t* yci,
+                          int64_t* yar, int64_t* yai)
+{
+    int st = check_args(n, k, p, lda, ldc);
+    if (st) return st;
+    int64_t* wr = (int64_t*)calloc((size_t)(k > 0 ? k : 1), sizeof(int64_t));
+    int64_t* wi = (int64_t*)calloc((size_t)(k > 0 ? k : 1), sizeof(int64_t));
+    if (!wr || !wi) { free(wr); free(wi); return ORC_EINVAL; }
+    /* w = A^H x: w_t = sum_i conj(A_it) x_i */
+    for (int64_t t = 0; t < k; ++t) {
+        i128 sr = 0, si = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t ar = Ar[i * lda + t], ai = Ai[i * lda + t];
+            sr += (i128)ar * xr[i] + (i128)ai * xi[i];
+            si += (i128)ar * xi[i] - (i128)ai * xr[i];
+        }
+        wr[t] = canon128(sr, p);
+        wi[t] = canon128(si, p);
+    }
+#pragma omp parallel for schedule(static, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        i128 sr = 0, si = 0;
+        for (int64_t t = 0; t < k; ++t) {
+            const int64_t ar = Ar[i * lda + t], ai = Ai[i * lda + t];
+            sr += (i128)ar * wr[t] - (i128)ai * wi[t];
+            si += (i128)ar * wi[t] + (i128)ai * wr[t];
+        }
+        yar[i] = canon128(sr, p);
+        yai[i] = canon128(si, p);
+        i128 ur = 0, ui = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            int64_t cr, ci;
+            if (j <= i) { cr = Cr[i * ldc + j]; ci = Ci[i * ldc + j]; }
+            else { cr = Cr[j * ldc + i]; ci = -Ci[j * ldc + i]; }
+            ur += (i128)cr * xr[j] - (i128)ci * xi[j];
+            ui += (i128)cr * xi[j] + (i128)ci * xr[j];
+        }
+        ycr[i] = canon128(ur, p);
+        yci[i] = canon128(ui, p);
+    }
+    free(wr);
+    free(wi);
+    return ORC_OK;
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

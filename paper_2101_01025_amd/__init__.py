@@ -19,12 +19,14 @@ OK, EINVAL, EPRIME, ERANGE, ENOMEM, EDEVICE, EUNSUPPORTED, EBOUND = 0, -1, -2, -
 I64, I32, U16, U8, F64, I8_CENTRED = 0, 1, 2, 3, 4, 5
 ALGO_AUTO, ALGO_CLASSICAL, ALGO_RECURSIVE = 0, 1, 2
 CARRIER_AUTO, CARRIER_INT8, CARRIER_F64 = 0, 1, 2
+LAUNCH_GRAPH, LAUNCH_DIRECT = 0, 1
 
 SYMBOLS = [
     "ffa_create", "ffa_destroy", "ffa_set_stream", "ffa_last_device_error", "ffa_status_string",
     "ffa_skew_unitary", "ffa_syrk_modp", "ffa_herk_modp2", "ffa_batch_syrk_plan",
     "ffa_batch_offsets", "ffa_batch_syrk_exec", "ffa_batch_destroy", "ffa_plan_describe",
     "ffa_profile_enable", "ffa_profile_read", "ffa_profile_reset",
+    "ffa_autotune_syrk", "ffa_batch_autotune", "ffa_tune_export", "ffa_tune_import",
 ]
 PHASE_COND, PHASE_PRE, PHASE_PRODUCTS, PHASE_POST = 0, 1, 2, 3
 
@@ -38,11 +40,15 @@ class FfaError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("levels", ctypes.c_int32), ("cutoff", ctypes.c_int32),
                 ("carrier", ctypes.c_int32), ("check_inputs", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("kernel", ctypes.c_int32), ("launch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
-def make_opts(algo=ALGO_AUTO, levels=-1, cutoff=0, carrier=CARRIER_AUTO, check_inputs=False):
-    return Opts(algo, levels, cutoff, carrier, int(bool(check_inputs)))
+def make_opts(algo=ALGO_AUTO, levels=-1, cutoff=0, carrier=CARRIER_AUTO, check_inputs=False,
+              kernel=0, launch=LAUNCH_GRAPH):
+    return Opts(algo, levels, cutoff, carrier, int(bool(check_inputs)), kernel, launch)
 
 
 _lib = None
@@ -73,6 +79,12 @@ def lib():
         L.ffa_profile_enable.argtypes = [P, i32]
         L.ffa_profile_read.argtypes = [P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         L.ffa_profile_reset.argtypes = [P]
+        L.ffa_autotune_syrk.argtypes = [P, i64, i64, u32, i32, P, i64, i32, P, i64, i32, P,
+                                         ctypes.POINTER(ctypes.c_double)]
+        L.ffa_batch_autotune.argtypes = [P, P, P, i32, P, ctypes.POINTER(ctypes.c_double)]
+        L.ffa_tune_export.argtypes = [P, ctypes.c_char_p, i64]
+        L.ffa_tune_export.restype = i64
+        L.ffa_tune_import.argtypes = [P, ctypes.c_char_p]
         L.ffa_plan_describe.argtypes = [i64, i64, u32, i32, i32, i32, i64, i64, P, ctypes.c_char_p,
                                         i64]
         _lib = L
@@ -219,6 +231,41 @@ def herk_modp2(A_re, A_im, p, C_re=None, C_im=None, out_dtype=None, opts=None, *
     return C_re, C_im
 
 
+def autotune_syrk(A, p, C=None, out_dtype=None, reps=3):
+    """Runs the autotuner for this call; returns (chosen Opts, ms per call).  Later
+    calls with the same shape and formats and no explicit options use the choice."""
+    ctx = _prep(A)
+    n, k = A.shape
+    C = _out(C, n, A.device, out_dtype or default_out_dtype(p))
+    best = Opts()
+    ms = ctypes.c_double()
+    st = lib().ffa_autotune_syrk(ctx, n, k, p, _dtype_code(A), ctypes.c_void_p(A.data_ptr()),
+                                 max(A.stride(0), k, 1), _dtype_code(C, True),
+                                 ctypes.c_void_p(C.data_ptr()), max(C.stride(0), n, 1), reps,
+                                 ctypes.byref(best), ctypes.byref(ms))
+    _check(st, "autotune")
+    return best, ms.value
+
+
+def tune_export(device_index=0):
+    """The context's autotuner records as a JSON string."""
+    ctx = context(device_index)
+    need = lib().ffa_tune_export(ctx, None, 0)
+    if need < 0:
+        raise FfaError(int(need), "tune export")
+    buf = ctypes.create_string_buffer(need + 1)
+    lib().ffa_tune_export(ctx, buf, need + 1)
+    return buf.value.decode()
+
+
+def tune_import(text, device_index=0):
+    """Adds autotuner records from tune_export's JSON; returns how many were taken."""
+    st = lib().ffa_tune_import(context(device_index), text.encode())
+    if st < 0:
+        raise FfaError(st, "tune import")
+    return st
+
+
 class BatchSyrk:
     """Batched Low(A_i A_i^T) mod p over a packed layout (ffa_batch_syrk_*)."""
 
@@ -247,6 +294,17 @@ class BatchSyrk:
         lib().ffa_set_stream(self.ctx, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
         _check(lib().ffa_batch_syrk_exec(self.handle, ctypes.c_void_p(A_packed.data_ptr()),
                                          ctypes.c_void_p(C_packed.data_ptr())), "batch exec")
+
+    def autotune(self, A_packed, C_packed, reps=3):
+        """Re-plans with each kernel configuration / cutoff, keeps the fastest."""
+        torch = _torch()
+        lib().ffa_set_stream(self.ctx, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        best = Opts()
+        ms = ctypes.c_double()
+        _check(lib().ffa_batch_autotune(self.handle, ctypes.c_void_p(A_packed.data_ptr()),
+                                        ctypes.c_void_p(C_packed.data_ptr()), reps,
+                                        ctypes.byref(best), ctypes.byref(ms)), "batch autotune")
+        return best, ms.value
 
     def close(self):
         if self.handle:

@@ -2,6 +2,8 @@
 // the launch sequence of a plan on the context's stream.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -16,12 +18,15 @@ using namespace ffa;
 
 struct ffa_ctx {
     int device = 0;
+    std::string arch;  // gcnArchName up to the first ':'
+
     hipStream_t stream = nullptr;
     char* ws = nullptr;
     int64_t ws_bytes = 0;
     int32_t* d_err = nullptr;
     int last_err = 0;
     std::map<std::string, std::unique_ptr<Plan>> cache;
+    std::map<std::string, ffa_opts> tuned;  // autotuner's choice per shape and per size class
     // phase timing
     bool prof = false;
     struct Pending {
@@ -36,7 +41,15 @@ struct ffa_ctx {
 
 struct ffa_batch {
     ffa_ctx* ctx = nullptr;
+    std::vector<Problem> prs;
     Plan plan;
+    char* ws = nullptr;  // the plan's own workspace
+    int64_t ws_bytes = 0;
+    // captured launch sequence for one (A, C) pair
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const void* gA = nullptr;
+    void* gC = nullptr;
 };
 
 namespace {
@@ -52,11 +65,47 @@ ffa_opts default_opts()
 std::string key_of(const Problem& p)
 {
     char buf[256];
-    snprintf(buf, sizeof(buf), "%lld|%lld|%lld|%lld|%u|%d|%d|%d|%d|%d|%d|%d|%d|%d", (long long)p.n,
+    snprintf(buf, sizeof(buf), "%lld|%lld|%lld|%lld|%u|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d", (long long)p.n,
              (long long)p.k, (long long)p.lda, (long long)p.ldc, p.p, p.herm, p.dA, p.dC,
              p.opts.algo, p.opts.levels, p.opts.cutoff, p.opts.carrier, p.opts.check_inputs,
-             p.aligned ? 1 : 0);
+             p.opts.kernel, p.aligned ? 1 : 0);
     return buf;
+}
+
+// keys of the autotuner's records: the exact shape, and its size class (n and k
+// by half-octave)
+std::string tune_key(int64_t n, int64_t k, uint32_t p, int herm, int dA, int dC)
+{
+    char buf[128];
+    snprintf(buf, sizeof(buf), "%lld|%lld|%u|%d|%d|%d", (long long)n, (long long)k, p, herm, dA, dC);
+    return buf;
+}
+
+// 2 floor(log2 x) + (x >= 1.5 * 2^floor(log2 x)); -1 for x <= 0
+int half_octave(int64_t x)
+{
+    if (x <= 0) return -1;
+    int e = 0;
+    while ((x >> (e + 1)) > 0) ++e;
+    const int64_t base = (int64_t)1 << e;
+    return 2 * e + (x >= base + base / 2 ? 1 : 0);
+}
+
+std::string tune_class_key(int64_t n, int64_t k, uint32_t p, int herm, int dA, int dC)
+{
+    char buf[128];
+    snprintf(buf, sizeof(buf), "c%d|%d|%u|%d|%d|%d", half_octave(n), half_octave(k), p, herm, dA, dC);
+    return buf;
+}
+
+bool tuned_opts(const ffa_ctx* c, int64_t n, int64_t k, uint32_t p, int herm, int dA, int dC,
+                ffa_opts* o)
+{
+    auto it = c->tuned.find(tune_key(n, k, p, herm, dA, dC));
+    if (it == c->tuned.end()) it = c->tuned.find(tune_class_key(n, k, p, herm, dA, dC));
+    if (it == c->tuned.end()) return false;
+    *o = it->second;
+    return true;
 }
 
 int dev_fail(ffa_ctx* c, int e)
@@ -156,13 +205,11 @@ void free_tables(Plan& pl)
 
 // The launch sequence: conditioning, pre-additions (top-down), all products in
 // one grouped launch, post-additions (bottom-up).
-int run_plan(ffa_ctx* c, Plan& pl, Bases b)
+// The workspace (at least pl.ws_bytes) and the uploaded tables are the caller's
+// to provide.
+int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws)
 {
-    int st = ensure_workspace(c, pl.ws_bytes);
-    if (st) return st;
-    st = upload_tables(c, pl);
-    if (st) return st;
-    b.p[BUF_WS] = c->ws;
+    b.p[BUF_WS] = ws;
     char* blob = (char*)pl.d_blob;
     void* s = (void*)c->stream;
     int e;
@@ -239,7 +286,90 @@ int run_call(ffa_ctx* c, const Problem& pr, const void* A, const void* A2, void*
     b.p[BUF_A2] = (char*)A2;
     b.p[BUF_C] = (char*)C;
     b.p[BUF_C2] = (char*)C2;
-    return run_plan(c, *pl, b);
+    int st = ensure_workspace(c, pl->ws_bytes);
+    if (!st) st = upload_tables(c, *pl);
+    if (st) return st;
+    return run_plan(c, *pl, b, c->ws);
+}
+
+// The batch plan's own workspace, sized for its plan; drops a captured graph
+// (which holds the old addresses).
+void drop_graph(ffa_batch* b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+    b->gA = nullptr;
+    b->gC = nullptr;
+}
+
+int batch_workspace(ffa_batch* b)
+{
+    if (b->plan.ws_bytes <= b->ws_bytes) return FFA_OK;
+    drop_graph(b);
+    if (b->ws) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(b->ws);
+        b->ws = nullptr;
+        b->ws_bytes = 0;
+    }
+    if (hipMalloc((void**)&b->ws, (size_t)b->plan.ws_bytes) != hipSuccess) {
+        b->ws = nullptr;
+        (void)hipGetLastError();
+        return FFA_ENOMEM;
+    }
+    b->ws_bytes = b->plan.ws_bytes;
+    return FFA_OK;
+}
+
+// Captures the plan's launch sequence for buffers bs on the batch's private
+// stream and instantiates (or updates) the executable graph.
+int capture_graph(ffa_batch* b, const Bases& bs)
+{
+    ffa_ctx* c = b->ctx;
+    hipError_t he = hipSuccess;
+    if (!b->cap) {
+        he = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+        if (he != hipSuccess) {
+            b->cap = nullptr;
+            return dev_fail(c, he);
+        }
+    }
+    he = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (he != hipSuccess) return dev_fail(c, he);
+    hipStream_t user = c->stream;
+    c->stream = b->cap;
+    const int st = run_plan(c, b->plan, bs, b->ws);
+    c->stream = user;
+    hipGraph_t g = nullptr;
+    he = hipStreamEndCapture(b->cap, &g);
+    if (st || he != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        drop_graph(b);
+        return st ? st : dev_fail(c, he);
+    }
+    bool updated = false;
+    if (b->gexec) {
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult res;
+        updated = hipGraphExecUpdate(b->gexec, g, &err_node, &res) == hipSuccess &&
+                  res == hipGraphExecUpdateSuccess;
+        if (!updated) {
+            (void)hipGetLastError();
+            drop_graph(b);
+        }
+    }
+    if (!updated) {
+        he = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+        if (he != hipSuccess) {
+            b->gexec = nullptr;
+            (void)hipGraphDestroy(g);
+            return dev_fail(c, he);
+        }
+    }
+    (void)hipGraphDestroy(g);
+    b->gA = bs.p[BUF_A];
+    b->gC = bs.p[BUF_C];
+    return FFA_OK;
 }
 
 }  // namespace
@@ -258,6 +388,12 @@ int ffa_create(ffa_ctx** out, int device, void* hip_stream)
     ffa_ctx* c = new ffa_ctx;
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        c->arch = prop.gcnArchName;
+        const size_t colon = c->arch.find(':');
+        if (colon != std::string::npos) c->arch.resize(colon);
+    }
     hipError_t e = hipSetDevice(device);
     if (e == hipSuccess) e = hipMalloc((void**)&c->d_err, 256);
     if (e != hipSuccess) {
@@ -359,6 +495,7 @@ int ffa_syrk_modp(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA, const 
     pr.dA = dA;
     pr.dC = dC;
     pr.opts = opts ? *opts : default_opts();
+    if (!opts && ctx) (void)tuned_opts(ctx, n, k, p, 0, dA, dC, &pr.opts);
     pr.aligned = ((uintptr_t)A % 16) == 0;
     return run_call(ctx, pr, A, nullptr, C, nullptr);
 }
@@ -377,6 +514,7 @@ int ffa_herk_modp2(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA, const
     pr.dA = dA;
     pr.dC = dC;
     pr.opts = opts ? *opts : default_opts();
+    if (!opts && ctx) (void)tuned_opts(ctx, n, k, p, 1, dA, dC, &pr.opts);
     pr.aligned = false;  // the conditioning always builds the complex planes
     return run_call(ctx, pr, A_re, A_im, C_re, C_im);
 }
@@ -388,6 +526,7 @@ int ffa_batch_syrk_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int
     *out = nullptr;
     std::vector<Problem> prs(count);
     const ffa_opts o = opts ? *opts : default_opts();
+    if (o.launch != FFA_LAUNCH_GRAPH && o.launch != FFA_LAUNCH_DIRECT) return FFA_EINVAL;
     for (int64_t i = 0; i < count; ++i) {
         prs[i].n = n[i];
         prs[i].k = k[i];
@@ -398,6 +537,7 @@ int ffa_batch_syrk_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int
     }
     ffa_batch* b = new ffa_batch;
     b->ctx = ctx;
+    b->prs = prs;
     b->plan = make_batch_plan(prs);
     if (b->plan.status) {
         const int st = b->plan.status;
@@ -405,10 +545,11 @@ int ffa_batch_syrk_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int
         return st;
     }
     (void)hipSetDevice(ctx->device);
-    int st = ensure_workspace(ctx, b->plan.ws_bytes);
+    int st = batch_workspace(b);
     if (!st) st = upload_tables(ctx, b->plan);
     if (st) {
         free_tables(b->plan);
+        if (b->ws) (void)hipFree(b->ws);
         delete b;
         return st;
     }
@@ -438,7 +579,20 @@ int ffa_batch_syrk_exec(ffa_batch* b, const void* A_packed, void* C_packed)
     Bases bs{};
     bs.p[BUF_A] = (char*)A_packed;
     bs.p[BUF_C] = (char*)C_packed;
-    return run_plan(c, b->plan, bs);
+    bool direct = b->prs[0].opts.launch == FFA_LAUNCH_DIRECT || c->prof || b->plan.check_inputs;
+    if (!direct) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        he = hipStreamIsCapturing(c->stream, &cs);
+        if (he != hipSuccess) return dev_fail(c, he);
+        direct = cs != hipStreamCaptureStatusNone;  // the caller's capture records the kernels
+    }
+    if (direct) return run_plan(c, b->plan, bs, b->ws);
+    if (!b->gexec || b->gA != A_packed || b->gC != C_packed) {
+        const int st = capture_graph(b, bs);
+        if (st) return st;
+    }
+    he = hipGraphLaunch(b->gexec, c->stream);
+    return he == hipSuccess ? FFA_OK : dev_fail(c, he);
 }
 
 int ffa_batch_destroy(ffa_batch* b)
@@ -446,9 +600,284 @@ int ffa_batch_destroy(ffa_batch* b)
     if (!b) return FFA_EINVAL;
     (void)hipSetDevice(b->ctx->device);
     (void)hipDeviceSynchronize();
+    drop_graph(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
     free_tables(b->plan);
+    if (b->ws) (void)hipFree(b->ws);
     delete b;
     return FFA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Time of `reps` calls of f on the context's stream (HIP events), after one untimed call.
+template <typename F>
+int time_calls(ffa_ctx* c, int reps, F f, double* ms_out)
+{
+    int st = f();
+    if (st) return st;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return dev_fail(c, hipGetLastError());
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return dev_fail(c, hipGetLastError());
+    }
+    (void)hipEventRecord(e0, c->stream);
+    for (int r = 0; r < reps && st == FFA_OK; ++r) st = f();
+    (void)hipEventRecord(e1, c->stream);
+    float ms = 0.f;
+    hipError_t he = hipEventSynchronize(e1);
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    if (he != hipSuccess) return dev_fail(c, he);
+    *ms_out = ms / reps;
+    return FFA_OK;
+}
+
+// INT8 product-kernel configurations that fit a plan's carrier ({0} for fp64).
+std::vector<int> kernel_candidates(const Plan& pl)
+{
+    std::vector<int> out;
+    if (pl.carrier != CAR_I8) return {0};
+    for (int cfg = 0; cfg < 64; ++cfg)
+        if (gemm_i8_config_valid(cfg, pl.nl, pl.cplx)) out.push_back(cfg + 1);
+    return out;
+}
+
+// Carriers worth timing: INT8 limbs always; FP64 where the problem allows it
+// (real field, p below its limit, bound held) and limbs are needed (p > 255).
+std::vector<int> carrier_candidates(const Problem& base)
+{
+    std::vector<int> out{FFA_CARRIER_INT8};
+    if (base.herm || base.p < 256) return out;
+    Problem q = base;
+    q.opts = default_opts();
+    q.opts.carrier = FFA_CARRIER_F64;
+    q.opts.levels = 0;
+    q.opts.algo = FFA_ALGO_CLASSICAL;
+    if (make_plan(q).status == FFA_OK) out.push_back(FFA_CARRIER_F64);
+    return out;
+}
+
+void record_tuned(ffa_ctx* c, int64_t n, int64_t k, uint32_t p, int herm, int dA, int dC,
+                  const ffa_opts& o)
+{
+    c->tuned[tune_key(n, k, p, herm, dA, dC)] = o;
+    c->tuned[tune_class_key(n, k, p, herm, dA, dC)] = o;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ffa_autotune_syrk(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA, const void* A,
+                      int64_t lda, int dC, void* C, int64_t ldc, int reps, ffa_opts* best,
+                      double* best_ms)
+{
+    if (!ctx || reps <= 0) return FFA_EINVAL;
+    Problem base;
+    base.n = n;
+    base.k = k;
+    base.lda = lda;
+    base.ldc = ldc;
+    base.p = p;
+    base.dA = dA;
+    base.dC = dC;
+    base.opts = default_opts();
+    base.aligned = ((uintptr_t)A % 16) == 0;
+    Plan probe = make_plan(base);
+    if (probe.status) return probe.status;
+    double best_t = 1e30;
+    ffa_opts best_o = default_opts();
+    bool found = false;
+    for (int car : carrier_candidates(base)) {
+        Problem cb = base;
+        cb.opts.carrier = car;
+        const Plan cprobe = make_plan(cb);
+        if (cprobe.status) continue;
+        for (int L = 0; L <= 4; ++L) {
+            if (L > 0 && ((n >> L) < 64 || k == 0)) break;
+            for (int kc : kernel_candidates(cprobe)) {
+                ffa_opts o = default_opts();
+                o.algo = L == 0 ? FFA_ALGO_CLASSICAL : FFA_ALGO_RECURSIVE;
+                o.levels = L;
+                o.kernel = kc;
+                o.carrier = car;
+                Problem pr = base;
+                pr.opts = o;
+                double ms = 0;
+                const int st =
+                    time_calls(ctx, reps, [&] { return run_call(ctx, pr, A, nullptr, C, nullptr); }, &ms);
+                if (st == FFA_EBOUND || st == FFA_EUNSUPPORTED || st == FFA_EINVAL) continue;
+                if (st) return st;
+                if (ms < best_t) {
+                    best_t = ms;
+                    best_o = o;
+                    found = true;
+                }
+            }
+        }
+    }
+    if (!found) return FFA_EUNSUPPORTED;
+    record_tuned(ctx, n, k, p, 0, dA, dC, best_o);
+    if (best) *best = best_o;
+    if (best_ms) *best_ms = best_t;
+    return FFA_OK;
+}
+
+int ffa_batch_autotune(ffa_batch* b, const void* A_packed, void* C_packed, int reps, ffa_opts* best,
+                       double* best_ms)
+{
+    if (!b || reps <= 0) return FFA_EINVAL;
+    ffa_ctx* c = b->ctx;
+    const int64_t cutoffs[] = {0, 256, 384};
+    double best_t = 1e30;
+    ffa_opts best_o = b->prs[0].opts;
+    bool found = false;
+    for (int car : carrier_candidates(b->prs[0])) {
+        std::vector<Problem> cprs = b->prs;
+        for (auto& q : cprs) q.opts.carrier = car;
+        const Plan cprobe = make_batch_plan(cprs);
+        if (cprobe.status) continue;
+        for (int kc : kernel_candidates(cprobe)) {
+            for (int64_t cut : cutoffs) {
+                std::vector<Problem> prs = cprs;
+                for (auto& q : prs) {
+                    q.opts.kernel = kc;
+                    q.opts.cutoff = (int32_t)cut;
+                    q.opts.levels = -1;
+                    q.opts.algo = cut == 0 ? FFA_ALGO_CLASSICAL : FFA_ALGO_AUTO;
+                }
+                ffa_batch trial;
+                trial.ctx = c;
+                trial.prs = prs;
+                trial.plan = make_batch_plan(prs);
+                if (trial.plan.status) continue;
+                if (trial.plan.a_total != b->plan.a_total || trial.plan.c_total != b->plan.c_total) continue;
+                int st = batch_workspace(&trial);
+                if (!st) st = upload_tables(c, trial.plan);
+                double ms = 0;
+                if (!st)
+                    st = time_calls(c, reps, [&] { return ffa_batch_syrk_exec(&trial, A_packed, C_packed); },
+                                    &ms);
+                (void)hipDeviceSynchronize();
+                drop_graph(&trial);
+                if (trial.cap) (void)hipStreamDestroy(trial.cap);
+                trial.cap = nullptr;
+                const bool better = !st && ms < best_t;
+                if (better) {
+                    // the trial's plan, tables and workspace move into the batch
+                    best_t = ms;
+                    best_o = prs[0].opts;
+                    found = true;
+                    drop_graph(b);
+                    free_tables(b->plan);
+                    if (b->ws) (void)hipFree(b->ws);
+                    b->prs = prs;
+                    b->plan = std::move(trial.plan);
+                    b->ws = trial.ws;
+                    b->ws_bytes = trial.ws_bytes;
+                    trial.plan.d_blob = nullptr;
+                    trial.ws = nullptr;
+                } else {
+                    free_tables(trial.plan);
+                    if (trial.ws) (void)hipFree(trial.ws);
+                    trial.ws = nullptr;
+                }
+                if (st) return st;
+            }
+        }
+    }
+    if (!found) return FFA_EUNSUPPORTED;
+    if (best) *best = best_o;
+    if (best_ms) *best_ms = best_t;
+    return FFA_OK;
+}
+
+namespace {
+
+// "key":<integer> inside one record object [p, e); false when missing
+bool json_int(const char* p, const char* e, const char* key, long long* v)
+{
+    char pat[32];
+    snprintf(pat, sizeof(pat), "\"%s\"", key);
+    const size_t m = strlen(pat);
+    for (const char* q = p; q + m <= e; ++q) {
+        if (strncmp(q, pat, m)) continue;
+        q += m;
+        while (q < e && (*q == ' ' || *q == ':' || *q == '\t' || *q == '\n')) ++q;
+        char* end = nullptr;
+        *v = strtoll(q, &end, 10);
+        return end != q && end <= e;
+    }
+    return false;
+}
+
+}  // namespace
+
+int64_t ffa_tune_export(const ffa_ctx* c, char* buf, int64_t size)
+{
+    if (!c) return FFA_EINVAL;
+    std::string s = "{\"arch\":\"" + c->arch + "\",\"records\":[";
+    bool first = true;
+    for (const auto& kv : c->tuned) {
+        if (kv.first.empty() || kv.first[0] == 'c') continue;  // size-class entries follow the exact ones
+        long long n, k;
+        unsigned p;
+        int herm, dA, dC;
+        if (sscanf(kv.first.c_str(), "%lld|%lld|%u|%d|%d|%d", &n, &k, &p, &herm, &dA, &dC) != 6) continue;
+        const ffa_opts& o = kv.second;
+        char rec[320];
+        snprintf(rec, sizeof(rec),
+                 "%s{\"n\":%lld,\"k\":%lld,\"p\":%u,\"herm\":%d,\"dA\":%d,\"dC\":%d,\"algo\":%d,"
+                 "\"levels\":%d,\"cutoff\":%d,\"carrier\":%d,\"kernel\":%d}",
+                 first ? "" : ",", n, k, p, herm, dA, dC, o.algo, o.levels, o.cutoff, o.carrier, o.kernel);
+        s += rec;
+        first = false;
+    }
+    s += "]}";
+    if (buf && size > (int64_t)s.size()) std::memcpy(buf, s.c_str(), s.size() + 1);
+    return (int64_t)s.size();
+}
+
+int ffa_tune_import(ffa_ctx* c, const char* json)
+{
+    if (!c || !json) return FFA_EINVAL;
+    const char* arch = strstr(json, "\"arch\"");
+    const char* recs = strstr(json, "\"records\"");
+    if (!arch || !recs) return FFA_EINVAL;
+    const char* q1 = strchr(arch + 6, '"');
+    const char* q2 = q1 ? strchr(q1 + 1, '"') : nullptr;
+    if (!q2) return FFA_EINVAL;
+    if (std::string(q1 + 1, q2) != c->arch) return 0;
+    const char* p = strchr(recs, '[');
+    if (!p) return FFA_EINVAL;
+    int taken = 0;
+    while ((p = strchr(p, '{')) != nullptr) {
+        const char* e = strchr(p, '}');
+        if (!e) return FFA_EINVAL;
+        long long n, k, pp, herm, dA, dC, algo, levels, cutoff, carrier, kernel;
+        if (!json_int(p, e, "n", &n) || !json_int(p, e, "k", &k) || !json_int(p, e, "p", &pp) ||
+            !json_int(p, e, "herm", &herm) || !json_int(p, e, "dA", &dA) || !json_int(p, e, "dC", &dC) ||
+            !json_int(p, e, "algo", &algo) || !json_int(p, e, "levels", &levels) ||
+            !json_int(p, e, "cutoff", &cutoff) || !json_int(p, e, "carrier", &carrier) ||
+            !json_int(p, e, "kernel", &kernel))
+            return FFA_EINVAL;
+        ffa_opts o = default_opts();
+        o.algo = (int32_t)algo;
+        o.levels = (int32_t)levels;
+        o.cutoff = (int32_t)cutoff;
+        o.carrier = (int32_t)carrier;
+        o.kernel = (int32_t)kernel;
+        record_tuned(c, n, k, (uint32_t)pp, (int)herm, (int)dA, (int)dC, o);
+        ++taken;
+        p = e + 1;
+    }
+    return taken;
 }
 
 int ffa_plan_describe(int64_t n, int64_t k, uint32_t p, int hermitian, int dA, int dC,

@@ -19,7 +19,6 @@
 
 #include <algorithm>
 #include <cstdio>
-#include <cstdlib>
 
 #include "field.h"
 
@@ -371,10 +370,8 @@ void choose_kernel(Plan& pl, int64_t max_dim)
         return;
     }
     int cfg = gemm_i8_default_config(pl.nl, pl.cplx, max_dim);
-    if (const char* e = std::getenv("FFA_I8_CFG")) {
-        const int c = std::atoi(e);
-        if (gemm_i8_config_valid(c, pl.nl, pl.cplx)) cfg = c;
-    }
+    if (pl.kernel_req > 0 && gemm_i8_config_valid(pl.kernel_req - 1, pl.nl, pl.cplx))
+        cfg = pl.kernel_req - 1;
     pl.gemm_cfg = cfg;
     pl.tile = gemm_i8_config_tile(cfg);
     pl.ktile = gemm_i8_config_ktile(cfg);
@@ -412,6 +409,7 @@ Plan make_plan(const Problem& pr)
     pl.levels = choose_levels(pr.n, pr.k, o, pl.carrier, pl.nl, pl.cplx);
     pl.pre.assign(pl.levels, {});
     pl.post.assign(pl.levels, {});
+    pl.kernel_req = o.kernel;
     choose_kernel(pl, pr.n >> pl.levels);
     Builder B = make_builder(pl);
     int st = add_problem(pl, B, pr, pl.levels, true);
@@ -450,6 +448,7 @@ Plan make_batch_plan(const std::vector<Problem>& prs)
     pl.post.assign(maxL, {});
     int64_t maxn = 0;
     for (const auto& q : prs) maxn = std::max(maxn, q.n);
+    pl.kernel_req = p0.opts.kernel;
     choose_kernel(pl, maxn);
     Builder B = make_builder(pl);
     int64_t aoff = 0, coff = 0;

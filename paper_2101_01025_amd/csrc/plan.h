@@ -43,6 +43,7 @@ struct Plan {
     std::vector<GemmTask> gemm;
     int total_tiles = 0;
     int gemm_cfg = 0;                  // INT8 product kernel configuration
+    int kernel_req = 0;                // requested configuration + 1 (0: built-in choice)
     int tile = 0;                      // product tile edge
     int ktile = 0;                     // product k-tile (carrier elements); K is padded to it
     std::vector<TileEnt> sched;         // XCD-balanced tile schedule, one entry per workgroup

@@ -1,0 +1,172 @@
+"""GPU tests of the batched path's launch modes and of the autotuner.
+
+Every result is compared bit-exactly with the CPU oracle.  The graph tests
+replay a captured launch sequence several times, with unrelated eager GPU
+work and synchronisations between replays, and check every replay.
+"""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _ffa():
+    import paper_2101_01025_amd as ffa
+    return ffa
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _u16(a):
+    return torch.from_numpy(np.ascontiguousarray(a).astype(np.int32)).to("cuda").to(torch.uint16)
+
+
+def _host(t):
+    if t.dtype == torch.uint16:
+        t = t.to(torch.int32)
+    return t.cpu().numpy().astype(np.int64)
+
+
+def _batch(count, seed, nmax=300, p=65521, **opts):
+    ffa = _ffa()
+    ns, ks = si.batch_shapes(count, seed, nmin=1, nmax=nmax)
+    mats = si.batch_residues(ns, ks, p, seed)
+    B = ffa.BatchSyrk(ns, ks, p, ffa.U16, ffa.U16, **opts)
+    Ap = np.zeros(B.a_total, dtype=np.int64)
+    for i, M in enumerate(mats):
+        Ap[B.a_off[i]:B.a_off[i] + M.size] = M.ravel()
+    B.ks_host = ks
+    return B, ns, mats, _u16(Ap)
+
+
+def _check_batch(B, ns, mats, Cp, p=65521, upper=None):
+    Ch = _host(Cp)
+    for i, M in enumerate(mats):
+        n = int(ns[i])
+        got = Ch[B.c_off[i]:B.c_off[i] + n * n].reshape(n, n)
+        assert np.array_equal(np.tril(got), oracle.syrk_modp(M, p)), f"problem {i}"
+        if upper is not None:
+            assert np.all(got[np.triu_indices(n, 1)] == upper), f"upper triangle of problem {i}"
+
+
+def _sentinel(total, v=0xBEEF):
+    return torch.full((total,), v, dtype=torch.int32, device="cuda").to(torch.uint16)
+
+
+def _busy_work():
+    x = torch.randn(512, 512, device="cuda")
+    y = (x @ x).sum()
+    torch.cuda.synchronize()
+    return float(y)
+
+
+@pytest.mark.parametrize("levels", [0, 1])
+def test_batch_graph_replays_and_buffer_changes(levels):
+    """Default launch mode (captured hipGraph): repeated calls on one buffer pair,
+    then on another pair (re-capture), then back; each result checked."""
+    ffa = _ffa()
+    _say("batch graph", levels)
+    B, ns, mats, A = _batch(20, 301, levels=levels)
+    C1, C2 = _sentinel(B.c_total), _sentinel(B.c_total)
+    for C in (C1, C1, C2, C1, C2):
+        B.run(A, C)
+        torch.cuda.synchronize()
+        _check_batch(B, ns, mats, C, upper=0xBEEF)
+        _busy_work()
+    B.close()
+
+
+def test_batch_direct_and_graph_agree():
+    ffa = _ffa()
+    _say("batch direct vs graph")
+    Bg, ns, mats, A = _batch(16, 302, levels=1)
+    Bd = ffa.BatchSyrk(ns, Bg.ks_host, 65521, ffa.U16, ffa.U16, levels=1, launch=ffa.LAUNCH_DIRECT)
+    Cg, Cd = _sentinel(Bg.c_total), _sentinel(Bd.c_total)
+    Bg.run(A, Cg)
+    Bd.run(A, Cd)
+    torch.cuda.synchronize()
+    assert torch.equal(Cg, Cd)
+    _check_batch(Bg, ns, mats, Cg)
+    Bg.close()
+    Bd.close()
+
+
+def test_batch_inside_torch_graph_capture():
+    """The caller captures the batched call into its own graph: the kernels join
+    that graph.  Replays are checked one by one, with C cleared eagerly between."""
+    ffa = _ffa()
+    _say("batch in torch graph")
+    B, ns, mats, A = _batch(12, 303, levels=1)
+    C = _sentinel(B.c_total)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        B.run(A, C)  # warm-up outside capture (first launches set kernel attributes)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    _check_batch(B, ns, mats, C)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        B.run(A, C)
+    for rep in range(3):
+        C.copy_(_sentinel(B.c_total, 0x0101 + rep))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _check_batch(B, ns, mats, C, upper=0x0101 + rep)
+        _busy_work()
+    del g
+    B.close()
+
+
+def test_batch_autotune_keeps_results_exact():
+    ffa = _ffa()
+    _say("batch autotune")
+    B, ns, mats, A = _batch(24, 304)
+    C = _sentinel(B.c_total)
+    best, ms = B.autotune(A, C, reps=1)
+    assert ms > 0
+    assert best.carrier in (ffa.CARRIER_INT8, ffa.CARRIER_F64)
+    torch.cuda.synchronize()
+    _check_batch(B, ns, mats, C)
+    C2 = _sentinel(B.c_total)
+    B.run(A, C2)
+    torch.cuda.synchronize()
+    _check_batch(B, ns, mats, C2, upper=0xBEEF)
+    B.close()
+
+
+@pytest.mark.parametrize("p,n,k,dt", [(251, 1000, 700, "u8"), (65521, 600, 500, "u16")])
+def test_autotune_syrk_and_tuned_default(p, n, k, dt):
+    ffa = _ffa()
+    _say("autotune", p, n, k)
+    Ares = si.uniform_residues(n, k, p, 305)
+    if dt == "u8":
+        A = torch.from_numpy(Ares.astype(np.uint8)).to("cuda")
+    else:
+        A = _u16(Ares)
+    exp = oracle.syrk_modp(Ares, p)
+    best, ms = ffa.autotune_syrk(A, p, reps=1)
+    assert ms > 0 and 0 <= best.levels <= 4
+    # no options: the tuned choice for this shape
+    C = ffa.syrk_modp(A, p)
+    torch.cuda.synchronize()
+    assert np.array_equal(np.tril(_host(C)), exp)
+    rec = json.loads(ffa.tune_export())
+    assert rec["arch"].startswith("gfx")
+    mine = [r for r in rec["records"] if (r["n"], r["k"], r["p"]) == (n, k, p)]
+    assert mine and mine[0]["levels"] == best.levels and mine[0]["kernel"] == best.kernel
+    assert ffa.tune_import(json.dumps(rec)) == len(rec["records"])
+    # a shape of the same size class without a record of its own uses the class record
+    A2 = A[: n - 3, : k - 5].contiguous()
+    C2 = ffa.syrk_modp(A2, p)
+    torch.cuda.synchronize()
+    assert np.array_equal(np.tril(_host(C2)), oracle.syrk_modp(Ares[: n - 3, : k - 5], p))

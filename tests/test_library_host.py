@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_symbols():
     src = open(os.path.join(ROOT, "include", "ffa.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(ffa_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(ffa_\w+)\s*\(", src, re.M)))
 
 
 def test_library_exports_every_declared_symbol():

@@ -211,6 +211,22 @@ def test_freivalds_accepts_correct_and_rejects_planted_error():
     assert caught >= 1
 
 
+def test_hermitian_freivalds_accepts_and_rejects():
+    p = 65519
+    Ar, Ai = si.complex_residues(30, 17, p, 8)
+    Cr, Ci = oracle.herk_modp2(Ar, Ai, p)
+    rng = np.random.default_rng(6)
+    for _ in range(3):
+        xr, xi = rng.integers(0, p, 30), rng.integers(0, p, 30)
+        yc, ya = oracle.freivalds_herk(Ar, Ai, Cr, Ci, p, xr, xi)
+        assert np.array_equal(yc[0], ya[0]) and np.array_equal(yc[1], ya[1])
+    Bad = Ci.copy()
+    Bad[20, 7] = (Bad[20, 7] + 1) % p
+    xr, xi = rng.integers(0, p, 30), rng.integers(0, p, 30)
+    yc, ya = oracle.freivalds_herk(Ar, Ai, Cr, Bad, p, xr, xi)
+    assert not (np.array_equal(yc[0], ya[0]) and np.array_equal(yc[1], ya[1]))
+
+
 def test_entries_match_full():
     p = 65521
     A = si.uniform_residues(30, 21, p, 9)
