@@ -77,8 +77,19 @@ enum { FFA_CARRIER_AUTO = 0, FFA_CARRIER_INT8 = 1, FFA_CARRIER_F64 = 2 };
  *                 0 = built-in choice; a configuration that does not fit the carrier is ignored
  *   launch        batched execution only: FFA_LAUNCH_GRAPH (default) replays the plan's
  *                 launch sequence as one captured hipGraph; FFA_LAUNCH_DIRECT enqueues
- *                 the kernels one by one */
+ *                 the kernels one by one
+ *   operands      FFA_OPERANDS_AUTO: limb planes prepared by a conditioning pass, except
+ *                 where those planes would not be addressable with 32-bit offsets;
+ *                 FFA_OPERANDS_PLANES: always; FFA_OPERANDS_RAW: without recursion and
+ *                 with uint16 input in 16-byte aligned rows, the product kernel reads A
+ *                 itself and forms the limbs on the fly (else ignored)
+ *   streams       FFA_STREAMS_AUTO / FFA_STREAMS_TWO: with recursion, the pre-additions
+ *                 and the products that need them run on a second stream of the context
+ *                 while the products that read only A run on the caller's stream (joined
+ *                 before the post-additions); FFA_STREAMS_ONE: everything in stream order */
 enum { FFA_LAUNCH_GRAPH = 0, FFA_LAUNCH_DIRECT = 1 };
+enum { FFA_OPERANDS_AUTO = 0, FFA_OPERANDS_PLANES = 1, FFA_OPERANDS_RAW = 2 };
+enum { FFA_STREAMS_AUTO = 0, FFA_STREAMS_ONE = 1, FFA_STREAMS_TWO = 2 };
 typedef struct {
     int32_t algo;
     int32_t levels;
@@ -87,7 +98,9 @@ typedef struct {
     int32_t check_inputs;
     int32_t kernel;
     int32_t launch;
-    int32_t reserved;
+    int32_t operands;
+    int32_t streams;
+    int32_t reserved[3];
 } ffa_opts;
 
 /* Context bound to a HIP device and stream (stream NULL = the null stream).
@@ -123,9 +136,10 @@ int ffa_herk_modp2(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA,
                    int dC, void* C_re, void* C_im, int64_t ldc, const ffa_opts* opts);
 
 /* Batched C_i = Low(A_i A_i^T) mod p for independent problems (one p).
- * Problems use a PACKED layout: A_i starts at element a_off[i] of one buffer with
- * lda = k_i, C_i at element c_off[i] of another with ldc = n_i; the offsets are
- * fixed by the plan (ffa_batch_offsets); both buffers must be 16-byte aligned.
+ * Problems use a PACKED layout fixed by the plan (ffa_batch_offsets): A_i starts
+ * at element a_off[i] of one buffer with row stride lda[i] = k_i rounded up to 16
+ * bytes (the padding columns are never read), C_i at element c_off[i] of another
+ * with ldc = n_i; both buffers must be 16-byte aligned.
  * The plan (host work: tables, its own device workspace) is made once and owns
  * that workspace, so later single calls on the context never move it.
  * ffa_batch_syrk_exec allocates nothing.  With opts.launch = FFA_LAUNCH_GRAPH it
@@ -137,10 +151,13 @@ int ffa_herk_modp2(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA,
  * graph).  One plan must not be executed from two threads at once. */
 int ffa_batch_syrk_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int64_t* k,
                         uint32_t p, int dA, int dC, const ffa_opts* opts, ffa_batch** out);
-int ffa_batch_offsets(const ffa_batch* b, int64_t* a_off, int64_t* c_off,
+int ffa_batch_offsets(const ffa_batch* b, int64_t* a_off, int64_t* lda, int64_t* c_off,
                       int64_t* a_total, int64_t* c_total);
 int ffa_batch_syrk_exec(ffa_batch* b, const void* A_packed, void* C_packed);
 int ffa_batch_destroy(ffa_batch* b);
+/* The batch plan as JSON (the fields of ffa_plan_describe, summed or maximal over
+ * the problems: levels is the deepest recursion, macs the total per limb product). */
+int ffa_batch_describe(const ffa_batch* b, char* buf, int64_t size);
 
 /* Phase timing with HIP events recorded on the context's stream around each
  * phase of every later call: 0 = conditioning, 1 = pre-additions (all levels),

@@ -20,6 +20,8 @@ I64, I32, U16, U8, F64, I8_CENTRED = 0, 1, 2, 3, 4, 5
 ALGO_AUTO, ALGO_CLASSICAL, ALGO_RECURSIVE = 0, 1, 2
 CARRIER_AUTO, CARRIER_INT8, CARRIER_F64 = 0, 1, 2
 LAUNCH_GRAPH, LAUNCH_DIRECT = 0, 1
+OPERANDS_AUTO, OPERANDS_PLANES, OPERANDS_RAW = 0, 1, 2
+STREAMS_AUTO, STREAMS_ONE, STREAMS_TWO = 0, 1, 2
 
 SYMBOLS = [
     "ffa_create", "ffa_destroy", "ffa_set_stream", "ffa_last_device_error", "ffa_status_string",
@@ -27,6 +29,7 @@ SYMBOLS = [
     "ffa_batch_offsets", "ffa_batch_syrk_exec", "ffa_batch_destroy", "ffa_plan_describe",
     "ffa_profile_enable", "ffa_profile_read", "ffa_profile_reset",
     "ffa_autotune_syrk", "ffa_batch_autotune", "ffa_tune_export", "ffa_tune_import",
+    "ffa_batch_describe",
 ]
 PHASE_COND, PHASE_PRE, PHASE_PRODUCTS, PHASE_POST = 0, 1, 2, 3
 
@@ -40,15 +43,17 @@ class FfaError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("levels", ctypes.c_int32), ("cutoff", ctypes.c_int32),
                 ("carrier", ctypes.c_int32), ("check_inputs", ctypes.c_int32),
-                ("kernel", ctypes.c_int32), ("launch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("kernel", ctypes.c_int32), ("launch", ctypes.c_int32), ("operands", ctypes.c_int32),
+                ("streams", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 def make_opts(algo=ALGO_AUTO, levels=-1, cutoff=0, carrier=CARRIER_AUTO, check_inputs=False,
-              kernel=0, launch=LAUNCH_GRAPH):
-    return Opts(algo, levels, cutoff, carrier, int(bool(check_inputs)), kernel, launch)
+              kernel=0, launch=LAUNCH_GRAPH, operands=OPERANDS_AUTO, streams=STREAMS_AUTO):
+    return Opts(algo, levels, cutoff, carrier, int(bool(check_inputs)), kernel, launch, operands,
+                streams)
 
 
 _lib = None
@@ -73,7 +78,7 @@ def lib():
         L.ffa_syrk_modp.argtypes = [P, i64, i64, u32, i32, P, i64, i32, P, i64, P]
         L.ffa_herk_modp2.argtypes = [P, i64, i64, u32, i32, P, P, i64, i32, P, P, i64, P]
         L.ffa_batch_syrk_plan.argtypes = [P, i64, P, P, u32, i32, i32, P, ctypes.POINTER(P)]
-        L.ffa_batch_offsets.argtypes = [P, P, P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.ffa_batch_offsets.argtypes = [P, P, P, P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.ffa_batch_syrk_exec.argtypes = [P, P, P]
         L.ffa_batch_destroy.argtypes = [P]
         L.ffa_profile_enable.argtypes = [P, i32]
@@ -82,6 +87,7 @@ def lib():
         L.ffa_autotune_syrk.argtypes = [P, i64, i64, u32, i32, P, i64, i32, P, i64, i32, P,
                                          ctypes.POINTER(ctypes.c_double)]
         L.ffa_batch_autotune.argtypes = [P, P, P, i32, P, ctypes.POINTER(ctypes.c_double)]
+        L.ffa_batch_describe.argtypes = [P, ctypes.c_char_p, i64]
         L.ffa_tune_export.argtypes = [P, ctypes.c_char_p, i64]
         L.ffa_tune_export.restype = i64
         L.ffa_tune_import.argtypes = [P, ctypes.c_char_p]
@@ -283,11 +289,26 @@ class BatchSyrk:
                                          ctypes.byref(h)), "batch plan")
         self.handle = h
         self.a_off = np.zeros(self.count, np.int64)
+        self.lda = np.zeros(self.count, np.int64)
         self.c_off = np.zeros(self.count, np.int64)
         at, ct = ctypes.c_int64(), ctypes.c_int64()
-        _check(lib().ffa_batch_offsets(h, self.a_off.ctypes.data, self.c_off.ctypes.data,
-                                       ctypes.byref(at), ctypes.byref(ct)))
+        _check(lib().ffa_batch_offsets(h, self.a_off.ctypes.data, self.lda.ctypes.data,
+                                       self.c_off.ctypes.data, ctypes.byref(at), ctypes.byref(ct)))
         self.a_total, self.c_total = at.value, ct.value
+
+    def pack(self, mats, dtype=None):
+        """Host array of the packed A layout holding mats[i] (n_i x k_i each);
+        padding columns are zero."""
+        import numpy as np
+        out = np.zeros(self.a_total, dtype=dtype or np.asarray(mats[0]).dtype)
+        for i, M in enumerate(mats):
+            n, k = int(self.ns[i]), int(self.ks[i])
+            if n == 0:
+                continue
+            ld = int(self.lda[i])
+            view = out[self.a_off[i]:self.a_off[i] + n * ld].reshape(n, ld)
+            view[:, :k] = M
+        return out
 
     def run(self, A_packed, C_packed):
         torch = _torch()
@@ -305,6 +326,11 @@ class BatchSyrk:
                                         ctypes.c_void_p(C_packed.data_ptr()), reps,
                                         ctypes.byref(best), ctypes.byref(ms)), "batch autotune")
         return best, ms.value
+
+    def describe(self):
+        buf = ctypes.create_string_buffer(4096)
+        _check(lib().ffa_batch_describe(self.handle, buf, 4096), "batch describe")
+        return json.loads(buf.value.decode())
 
     def close(self):
         if self.handle:

@@ -19,6 +19,10 @@ using namespace ffa;
 struct ffa_ctx {
     int device = 0;
     std::string arch;  // gcnArchName up to the first ':'
+    // second stream for the pre-additions and the products that need them, and
+    // the events that fork it from and join it back to the caller's stream
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
     hipStream_t stream = nullptr;
     char* ws = nullptr;
@@ -130,20 +134,20 @@ hipEvent_t take_event(ffa_ctx* c)
 }
 
 // Records the start event of a phase (no-op when profiling is off).
-hipEvent_t phase_begin(ffa_ctx* c)
+hipEvent_t phase_begin(ffa_ctx* c, hipStream_t s)
 {
     if (!c->prof) return nullptr;
     hipEvent_t e = take_event(c);
-    if (e) (void)hipEventRecord(e, c->stream);
+    if (e) (void)hipEventRecord(e, s);
     return e;
 }
 
-void phase_end(ffa_ctx* c, hipEvent_t start, int phase)
+void phase_end(ffa_ctx* c, hipStream_t s, hipEvent_t start, int phase)
 {
     if (!c->prof || !start) return;
     hipEvent_t e = take_event(c);
     if (!e) return;
-    (void)hipEventRecord(e, c->stream);
+    (void)hipEventRecord(e, s);
     c->pending.push_back({start, e, phase});
 }
 
@@ -206,48 +210,70 @@ void free_tables(Plan& pl)
 // The launch sequence: conditioning, pre-additions (top-down), all products in
 // one grouped launch, post-additions (bottom-up).
 // The workspace (at least pl.ws_bytes) and the uploaded tables are the caller's
-// to provide.
+// to provide.  With pl.fork the pre-additions and the second product group run
+// on the context's second stream, forked from the caller's stream after the
+// conditioning and joined back before the post-additions; the first product
+// group (products that read only A) runs on the caller's stream meanwhile.
 int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws)
 {
     b.p[BUF_WS] = ws;
     char* blob = (char*)pl.d_blob;
-    void* s = (void*)c->stream;
+    hipStream_t ms = c->stream;
+    void* s = (void*)ms;
     int e;
     if (!pl.cond.empty()) {
         if (pl.check_inputs && (e = launch_zero_flag(c->d_err, s))) return dev_fail(c, e);
-        hipEvent_t ev = phase_begin(c);
+        hipEvent_t ev = phase_begin(c, ms);
         e = launch_condition((const CondTask*)(blob + pl.off_cond), (int)pl.cond.size(),
                              pl.cond_max_blocks, pl.cond[0].dt_in, b, pl.fp, pl.carrier, c->d_err, s);
         if (e) return dev_fail(c, e);
-        phase_end(c, ev, 0);
+        phase_end(c, ms, ev, 0);
         if (pl.check_inputs) {
             int32_t h_err = 0;
             hipError_t he = hipMemcpyAsync(&h_err, c->d_err, sizeof(int32_t),
-                                           hipMemcpyDeviceToHost, c->stream);
-            if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+                                           hipMemcpyDeviceToHost, ms);
+            if (he == hipSuccess) he = hipStreamSynchronize(ms);
             if (he != hipSuccess) return dev_fail(c, he);
             if (h_err) return FFA_ERANGE;
         }
     }
-    hipEvent_t ev = pl.levels > 0 ? phase_begin(c) : nullptr;
+    const bool fork = pl.fork && !pl.sched2.empty();
+    hipStream_t ps = fork ? c->aux : ms;  // stream of the pre-additions
+    if (fork) {
+        hipError_t he = hipEventRecord(c->ev_fork, ms);
+        if (he == hipSuccess) he = hipStreamWaitEvent(ps, c->ev_fork, 0);
+        if (he != hipSuccess) return dev_fail(c, he);
+    }
+    const GemmTask* g = (const GemmTask*)(blob + pl.off_gemm);
+    auto products = [&](hipStream_t st, int64_t off, size_t nsched) -> int {
+        if (nsched == 0) return 0;
+        hipEvent_t pev = phase_begin(c, st);
+        const TileEnt* sc = (const TileEnt*)(blob + off);
+        const int r = pl.carrier == CAR_F64
+                          ? launch_gemm_f64(g, sc, (int)nsched, b, pl.fp, (void*)st)
+                          : launch_gemm_i8(pl.gemm_cfg, pl.gemm_src, g, sc, (int)nsched, b, pl.fp, (void*)st);
+        phase_end(c, st, pev, 2);
+        return r;
+    };
+    hipEvent_t ev = pl.levels > 0 ? phase_begin(c, ps) : nullptr;
     for (int l = 0; l < pl.levels; ++l) {
         if (pl.pre[l].empty()) continue;
         e = launch_preadd((const PreaddTask*)(blob + pl.off_pre[l]), (int)pl.pre[l].size(),
-                          pl.pre_max_h[l], pl.pre_max_w[l], b, pl.fp, pl.carrier, s);
+                          pl.pre_max_h[l], pl.pre_max_w[l], b, pl.fp, pl.carrier, (void*)ps);
         if (e) return dev_fail(c, e);
     }
-    phase_end(c, ev, 1);
-    if (!pl.gemm.empty()) {
-        ev = phase_begin(c);
-        const GemmTask* g = (const GemmTask*)(blob + pl.off_gemm);
-        const TileEnt* sc = (const TileEnt*)(blob + pl.off_sched);
-        const int nb = (int)pl.sched.size();
-        e = pl.carrier == CAR_F64 ? launch_gemm_f64(g, sc, nb, b, pl.fp, s)
-                                  : launch_gemm_i8(pl.gemm_cfg, g, sc, nb, b, pl.fp, s);
-        if (e) return dev_fail(c, e);
-        phase_end(c, ev, 2);
+    phase_end(c, ps, ev, 1);
+    if (fork) {
+        if ((e = products(ps, pl.off_sched2, pl.sched2.size()))) return dev_fail(c, e);
+        hipError_t he = hipEventRecord(c->ev_join, ps);
+        if (he != hipSuccess) return dev_fail(c, he);
     }
-    ev = pl.levels > 0 ? phase_begin(c) : nullptr;
+    if ((e = products(ms, pl.off_sched, pl.sched.size()))) return dev_fail(c, e);
+    if (fork) {
+        hipError_t he = hipStreamWaitEvent(ms, c->ev_join, 0);
+        if (he != hipSuccess) return dev_fail(c, he);
+    }
+    ev = pl.levels > 0 ? phase_begin(c, ms) : nullptr;
     for (int l = pl.levels - 1; l >= 0; --l) {
         if (pl.post[l].empty()) continue;
         // every task of a level writes the same format: the caller's C at level 0,
@@ -256,7 +282,7 @@ int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws)
                            pl.post_max_h[l], pl.post[l][0].c.dt, b, pl.fp, s);
         if (e) return dev_fail(c, e);
     }
-    phase_end(c, ev, 3);
+    phase_end(c, ms, ev, 3);
     return FFA_OK;
 }
 
@@ -396,7 +422,13 @@ int ffa_create(ffa_ctx** out, int device, void* hip_stream)
     }
     hipError_t e = hipSetDevice(device);
     if (e == hipSuccess) e = hipMalloc((void**)&c->d_err, 256);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
     if (e != hipSuccess) {
+        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+        if (c->aux) (void)hipStreamDestroy(c->aux);
+        if (c->d_err) (void)hipFree(c->d_err);
         delete c;
         return FFA_EDEVICE;
     }
@@ -414,6 +446,9 @@ int ffa_destroy(ffa_ctx* c)
     for (auto& kv : c->cache) free_tables(*kv.second);
     if (c->ws) (void)hipFree(c->ws);
     if (c->d_err) (void)hipFree(c->d_err);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
     delete c;
     return FFA_OK;
 }
@@ -557,12 +592,13 @@ int ffa_batch_syrk_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int
     return FFA_OK;
 }
 
-int ffa_batch_offsets(const ffa_batch* b, int64_t* a_off, int64_t* c_off, int64_t* a_total,
-                      int64_t* c_total)
+int ffa_batch_offsets(const ffa_batch* b, int64_t* a_off, int64_t* lda, int64_t* c_off,
+                      int64_t* a_total, int64_t* c_total)
 {
     if (!b) return FFA_EINVAL;
     const size_t cnt = b->plan.a_off.size();
     if (a_off) std::memcpy(a_off, b->plan.a_off.data(), cnt * sizeof(int64_t));
+    if (lda) std::memcpy(lda, b->plan.a_ld.data(), cnt * sizeof(int64_t));
     if (c_off) std::memcpy(c_off, b->plan.c_off.data(), cnt * sizeof(int64_t));
     if (a_total) *a_total = b->plan.a_total;
     if (c_total) *c_total = b->plan.c_total;
@@ -593,6 +629,18 @@ int ffa_batch_syrk_exec(ffa_batch* b, const void* A_packed, void* C_packed)
     }
     he = hipGraphLaunch(b->gexec, c->stream);
     return he == hipSuccess ? FFA_OK : dev_fail(c, he);
+}
+
+int ffa_batch_describe(const ffa_batch* b, char* buf, int64_t size)
+{
+    if (!b) return FFA_EINVAL;
+    if (buf && size > 0) {
+        const std::string d = describe(b->plan);
+        const size_t m = std::min<size_t>(d.size(), (size_t)size - 1);
+        std::memcpy(buf, d.data(), m);
+        buf[m] = 0;
+    }
+    return FFA_OK;
 }
 
 int ffa_batch_destroy(ffa_batch* b)

@@ -121,13 +121,24 @@ struct PostaddTask {
 };
 
 // One product C = X * phi(Z) restricted to tiles; syrk: X == Z, only the
-// lower triangle (row >= col) is produced.
+// lower triangle (row >= col) is produced.  With raw operands (the caller's
+// canonical uint16 residues, split into limbs by the product kernel) x and z
+// point at the caller's matrix, ld is its row stride in bytes and the columns
+// kvalid .. K-1 are treated as zero.
 struct GemmTask {
     CarRef x, z;
     ResRef c;
     int32_t M, N, K;       // K in carrier elements, a multiple of the k-tile
     int32_t syrk;
     int32_t tiles_m, tiles_n;
+    int32_t kvalid;        // columns of the operands that hold data (K for carriers)
+    int32_t pad_;
+};
+
+// Operand source of a product launch (every task of a launch shares it).
+enum GemmSrc : int32_t {
+    SRC_CARRIER = 0,  // carrier planes prepared by conditioning / pre-additions
+    SRC_RAW_U16 = 1,  // the caller's canonical uint16 residues (two limbs, real field)
 };
 
 // One entry of a product launch's schedule: x = task index (-1: idle entry),
@@ -159,7 +170,7 @@ int launch_postadd(const PostaddTask* d_tasks, int ntasks, int h, int out_dt, co
                    const FieldParams& fp, void* stream);
 // Product launches read the task table and a schedule: entry blockIdx = (task,
 // tile row | tile column << 16), or task = -1 for an idle padding entry.
-int launch_gemm_i8(int cfg, const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks,
+int launch_gemm_i8(int cfg, int src, const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks,
                    const Bases& b, const FieldParams& fp, void* stream);
 int launch_gemm_f64(const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks, const Bases& b,
                     const FieldParams& fp, void* stream);

@@ -15,6 +15,16 @@
 // -re:  Re(X Z^H) = Xr Zr^T + Xi Zi^T,  Im(X Z^H) = Xi Zr^T + (-Xr) Zi^T, i.e.
 // two K-segments that share the B operand (Zr, then Zi) and two A roles.
 //
+// Raw operands: when the products read the caller's canonical uint16 residues
+// directly (no recursion, two limbs), each 16-byte load brings 8 residues c
+// and the limbs are formed between the registers and LDS in offset binary:
+// r = c - D with D = 32896 = 128 * 257 has limbs (c >> 8) - 128 and
+// (c & 255) - 128, i.e. the two bytes of c with their top bit flipped.  With
+// s_i = sum_t c_it (row sums over the padded K, taken on the same loads),
+//   sum_t c_it c_jt = sum_t r_it r_jt + D (s_i + s_j) - K D^2,
+// exact in the fp64 epilogue.  Columns at or past the valid width are never read
+// (the last chunk of a row is read element by element) and enter as c = 0.
+//
 // Data movement: global -> registers (a ring of PF k-tiles in flight) -> LDS
 // (double buffer, XOR-swizzled 16-byte segments so that the ds_read_b128 of
 // consecutive rows hits distinct banks) -> MFMA.  Which tile a workgroup
@@ -41,18 +51,6 @@ __device__ __forceinline__ int swz(int r, int seg)
     return r * KT + ((seg ^ ((r / RPB) & (NSEG - 1))) << 4);
 }
 
-// Canonical residue of an int32 for any odd p < 2^16 (|x| < 2^31 - 2^16).
-__device__ __forceinline__ int32_t mod_i32(int32_t x, int32_t p, float inv_p)
-{
-    int32_t q = (int32_t)floorf((float)x * inv_p);
-    int32_t r = (int32_t)((uint32_t)x - (uint32_t)q * (uint32_t)p);
-    q = (int32_t)floorf((float)r * inv_p);
-    r -= q * p;
-    r += (r < 0) ? p : 0;
-    r -= (r >= p) ? p : 0;
-    return r;
-}
-
 // Canonical residue of an int32 for p < 2^8 with full-rate 24-bit arithmetic:
 // x = hi 2^16 + lo, v = hi (2^16 mod p) + lo has |v| < 2^24 (exact in fp32), one
 // fp32 quotient within one of v / p, then a correction.  c16 = 2^16 mod p.
@@ -67,11 +65,54 @@ __device__ __forceinline__ int32_t mod_small_p(int32_t x, int32_t p, int32_t c16
     return r;
 }
 
-template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF>
+// The first lim (1 <= lim < 8) uint16 elements at byte offset off, element by
+// element (the row ends inside this chunk), the rest zero.
+__device__ __forceinline__ v4i load_u16_partial(__amdgpu_buffer_rsrc_t rs, int off, int lim)
+{
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int e = 0; e < 7; ++e)
+        if (e < lim)
+            w[e >> 1] |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rs, off + 2 * e, 0, 0)
+                         << (16 * (e & 1));
+    return v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+}
+
+// Offset-binary limbs of 8 uint16 values: high limbs into hi (8 bytes), low
+// limbs into lo, element e at byte e.
+__device__ __forceinline__ void split_u16x8(v4i v, int2& hi, int2& lo)
+{
+    const uint32_t x0 = (uint32_t)v[0] ^ 0x80808080u, x1 = (uint32_t)v[1] ^ 0x80808080u;
+    const uint32_t x2 = (uint32_t)v[2] ^ 0x80808080u, x3 = (uint32_t)v[3] ^ 0x80808080u;
+    // v_perm_b32 selects bytes of the pair {second operand: bytes 0..3, first: 4..7}
+    hi.x = (int)__builtin_amdgcn_perm(x1, x0, 0x07050301u);
+    hi.y = (int)__builtin_amdgcn_perm(x3, x2, 0x07050301u);
+    lo.x = (int)__builtin_amdgcn_perm(x1, x0, 0x06040200u);
+    lo.y = (int)__builtin_amdgcn_perm(x3, x2, 0x06040200u);
+}
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// acc + the sum of the 8 uint16 values of a chunk.
+__device__ __forceinline__ uint32_t sum_u16x8(v4i v, uint32_t acc)
+{
+    const u16x2 one = {1, 1};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        // through a scalar: a bit_cast of the vector element itself read element 0
+        const uint32_t w = (uint32_t)v[j];
+        acc = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, w), one, acc, false);
+    }
+    return acc;
+}
+
+template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC>
 __global__ void __launch_bounds__(WGM* WGN * 64)
     gemm_i8(Bases bases, const GemmTask* __restrict__ tasks, const TileEnt* __restrict__ sched,
             FieldParams fp)
 {
+    constexpr bool RAW = SRC == SRC_RAW_U16;
+    static_assert(!RAW || (NL == 2 && !CPLX), "raw uint16 operands feed two limbs of a real field");
     constexpr int NT = WGM * WGN * 64;
     constexpr int NROLE = CPLX ? 2 : 1;
     constexpr int NSEG = CPLX ? 2 : 1;
@@ -82,7 +123,8 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     constexpr int NACC = NL == 1 ? 1 : 3;
     constexpr int TILE = BT * KT;
     constexpr int STAGE = (NA + NB) * TILE;
-    constexpr int SPR = KT / 16;  // 16-byte segments per row
+    constexpr int SPR = KT / 16;  // 16-byte segments per carrier row
+    constexpr int RPR = KT / 8;   // 16-byte raw chunks (8 residues) per row
     constexpr int ACH = NA * TILE / 16 / NT;
     constexpr int BCH = NB * TILE / 16 / NT;
     static_assert(NA * TILE % (16 * NT) == 0 && NB * TILE % (16 * NT) == 0, "chunking");
@@ -110,19 +152,40 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     const __amdgpu_buffer_rsrc_t rsa = __builtin_amdgcn_make_buffer_rsrc((void*)abase, (short)0, ext_a, 0x00020000);
     const __amdgpu_buffer_rsrc_t rsb = __builtin_amdgcn_make_buffer_rsrc((void*)bbase, (short)0, ext_b, 0x00020000);
     int aoff[ACH], boff[BCH], alds[ACH], blds[BCH];
+    int acol[RAW ? ACH : 1], bcol[RAW ? BCH : 1];  // raw: first column of the chunk in a k-tile
+    uint32_t asum[RAW ? ACH : 1], bsum[RAW ? BCH : 1];  // raw: partial row sums of the chunks
+#pragma unroll
+    for (int i = 0; i < (RAW ? ACH : 1); ++i) asum[i] = 0;
+#pragma unroll
+    for (int i = 0; i < (RAW ? BCH : 1); ++i) bsum[i] = 0;
 #pragma unroll
     for (int i = 0; i < ACH; ++i) {
         const int c = tid + i * NT;
-        const int sub = c / (BT * SPR), r = (c / SPR) % BT, s = c % SPR;
-        aoff[i] = (int)(sub * T.x.ps + (int64_t)min(r, rows_a - 1) * T.x.ld) + s * 16;
-        alds[i] = sub * TILE + swz<KT>(r, s);
+        if (RAW) {
+            // (row, chunk) -> hi limb at sub-tile 0, lo limb at sub-tile 1, 8 bytes each
+            const int r = c / RPR, s = c % RPR;
+            aoff[i] = min(r, rows_a - 1) * T.x.ld + s * 16;
+            alds[i] = swz<KT>(r, s >> 1) + (s & 1) * 8;
+            acol[i] = s * 8;
+        } else {
+            const int sub = c / (BT * SPR), r = (c / SPR) % BT, s = c % SPR;
+            aoff[i] = (int)(sub * T.x.ps + (int64_t)min(r, rows_a - 1) * T.x.ld) + s * 16;
+            alds[i] = sub * TILE + swz<KT>(r, s);
+        }
     }
 #pragma unroll
     for (int i = 0; i < BCH; ++i) {
         const int c = tid + i * NT;
-        const int sub = c / (BT * SPR), r = (c / SPR) % BT, s = c % SPR;
-        boff[i] = (int)(sub * T.z.ps + (int64_t)min(r, rows_b - 1) * T.z.ld) + s * 16;
-        blds[i] = (NA + sub) * TILE + swz<KT>(r, s);
+        if (RAW) {
+            const int r = c / RPR, s = c % RPR;
+            boff[i] = min(r, rows_b - 1) * T.z.ld + s * 16;
+            blds[i] = NA * TILE + swz<KT>(r, s >> 1) + (s & 1) * 8;
+            bcol[i] = s * 8;
+        } else {
+            const int sub = c / (BT * SPR), r = (c / SPR) % BT, s = c % SPR;
+            boff[i] = (int)(sub * T.z.ps + (int64_t)min(r, rows_b - 1) * T.z.ld) + s * 16;
+            blds[i] = (NA + sub) * TILE + swz<KT>(r, s);
+        }
     }
     // Complex: A sub-tile index sub = role * NL + limb reads plane role (segment 0) and
     // plane role + 1 (segment 1); B reads plane 0 then plane 1.
@@ -131,7 +194,30 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     const int seg_a = (int)(NL * T.x.ps), seg_b = (int)(NL * T.z.ps);
 
     v4i ra[PF][ACH], rb[PF][BCH];
+    const int kvalid = T.kvalid;
     auto gload = [&](int st, v4i* a, v4i* b) {
+        if (RAW) {
+            // only chunks holding valid columns are read (the whole offset in the
+            // per-thread register); the tail of a partial chunk is zeroed
+            const int kb = st * KT;
+#pragma unroll
+            for (int i = 0; i < ACH; ++i) {
+                const int lim = kvalid - kb - acol[i];
+                v4i v = {0, 0, 0, 0};
+                if (lim >= 8) v = __builtin_amdgcn_raw_buffer_load_b128(rsa, aoff[i] + 2 * kb, 0, 0);
+                else if (lim > 0) v = load_u16_partial(rsa, aoff[i] + 2 * kb, lim);
+                a[i] = v;
+            }
+#pragma unroll
+            for (int i = 0; i < BCH; ++i) {
+                const int lim = kvalid - kb - bcol[i];
+                v4i v = {0, 0, 0, 0};
+                if (lim >= 8) v = __builtin_amdgcn_raw_buffer_load_b128(rsb, boff[i] + 2 * kb, 0, 0);
+                else if (lim > 0) v = load_u16_partial(rsb, boff[i] + 2 * kb, lim);
+                b[i] = v;
+            }
+            return;
+        }
         const int seg = st >= nkc ? 1 : 0;
         const int kc = st - seg * nkc;
         const int oa = seg * seg_a + kc * KT, ob = seg * seg_b + kc * KT;
@@ -142,6 +228,25 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     };
     auto sstore = [&](int buf, const v4i* a, const v4i* b) {
         char* base = lds + buf * STAGE;
+        if (RAW) {
+#pragma unroll
+            for (int i = 0; i < ACH; ++i) {
+                int2 hi, lo;
+                split_u16x8(a[i], hi, lo);
+                asum[i] = sum_u16x8(a[i], asum[i]);
+                *reinterpret_cast<int2*>(base + alds[i]) = hi;
+                *reinterpret_cast<int2*>(base + alds[i] + TILE) = lo;
+            }
+#pragma unroll
+            for (int i = 0; i < BCH; ++i) {
+                int2 hi, lo;
+                split_u16x8(b[i], hi, lo);
+                bsum[i] = sum_u16x8(b[i], bsum[i]);
+                *reinterpret_cast<int2*>(base + blds[i]) = hi;
+                *reinterpret_cast<int2*>(base + blds[i] + TILE) = lo;
+            }
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < ACH; ++i) *reinterpret_cast<v4i*>(base + alds[i]) = a[i];
 #pragma unroll
@@ -185,7 +290,7 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
 #pragma unroll
                     for (int n = 0; n < FN; ++n)
                         acc[r][0][m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                            af[r][m], bf[0][n], acc[r][0][m][n], 0, 0, 0);
+                            bf[0][n], af[r][m], acc[r][0][m][n], 0, 0, 0);
         } else {
             // limb products (hi,hi) -> 0, (hi,lo) and (lo,hi) -> 1, (lo,lo) -> 2, ordered
             // so that consecutive MFMAs do not share an accumulator
@@ -200,7 +305,7 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
 #pragma unroll
                         for (int n = 0; n < FN; ++n)
                             acc[r][ai][m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                                af[r * NL + la][m], bf[lb][n], acc[r][ai][m][n], 0, 0, 0);
+                                bf[lb][n], af[r * NL + la][m], acc[r][ai][m][n], 0, 0, 0);
             }
         }
     };
@@ -237,47 +342,140 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
         }
     }
 
-    // ---- epilogue: exact recombination, reduction mod p, store.  The output format is
-    // switched on once, outside the fully unrolled fragment loops.
-    // Output layout of the 32x32 MFMA: lane -> column (lane & 31), register v -> row
-    // 8 (v / 4) + 4 (lane / 32) + v % 4 of the fragment.
+    // ---- raw operands: row sums of the tile's A rows and B rows into LDS (the
+    // stage buffers are free after the last barrier of the loop).  The RPR
+    // consecutive threads that loaded one row's chunks reduce across lanes.
+    constexpr int RSUM_BYTES = RAW ? 2 * BT * 4 : 0;  // at the end of LDS, clear of the staging below
+    const uint32_t* rsum_a = reinterpret_cast<const uint32_t*>(lds + 2 * STAGE - RSUM_BYTES);
+    const uint32_t* rsum_b = rsum_a + BT;
+    if (RAW) {
+        static_assert(RPR <= 64 && NT % RPR == 0, "row chunks within a wave");
+        uint32_t* rs = reinterpret_cast<uint32_t*>(lds + 2 * STAGE - RSUM_BYTES);
+#pragma unroll
+        for (int i = 0; i < ACH; ++i) {
+            uint32_t v = asum[i];
+#pragma unroll
+            for (int o = RPR / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+            const int c = tid + i * NT;
+            if (c % RPR == 0) rs[c / RPR] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < BCH; ++i) {
+            uint32_t v = bsum[i];
+#pragma unroll
+            for (int o = RPR / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+            const int c = tid + i * NT;
+            if (c % RPR == 0) rs[BT + c / RPR] = v;
+        }
+        __syncthreads();
+    }
+    constexpr double RAW_D = 32896.0;
+    const double raw_kdd = RAW_D * RAW_D * (double)K;
+
+    // ---- epilogue: exact recombination, reduction mod p, store.
+    // The MFMAs take (B fragment, A fragment), so a 32x32 accumulator holds its
+    // block transposed: lane -> row (lane & 31), register v -> column
+    // 8 (v / 4) + 4 (lane / 32) + v % 4; four consecutive registers are four
+    // consecutive columns of one row of C.
     const int p = fp.p;
     const float inv_pf = (float)fp.inv_p;
     const int32_t c16 = (int32_t)(65536 % p);
-    const int i0 = row0 + wm0 + 4 * (lane >> 5), j0 = col0 + wn0 + (lane & 31);
     const bool syrk = T.syrk != 0;
-    const int64_t ldc = T.c.ld;
-    // interior tiles (inside the matrix and strictly below the diagonal) need no checks
-    const bool interior = row0 + BT <= M && col0 + BT <= N && (!syrk || row0 >= col0 + BT);
+    const int ldc = T.c.ld;
+    const int rows_c = min(BT, M - row0), cols_c = min(BT, N - col0);
+    auto residue = [&](int r, int m, int n, int v) -> int32_t {
+        if (NL == 1) return mod_small_p(acc[r][0][m][n][v], p, c16, inv_pf);  // one limb: p < 2^8
+        double val = 65536.0 * (double)acc[r][0][m][n][v] + 256.0 * (double)acc[r][NACC - 2][m][n][v] +
+                     (double)acc[r][NACC - 1][m][n][v];
+        if (RAW) {
+            const int li = wm0 + m * 32 + (lane & 31);
+            const int lj = wn0 + n * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            val += RAW_D * ((double)rsum_a[li] + (double)rsum_b[lj]) - raw_kdd;
+        }
+        return mod_canon(val, p, fp.inv_p);
+    };
+    // Staged store: the tile's residues go to LDS in the output format (rows of
+    // BT elements, 16-byte segments XOR-swizzled by row), then every thread
+    // writes whole 16-byte segments of C rows.  Segments that cross the matrix
+    // edge or the diagonal of a base case are written element by element.  Needs
+    // a 16-byte aligned tile origin and row stride, and 32-bit tile offsets.
     auto epilogue = [&](auto tag) {
         using OT = decltype(tag);
+        constexpr int ES = (int)sizeof(OT);
+        constexpr int RB = BT * ES;   // bytes per staged row
+        constexpr int NSR = RB / 16;  // segments per row
+        constexpr int EPS = 16 / ES;  // elements per segment
+        constexpr bool CAN_STAGE = BT * RB <= 2 * STAGE - RSUM_BYTES;
 #pragma unroll
         for (int r = 0; r < NROLE; ++r) {
-            OT* cp = reinterpret_cast<OT*>(r == 0 ? bases.p[T.c.buf] + T.c.off
-                                                  : bases.p[T.c.buf2] + T.c.off2);
+            char* cb = (r == 0 ? bases.p[T.c.buf] + T.c.off : bases.p[T.c.buf2] + T.c.off2) +
+                       ((int64_t)row0 * ldc + col0) * ES;
+            const bool staged = CAN_STAGE && ((((uintptr_t)cb) | (uintptr_t)(ldc * ES)) & 15) == 0 &&
+                                (int64_t)BT * ldc * ES < (1ll << 31);
+            if (staged) {
+                if (r > 0) __syncthreads();  // the previous role's reads of LDS are done
 #pragma unroll
-            for (int m = 0; m < FM; ++m)
+                for (int m = 0; m < FM; ++m)
 #pragma unroll
-                for (int n = 0; n < FN; ++n)
+                    for (int n = 0; n < FN; ++n)
 #pragma unroll
-                    for (int v = 0; v < 16; ++v) {
-                        int32_t res;
-                        if (NL == 1) {
-                            res = p < 256 ? mod_small_p(acc[r][0][m][n][v], p, c16, inv_pf)
-                                          : mod_i32(acc[r][0][m][n][v], p, inv_pf);
-                        } else {
-                            const double val = 65536.0 * (double)acc[r][0][m][n][v] +
-                                               256.0 * (double)acc[r][NACC - 2][m][n][v] +
-                                               (double)acc[r][NACC - 1][m][n][v];
-                            res = mod_canon(val, p, fp.inv_p);
+                        for (int q = 0; q < 4; ++q) {
+                            OT vals[4];
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) vals[e] = (OT)residue(r, m, n, 4 * q + e);
+                            const int li = wm0 + m * 32 + (lane & 31);
+                            const int byte = (wn0 + n * 32 + 8 * q + 4 * (lane >> 5)) * ES;
+#pragma unroll
+                            for (int h = 0; h < (4 * ES + 15) / 16; ++h) {
+                                // 4 * ES bytes: part of one segment, or whole segments (ES = 8)
+                                const int bb = byte + 16 * h;
+                                char* dst = lds + li * RB + (((bb >> 4) ^ (li & (NSR - 1))) << 4) + (bb & 15);
+                                if (ES == 1) *reinterpret_cast<uint32_t*>(dst) = *reinterpret_cast<const uint32_t*>(vals);
+                                else if (ES == 2) *reinterpret_cast<uint2*>(dst) = *reinterpret_cast<const uint2*>(vals);
+                                else *reinterpret_cast<int4*>(dst) = reinterpret_cast<const int4*>(vals)[h];
+                            }
+                            if (q == 3) __builtin_amdgcn_sched_barrier(0);
                         }
-                        const int i = i0 + m * 32 + 8 * (v >> 2) + (v & 3);
-                        const int j = j0 + n * 32;
-                        if (interior || (i < M && j < N && (!syrk || i >= j)))
-                            cp[(int64_t)i * ldc + j] = (OT)res;
-                        // keep the scheduler from hoisting the reads of every accumulator
-                        if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                __syncthreads();
+                const int ext = (int)((int64_t)(rows_c - 1) * ldc * ES + (int64_t)cols_c * ES);
+                const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc((void*)cb, (short)0, ext, 0x00020000);
+                constexpr int NCH = BT * NSR;
+                static_assert(NCH % NT == 0, "store chunks");
+#pragma unroll
+                for (int it = 0; it < NCH / NT; ++it) {
+                    const int c = tid + it * NT;
+                    const int rr = c / NSR, sg = c % NSR;
+                    if (rr >= rows_c) continue;
+                    const v4i val = *reinterpret_cast<const v4i*>(lds + rr * RB + ((sg ^ (rr & (NSR - 1))) << 4));
+                    const int off = rr * ldc * ES + sg * 16;
+                    // valid columns of the segment: inside the matrix, and on or below the diagonal
+                    int nv = cols_c - sg * EPS;
+                    if (syrk) nv = min(nv, row0 + rr - (col0 + sg * EPS) + 1);
+                    if (nv >= EPS) {
+                        __builtin_amdgcn_raw_buffer_store_b128(val, rc, off, 0, 0);
+                    } else if (nv > 0) {
+                        const OT* el = reinterpret_cast<const OT*>(&val);
+#pragma unroll
+                        for (int e = 0; e < EPS; ++e)
+                            if (e < nv) *reinterpret_cast<OT*>(cb + off + e * ES) = el[e];
                     }
+                }
+            } else {
+                OT* cp = reinterpret_cast<OT*>(cb);
+#pragma unroll
+                for (int m = 0; m < FM; ++m)
+#pragma unroll
+                    for (int n = 0; n < FN; ++n)
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) {
+                            const int li = wm0 + m * 32 + (lane & 31);
+                            const int lj = wn0 + n * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                            const int32_t res = residue(r, m, n, v);
+                            if (li < rows_c && lj < cols_c && (!syrk || row0 + li >= col0 + lj))
+                                cp[(int64_t)li * ldc + lj] = (OT)res;
+                            if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                        }
+            }
         }
     };
     switch (T.c.dt) {
@@ -297,15 +495,13 @@ struct CfgInfo {
     int nl, cplx, bt, kt, nthreads, lds;
 };
 
+// (Configurations whose accumulators do not fit the register file without
+// spilling are left out; ids are not renumbered.)
 #define FFA_I8_CONFIGS(X)                 \
-    X(0, 1, 0, 256, 2, 2, 128, 2)         \
     X(1, 1, 0, 256, 2, 4, 64, 2)          \
     X(2, 1, 0, 128, 2, 2, 128, 2)         \
-    X(3, 2, 0, 128, 2, 2, 128, 2)         \
     X(4, 1, 1, 128, 2, 2, 128, 2)         \
-    X(5, 2, 1, 128, 2, 4, 64, 1)          \
     X(6, 2, 0, 128, 2, 2, 64, 2)          \
-    X(7, 1, 0, 256, 2, 2, 64, 2)          \
     X(8, 2, 1, 64, 2, 2, 128, 2)          \
     X(9, 2, 0, 128, 2, 2, 128, 1)         \
     X(10, 1, 0, 256, 2, 4, 128, 2)        \
@@ -337,13 +533,13 @@ int gemm_i8_default_config(int nl, int cplx, int64_t max_dim)
     return max_dim >= 2048 ? 10 : 2;
 }
 
-template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF>
+template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC>
 static int launch_cfg(const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks, const Bases& b,
                       const FieldParams& fp, hipStream_t s)
 {
     constexpr int NA = (CPLX ? 2 : 1) * NL, NB = NL;
     constexpr int lds_bytes = 2 * (NA + NB) * BT * KT;
-    auto kern = gemm_i8<NL, CPLX, BT, WGM, WGN, KT, PF>;
+    auto kern = gemm_i8<NL, CPLX, BT, WGM, WGN, KT, PF, SRC>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -356,13 +552,27 @@ static int launch_cfg(const GemmTask* d_tasks, const TileEnt* d_sched, int nbloc
     return (int)hipGetLastError();
 }
 
-int launch_gemm_i8(int cfg, const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks,
+// Raw uint16 operands exist only for the two-limb real configurations.
+template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF>
+static int launch_src(int src, const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks,
+                      const Bases& b, const FieldParams& fp, hipStream_t s)
+{
+    if (src == SRC_CARRIER)
+        return launch_cfg<NL, CPLX, BT, WGM, WGN, KT, PF, SRC_CARRIER>(d_tasks, d_sched, nblocks, b, fp, s);
+    if constexpr (NL == 2 && CPLX == 0) {
+        if (src == SRC_RAW_U16)
+            return launch_cfg<NL, CPLX, BT, WGM, WGN, KT, PF, SRC_RAW_U16>(d_tasks, d_sched, nblocks, b, fp, s);
+    }
+    return (int)hipErrorInvalidValue;
+}
+
+int launch_gemm_i8(int cfg, int src, const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks,
                    const Bases& b, const FieldParams& fp, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
     if (nblocks <= 0) return 0;
 #define FFA_LAUNCH(ID, NL, CP, BT, WM, WN, KT, PF) \
-    if (cfg == ID) return launch_cfg<NL, CP, BT, WM, WN, KT, PF>(d_tasks, d_sched, nblocks, b, fp, s);
+    if (cfg == ID) return launch_src<NL, CP, BT, WM, WN, KT, PF>(src, d_tasks, d_sched, nblocks, b, fp, s);
     FFA_I8_CONFIGS(FFA_LAUNCH)
 #undef FFA_LAUNCH
     return (int)hipErrorInvalidValue;

@@ -86,7 +86,7 @@ struct Builder {
         return v;
     }
     void add_gemm(const CarRef& x, const CarRef& z, const ResRef& c, int64_t M, int64_t N,
-                  int64_t K, bool syrk)
+                  int64_t K, bool syrk, bool aonly, int64_t kvalid = -1)
     {
         GemmTask g{};
         g.x = x;
@@ -96,6 +96,7 @@ struct Builder {
         g.N = (int32_t)N;
         g.K = (int32_t)K;
         g.syrk = syrk ? 1 : 0;
+        g.kvalid = (int32_t)(kvalid >= 0 ? kvalid : K);
         g.tiles_m = (int32_t)((M + bt - 1) / bt);
         g.tiles_n = (int32_t)((N + bt - 1) / bt);
         // the INT8 kernel addresses an operand panel with 32-bit offsets: the
@@ -107,15 +108,17 @@ struct Builder {
             if (ea >= (1ll << 31) || eb >= (1ll << 31)) pl.status = FFA_EUNSUPPORTED;
         }
         pl.gemm.push_back(g);
+        pl.gemm_aonly.push_back(aonly ? 1 : 0);
         pl.max_k = std::max(pl.max_k, K);
         pl.products_macs += syrk ? M * (M + 1) / 2 * K : M * N * K;
     }
     // One node of the recursion: a is rows x cols, its result goes to c.
+    // aonly: a is a block of the (conditioned) input itself.
     void node(int level, const CarRef& a, int64_t rows, int64_t cols, const ResRef& c,
-              int64_t nvalid)
+              int64_t nvalid, bool aonly)
     {
         if (level == pl.levels) {
-            add_gemm(a, a, c, rows, rows, cols, true);
+            add_gemm(a, a, c, rows, rows, cols, true, aonly);
             return;
         }
         const int64_t h = rows / 2, w = cols / 2;
@@ -128,11 +131,11 @@ struct Builder {
         ResRef P[5];
         for (int j = 0; j < 5; ++j) P[j] = new_res(h);
         const CarRef A11 = view(a, 0, 0), A12 = view(a, 0, w), A22 = view(a, h, w);
-        add_gemm(A22, pt.s[3], P[2], h, h, w, false);   // P3 = A22 phi(S4)
-        add_gemm(pt.s[0], pt.s[1], P[3], h, h, w, false);  // P4 = S1 phi(S2)
-        node(level + 1, A11, h, w, P[0], h);               // P1 = A11 phi(A11)
-        node(level + 1, A12, h, w, P[1], h);               // P2 = A12 phi(A12)
-        node(level + 1, pt.s[2], h, w, P[4], h);           // P5 = S3 phi(S3)
+        add_gemm(A22, pt.s[3], P[2], h, h, w, false, false);   // P3 = A22 phi(S4)
+        add_gemm(pt.s[0], pt.s[1], P[3], h, h, w, false, false);  // P4 = S1 phi(S2)
+        node(level + 1, A11, h, w, P[0], h, aonly);               // P1 = A11 phi(A11)
+        node(level + 1, A12, h, w, P[1], h, aonly);               // P2 = A12 phi(A12)
+        node(level + 1, pt.s[2], h, w, P[4], h, false);           // P5 = S3 phi(S3)
         PostaddTask qt{};
         for (int j = 0; j < 5; ++j) qt.p[j] = P[j];
         qt.c = c;
@@ -155,6 +158,8 @@ Common common_setup(uint32_t p, int herm, int dA, int dC, const ffa_opts& o)
     if (!dtype_in_ok(dA) || !dtype_out_ok(dC)) { cm.status = FFA_EINVAL; return cm; }
     if (o.algo < FFA_ALGO_AUTO || o.algo > FFA_ALGO_RECURSIVE) { cm.status = FFA_EINVAL; return cm; }
     if (o.carrier < FFA_CARRIER_AUTO || o.carrier > FFA_CARRIER_F64) { cm.status = FFA_EINVAL; return cm; }
+    if (o.operands < FFA_OPERANDS_AUTO || o.operands > FFA_OPERANDS_RAW) { cm.status = FFA_EINVAL; return cm; }
+    if (o.streams < FFA_STREAMS_AUTO || o.streams > FFA_STREAMS_TWO) { cm.status = FFA_EINVAL; return cm; }
     if (!is_odd_prime(p)) { cm.status = FFA_EPRIME; return cm; }
     if ((uint64_t)p > dtype_pmax(dA) || (uint64_t)p > dtype_pmax(dC)) { cm.status = FFA_EINVAL; return cm; }
     if (herm && p % 4 != 3) { cm.status = FFA_EUNSUPPORTED; return cm; }
@@ -240,7 +245,7 @@ int check_bound(const Plan& pl)
 // XCD with the least work so far (workgroup b runs on XCD b mod 8), and the
 // schedule interleaves the eight per-XCD lists; shorter lists are padded with
 // idle entries.
-void build_schedule(Plan& pl)
+int build_schedule(const Plan& pl, size_t first, size_t last, std::vector<TileEnt>& sched)
 {
     constexpr int GR = 4, GC = 8, NX = 8;
     struct Group {
@@ -249,7 +254,7 @@ void build_schedule(Plan& pl)
     };
     std::vector<Group> groups;
     int tiles = 0;
-    for (size_t t = 0; t < pl.gemm.size(); ++t) {
+    for (size_t t = first; t < last; ++t) {
         const GemmTask& g = pl.gemm[t];
         const double kcost = (double)g.K * (pl.cplx ? 2 : 1) + 64.0;
         for (int bi = 0; bi < g.tiles_m; bi += GR) {
@@ -266,7 +271,6 @@ void build_schedule(Plan& pl)
             }
         }
     }
-    pl.total_tiles = tiles;
     std::stable_sort(groups.begin(), groups.end(),
                      [](const Group& a, const Group& b) { return a.cost > b.cost; });
     std::vector<std::vector<TileEnt>> bins(NX);
@@ -280,9 +284,32 @@ void build_schedule(Plan& pl)
     }
     size_t len = 0;
     for (const auto& b : bins) len = std::max(len, b.size());
-    pl.sched.assign(len * NX, TileEnt{-1, 0});
+    sched.assign(len * NX, TileEnt{-1, 0});
     for (int x = 0; x < NX; ++x)
-        for (size_t i = 0; i < bins[x].size(); ++i) pl.sched[i * NX + x] = bins[x][i];
+        for (size_t i = 0; i < bins[x].size(); ++i) sched[i * NX + x] = bins[x][i];
+    return tiles;
+}
+
+// Orders the products as [reads only A | reads pre-addition outputs] and builds
+// one schedule per group when they run on two streams (the second group exists
+// only with recursion), else one schedule for all.
+void schedule_products(Plan& pl)
+{
+    if (!pl.fork) {
+        pl.gemm_split = (int)pl.gemm.size();
+        pl.total_tiles = build_schedule(pl, 0, pl.gemm.size(), pl.sched);
+        pl.sched2.clear();
+        return;
+    }
+    std::vector<GemmTask> g1, g2;
+    for (size_t t = 0; t < pl.gemm.size(); ++t) (pl.gemm_aonly[t] ? g1 : g2).push_back(pl.gemm[t]);
+    pl.gemm_split = (int)g1.size();
+    pl.gemm = g1;
+    pl.gemm.insert(pl.gemm.end(), g2.begin(), g2.end());
+    pl.gemm_aonly.assign(pl.gemm_split, 1);
+    pl.gemm_aonly.resize(pl.gemm.size(), 0);
+    pl.total_tiles = build_schedule(pl, 0, pl.gemm_split, pl.sched);
+    pl.total_tiles += build_schedule(pl, pl.gemm_split, pl.gemm.size(), pl.sched2);
 }
 
 void size_grids(Plan& pl)
@@ -297,7 +324,7 @@ void size_grids(Plan& pl)
         }
         for (const auto& t : pl.post[l]) pl.post_max_h[l] = std::max(pl.post_max_h[l], t.h);
     }
-    build_schedule(pl);
+    schedule_products(pl);
 }
 
 // Adds one problem's conditioning and recursion tree to the plan.
@@ -312,6 +339,24 @@ int add_problem(Plan& pl, Builder& B, const Problem& pr, int levels, bool allow_
         pl.kpad = kpad;
     }
     const int in_size = dtype_size(pr.dA);
+    if (pl.gemm_src == SRC_RAW_U16) {
+        // the product kernel reads the caller's uint16 rows and splits them into limbs
+        CarRef a;
+        a.buf = BUF_A;
+        a.off = pr.a_off * in_size;
+        a.ps = 0;
+        a.ld = (int32_t)(pr.lda * in_size);
+        pl.direct = true;
+        pl.max_abs = std::max<int>(pl.max_abs, 32896);
+        ResRef c;
+        c.buf = BUF_C;
+        c.buf2 = BUF_C2;
+        c.off = c.off2 = pr.c_off * dtype_size(pr.dC);
+        c.ld = (int32_t)pr.ldc;
+        c.dt = pr.dC;
+        B.add_gemm(a, a, c, pr.n, pr.n, kpad, true, true, pr.k);
+        return FFA_OK;
+    }
     const bool in_matches = (pl.carrier == CAR_I8 && pl.nl == 1 && !pl.cplx && pr.dA == FFA_I8_CENTRED) ||
                             (pl.carrier == CAR_F64 && pr.dA == FFA_F64);
     const bool direct = allow_direct && in_matches && !pl.check_inputs && npad == pr.n &&
@@ -353,9 +398,9 @@ int add_problem(Plan& pl, Builder& B, const Problem& pr, int levels, bool allow_
     c.ld = (int32_t)pr.ldc;
     c.dt = pr.dC;
     if (levels == 0) {
-        B.add_gemm(a, a, c, pr.n, pr.n, kpad, true);
+        B.add_gemm(a, a, c, pr.n, pr.n, kpad, true, true);
     } else {
-        B.node(0, a, npad, kpad, c, pr.n);
+        B.node(0, a, npad, kpad, c, pr.n, true);
     }
     return FFA_OK;
 }
@@ -375,6 +420,16 @@ void choose_kernel(Plan& pl, int64_t max_dim)
     pl.gemm_cfg = cfg;
     pl.tile = gemm_i8_config_tile(cfg);
     pl.ktile = gemm_i8_config_ktile(cfg);
+}
+
+// Whether a problem's products can read the caller's uint16 rows directly: two
+// limbs of a real field, no recursion (nothing else reads A), no input check,
+// and 16-byte aligned rows.
+bool raw_u16_ok(const Plan& pl, const Problem& pr, int levels)
+{
+    return pl.carrier == CAR_I8 && pl.nl == 2 && !pl.cplx && pr.dA == FFA_U16 && levels == 0 &&
+           !pl.check_inputs && pr.k > 0 && pr.aligned && (pr.lda * 2) % 16 == 0 &&
+           (pr.a_off * 2) % 16 == 0 && pr.lda * 2 < (1ll << 31) / 256;
 }
 
 Builder make_builder(Plan& pl)
@@ -411,12 +466,28 @@ Plan make_plan(const Problem& pr)
     pl.post.assign(pl.levels, {});
     pl.kernel_req = o.kernel;
     choose_kernel(pl, pr.n >> pl.levels);
-    Builder B = make_builder(pl);
-    int st = add_problem(pl, B, pr, pl.levels, true);
-    if (st) { pl.status = st; return pl; }
-    pl.ws_bytes = B.ws;
+    // the problem's tasks on top of the settings above (pl is copied so that a
+    // second attempt starts from the same state)
+    const Plan base = pl;
+    auto build = [&](Plan& q, int src) {
+        q.gemm_src = src;
+        Builder B = make_builder(q);
+        const int st = add_problem(q, B, pr, q.levels, true);
+        if (st) q.status = st;
+        q.ws_bytes = B.ws;
+    };
+    const bool raw_ok = raw_u16_ok(pl, pr, pl.levels);
+    build(pl, raw_ok && o.operands == FFA_OPERANDS_RAW ? SRC_RAW_U16 : SRC_CARRIER);
+    if (pl.status == FFA_EUNSUPPORTED && raw_ok && o.operands == FFA_OPERANDS_AUTO) {
+        // limb planes too large for the product kernel's 32-bit offsets: raw
+        // operands need no planes
+        pl = base;
+        build(pl, SRC_RAW_U16);
+    }
+    if (pl.status != FFA_OK && pl.status != FFA_EBOUND && pl.status != FFA_EUNSUPPORTED) return pl;
     if (pl.status == FFA_OK) pl.status = check_bound(pl);
     pl.zero_fill = pr.k == 0;
+    pl.fork = o.streams != FFA_STREAMS_ONE && pl.levels > 0;
     size_grids(pl);
     return pl;
 }
@@ -453,16 +524,30 @@ Plan make_batch_plan(const std::vector<Problem>& prs)
     Builder B = make_builder(pl);
     int64_t aoff = 0, coff = 0;
     const int ain = dtype_size(p0.dA), cout = dtype_size(p0.dC);
+    // packed layout: A_i rows padded to 16 bytes, every A_i and C_i 16-byte aligned
+    auto lda_of = [&](const Problem& q) { return round_up(std::max<int64_t>(q.k, 1), 16 / ain); };
+    if (p0.opts.operands == FFA_OPERANDS_RAW) {
+        bool raw = true;
+        int64_t off = 0;
+        for (size_t i = 0; i < prs.size() && raw; ++i) {
+            Problem q = prs[i];
+            q.lda = lda_of(q);
+            q.a_off = off;
+            off += round_up(q.n * q.lda * ain, 16) / ain;
+            raw = q.n == 0 || raw_u16_ok(pl, q, L[i]);
+        }
+        if (raw) pl.gemm_src = SRC_RAW_U16;
+    }
     for (size_t i = 0; i < prs.size(); ++i) {
         Problem q = prs[i];
-        q.lda = std::max<int64_t>(q.k, 1);
+        q.lda = lda_of(q);
         q.ldc = std::max<int64_t>(q.n, 1);
-        // keep every problem's A and C 16-byte aligned in the packed buffers
         q.a_off = aoff;
         q.c_off = coff;
         pl.a_off.push_back(aoff);
         pl.c_off.push_back(coff);
-        aoff += round_up(q.n * q.k * ain, 16) / ain;
+        pl.a_ld.push_back(q.lda);
+        aoff += round_up(q.n * q.lda * ain, 16) / ain;
         coff += round_up(q.n * q.n * cout, 16) / cout;
         if (q.n == 0) continue;
         // problems of one batch share one set of levels per problem; the
@@ -477,6 +562,7 @@ Plan make_batch_plan(const std::vector<Problem>& prs)
     pl.c_total = coff;
     pl.ws_bytes = B.ws;
     if (pl.status == FFA_OK) pl.status = check_bound(pl);
+    pl.fork = p0.opts.streams != FFA_STREAMS_ONE && pl.levels > 0;
     size_grids(pl);
     return pl;
 }
@@ -499,6 +585,7 @@ std::vector<char> pack_tables(Plan& pl)
     }
     pl.off_gemm = put(pl.gemm.data(), pl.gemm.size() * sizeof(GemmTask));
     pl.off_sched = put(pl.sched.data(), pl.sched.size() * sizeof(TileEnt));
+    pl.off_sched2 = put(pl.sched2.data(), pl.sched2.size() * sizeof(TileEnt));
     pl.blob_bytes = (int64_t)blob.size();
     return blob;
 }
@@ -518,13 +605,15 @@ std::string describe(const Plan& pl)
              "\"npad\":%lld,\"kpad\":%lld,\"direct\":%d,\"max_abs\":%d,\"max_k\":%lld,"
              "\"ws_bytes\":%lld,\"conditioning\":%zu,\"preadd_tasks\":%s,\"postadd_tasks\":%s,"
              "\"gemm_tasks\":%zu,\"tiles\":%d,\"blocks\":%zu,\"cfg\":%d,\"tile\":%d,"
-             "\"macs\":%lld,\"ykind\":%d,\"ya\":%d,\"yb\":%d}",
+             "\"macs\":%lld,\"ykind\":%d,\"ya\":%d,\"yb\":%d,\"src\":\"%s\",\"streams\":%d,"
+             "\"blocks_a_only\":%zu}",
              pl.status, pl.levels, pl.carrier == CAR_F64 ? "f64" : "int8", pl.nl, pl.cplx,
              (long long)pl.npad, (long long)pl.kpad, pl.direct ? 1 : 0, pl.max_abs,
              (long long)pl.max_k, (long long)pl.ws_bytes, pl.cond.size(), pre.c_str(), post.c_str(),
-             pl.gemm.size(), pl.total_tiles, pl.sched.size(), pl.gemm_cfg, pl.tile,
+             pl.gemm.size(), pl.total_tiles, pl.sched.size() + pl.sched2.size(), pl.gemm_cfg, pl.tile,
              (long long)pl.products_macs, pl.fp.ykind, pl.fp.ya,
-             pl.fp.yb);
+             pl.fp.yb, pl.gemm_src == SRC_RAW_U16 ? "raw_u16" : "carrier", pl.fork ? 2 : 1,
+             pl.sched.size());
     return buf;
 }
 

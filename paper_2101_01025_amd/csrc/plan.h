@@ -40,21 +40,31 @@ struct Plan {
     std::vector<std::vector<PostaddTask>> post; // per level
     std::vector<int> pre_max_hw, post_max_h;    // grid sizing per level
     std::vector<int> pre_max_h, pre_max_w;
+    // Products, in two groups: [0, gemm_split) read only A (the leaves reached
+    // through P1 and P2 alone), [gemm_split, end) read pre-addition outputs.
+    // Each group has its own tile schedule so that the first can run while the
+    // pre-additions are still being computed.
     std::vector<GemmTask> gemm;
+    std::vector<char> gemm_aonly;      // per task while planning: reads only A
+    int gemm_split = 0;
     int total_tiles = 0;
     int gemm_cfg = 0;                  // INT8 product kernel configuration
+    int gemm_src = SRC_CARRIER;        // operand source of the product launch
     int kernel_req = 0;                // requested configuration + 1 (0: built-in choice)
     int tile = 0;                      // product tile edge
     int ktile = 0;                     // product k-tile (carrier elements); K is padded to it
-    std::vector<TileEnt> sched;         // XCD-balanced tile schedule, one entry per workgroup
+    std::vector<TileEnt> sched;         // XCD-balanced tile schedule of group 1, one entry per workgroup
+    std::vector<TileEnt> sched2;        // same for group 2
+    bool fork = false;                  // run pre-additions + group 2 on a second stream
     int64_t ws_bytes = 0;
     int64_t products_macs = 0;         // multiply-accumulates of the products (per limb product)
     std::vector<int64_t> a_off, c_off; // packed batch layout (elements)
+    std::vector<int64_t> a_ld;         // packed batch: row stride of each A_i (elements)
     int64_t a_total = 0, c_total = 0;
     // device copy of the tables (filled by the API layer)
     void* d_blob = nullptr;
     int64_t blob_bytes = 0;
-    int64_t off_cond = 0, off_gemm = 0, off_sched = 0;
+    int64_t off_cond = 0, off_gemm = 0, off_sched = 0, off_sched2 = 0;
     std::vector<int64_t> off_pre, off_post;
 };
 

@@ -40,9 +40,7 @@ def _batch(count, seed, nmax=300, p=65521, **opts):
     ns, ks = si.batch_shapes(count, seed, nmin=1, nmax=nmax)
     mats = si.batch_residues(ns, ks, p, seed)
     B = ffa.BatchSyrk(ns, ks, p, ffa.U16, ffa.U16, **opts)
-    Ap = np.zeros(B.a_total, dtype=np.int64)
-    for i, M in enumerate(mats):
-        Ap[B.a_off[i]:B.a_off[i] + M.size] = M.ravel()
+    Ap = B.pack(mats, np.int64)
     B.ks_host = ks
     return B, ns, mats, _u16(Ap)
 

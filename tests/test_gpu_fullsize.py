@@ -162,9 +162,7 @@ def test_batch_4096_p65521():
     _say("batch 4096", int((ns * ns * ks).sum()))
     mats = si.batch_residues(ns, ks, p, seed, dtype=np.int32)
     B = ffa.BatchSyrk(ns, ks, p, ffa.U16, ffa.U16)
-    Ap = np.zeros(B.a_total, dtype=np.int32)
-    for i, M in enumerate(mats):
-        Ap[B.a_off[i]:B.a_off[i] + M.size] = M.ravel()
+    Ap = B.pack(mats, np.int32)
     A = _u16(Ap)
     del Ap
     C = torch.full((B.c_total,), 0xBEEF, dtype=torch.int32, device="cuda").to(torch.uint16)

@@ -203,6 +203,45 @@ def test_deterministic_repeats():
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
+# ------------------------------------------------------------------ raw uint16 operands
+
+@pytest.mark.parametrize("n", [1, 5, 130, 257])
+@pytest.mark.parametrize("k", [1, 7, 8, 9, 127, 128, 129, 300, 1000])
+def test_raw_u16_products_ragged_k(n, k):
+    """No recursion, uint16 input with 16-byte rows: the product kernel reads the
+    caller's rows and splits them into limbs.  The row padding holds nonzero
+    residues, which must never reach the result."""
+    ffa = _ffa()
+    p = 65521
+    lda = (k + 7) // 8 * 8 + 8
+    _say("raw u16", n, k, lda)
+    big = si.uniform_residues(n, lda, p, 900 + n * 7 + k)
+    Ares = big[:, :k].copy()
+    st, d = ffa.plan_describe(n, k, p, dA=ffa.U16, dC=ffa.U16, lda=lda,
+                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL, operands=ffa.OPERANDS_RAW))
+    assert st == 0 and d["src"] == "raw_u16"
+    A = _dev(big, torch.uint16)[:, :k]
+    C = _sentinel_c(n, torch.uint16)
+    ffa.syrk_modp(A, p, C=C, algo=ffa.ALGO_CLASSICAL, operands=ffa.OPERANDS_RAW)
+    torch.cuda.synchronize()
+    got = _host(C)
+    low = np.tril(np.ones((n, n), dtype=bool))
+    assert np.array_equal(got[low], oracle.syrk_modp(Ares, p)[low])
+    assert (got[~low] == 0xBEEF).all()
+
+
+def test_raw_u16_extreme_residues():
+    """Residues at the edges of the limb split (around 2^15 - 128 and p - 1)."""
+    ffa = _ffa()
+    p = 65521
+    vals = np.array([0, 1, 127, 128, 255, 256, 32639, 32640, 32767, 32768, 65407, 65408, 65519, 65520])
+    n, k = 70, 264
+    A = np.resize(vals, n * k).reshape(n, k)
+    A[::3] = 65520
+    check_syrk(A.astype(np.int64), p, torch.uint16, torch.uint16, algo=ffa.ALGO_CLASSICAL,
+               operands=ffa.OPERANDS_RAW)
+
+
 # ------------------------------------------------------------------ batched
 
 def test_batched_uneven_problems():
@@ -213,9 +252,7 @@ def test_batched_uneven_problems():
     _say("batch", len(ns))
     for opts in (dict(), dict(levels=1)):
         B = ffa.BatchSyrk(ns, ks, p, ffa.U16, ffa.U16, **opts)
-        Ap = np.zeros(B.a_total, dtype=np.int64)
-        for i, M in enumerate(mats):
-            Ap[B.a_off[i]:B.a_off[i] + M.size] = M.ravel()
+        Ap = B.pack(mats, np.int64)
         Cp = torch.zeros(B.c_total, dtype=torch.int32, device="cuda").to(torch.uint16)
         B.run(_dev(Ap, torch.uint16), Cp)
         torch.cuda.synchronize()

@@ -71,6 +71,44 @@ def test_plan_levels_padding_and_carriers():
     assert st == 0 and d["complex"] == 1 and d["ykind"] == 2
 
 
+def test_plan_operand_source():
+    # no recursion, uint16 rows on 16-byte boundaries: raw operands on request
+    st, d = ffa.plan_describe(300, 200, 65521, dA=ffa.U16, dC=ffa.U16,
+                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL, operands=ffa.OPERANDS_RAW))
+    assert st == 0 and d["src"] == "raw_u16" and d["conditioning"] == 0 and d["direct"] == 1
+    st, d = ffa.plan_describe(300, 200, 65521, dA=ffa.U16, dC=ffa.U16,
+                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
+    assert st == 0 and d["src"] == "carrier" and d["conditioning"] == 1
+    # unaligned rows, recursion, another input format, one limb, complex: carriers
+    for kw in (dict(k=201), dict(levels=1), dict(dA=ffa.I32), dict(p=251, dC=ffa.U8),
+               dict(hermitian=True, p=65519)):
+        args = dict(n=300, k=200, p=65521, dA=ffa.U16, dC=ffa.U16)
+        levels = kw.pop("levels", 0)
+        herm = kw.pop("hermitian", False)
+        args.update(kw)
+        o = ffa.make_opts(levels=1, operands=ffa.OPERANDS_RAW) if levels else \
+            ffa.make_opts(algo=ffa.ALGO_CLASSICAL, operands=ffa.OPERANDS_RAW)
+        st, d = ffa.plan_describe(args["n"], args["k"], args["p"], hermitian=herm, dA=args["dA"],
+                                  dC=args["dC"], opts=o)
+        assert st == 0 and d["src"] == "carrier", (kw, d)
+
+
+def test_plan_product_groups_and_streams():
+    # one level: P1, P2 read only A (group 1), P3, P4, P5 need the pre-additions
+    st, d = ffa.plan_describe(4096, 4096, 251, dA=ffa.I8_CENTRED, dC=ffa.U8, opts=ffa.make_opts(levels=1))
+    assert st == 0 and d["streams"] == 2
+    st1, d1 = ffa.plan_describe(4096, 4096, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
+                                opts=ffa.make_opts(levels=1, streams=ffa.STREAMS_ONE))
+    assert st1 == 0 and d1["streams"] == 1 and d1["blocks_a_only"] == d1["blocks"]
+    assert 0 < d["blocks_a_only"] < d["blocks"] and d["tiles"] == d1["tiles"]
+    # no recursion: one group, one stream
+    st, d = ffa.plan_describe(4096, 4096, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
+                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
+    assert d["streams"] == 1 and d["blocks_a_only"] == d["blocks"]
+    assert ffa.plan_describe(10, 10, 251, opts=ffa.make_opts(streams=3))[0] == ffa.EINVAL
+    assert ffa.plan_describe(10, 10, 251, opts=ffa.make_opts(operands=3))[0] == ffa.EINVAL
+
+
 def test_plan_macs_follow_recursion():
     # products MACs = 3^l leaf SYRKs + 2 * 3^i general products of level i
     for L in range(0, 4):
@@ -126,5 +164,9 @@ def test_degenerate_plans():
 def test_plan_refuses_operands_beyond_32bit_offsets():
     # two-limb carrier: two planes of n*k bytes must stay addressable with 32-bit offsets
     assert ffa.plan_describe(16384, 16384, 65521, dA=ffa.U16, dC=ffa.U16)[0] == 0
-    assert ffa.plan_describe(50000, 50000, 65521, dA=ffa.U16, dC=ffa.U16,
+    assert ffa.plan_describe(50000, 50000, 65521, dA=ffa.I32, dC=ffa.U16,
                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))[0] == ffa.EUNSUPPORTED
+    # raw uint16 operands have no limb planes: only a tile of rows must be addressable
+    st, d = ffa.plan_describe(50000, 50000, 65521, dA=ffa.U16, dC=ffa.U16,
+                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
+    assert st == 0 and d["src"] == "raw_u16"
