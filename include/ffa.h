@@ -83,10 +83,11 @@ enum { FFA_CARRIER_AUTO = 0, FFA_CARRIER_INT8 = 1, FFA_CARRIER_F64 = 2 };
  *                 FFA_OPERANDS_PLANES: always; FFA_OPERANDS_RAW: without recursion and
  *                 with uint16 input in 16-byte aligned rows, the product kernel reads A
  *                 itself and forms the limbs on the fly (else ignored)
- *   streams       FFA_STREAMS_AUTO / FFA_STREAMS_TWO: with recursion, the pre-additions
- *                 and the products that need them run on a second stream of the context
- *                 while the products that read only A run on the caller's stream (joined
- *                 before the post-additions); FFA_STREAMS_ONE: everything in stream order */
+ *   streams       FFA_STREAMS_AUTO / FFA_STREAMS_ONE: everything in stream order on the
+ *                 caller's stream; FFA_STREAMS_TWO: with recursion, the pre-additions and
+ *                 the products that need them run on a second stream of the context while
+ *                 the products that read only A run on the caller's stream (joined before
+ *                 the post-additions) */
 enum { FFA_LAUNCH_GRAPH = 0, FFA_LAUNCH_DIRECT = 1 };
 enum { FFA_OPERANDS_AUTO = 0, FFA_OPERANDS_PLANES = 1, FFA_OPERANDS_RAW = 2 };
 enum { FFA_STREAMS_AUTO = 0, FFA_STREAMS_ONE = 1, FFA_STREAMS_TWO = 2 };

@@ -487,7 +487,7 @@ Plan make_plan(const Problem& pr)
     if (pl.status != FFA_OK && pl.status != FFA_EBOUND && pl.status != FFA_EUNSUPPORTED) return pl;
     if (pl.status == FFA_OK) pl.status = check_bound(pl);
     pl.zero_fill = pr.k == 0;
-    pl.fork = o.streams != FFA_STREAMS_ONE && pl.levels > 0;
+    pl.fork = o.streams == FFA_STREAMS_TWO && pl.levels > 0;
     size_grids(pl);
     return pl;
 }
@@ -562,7 +562,7 @@ Plan make_batch_plan(const std::vector<Problem>& prs)
     pl.c_total = coff;
     pl.ws_bytes = B.ws;
     if (pl.status == FFA_OK) pl.status = check_bound(pl);
-    pl.fork = p0.opts.streams != FFA_STREAMS_ONE && pl.levels > 0;
+    pl.fork = p0.opts.streams == FFA_STREAMS_TWO && pl.levels > 0;
     size_grids(pl);
     return pl;
 }

@@ -76,6 +76,21 @@ def test_int8_p251_centred(levels, shape):
     check_syrk(A, 251, torch.int8, torch.uint8, levels=levels)
 
 
+@pytest.mark.parametrize("levels", [1, 2])
+@pytest.mark.parametrize("p,dt", [(251, torch.int8), (65521, torch.uint16), (65519, torch.uint16)])
+def test_two_streams(levels, p, dt):
+    """Pre-additions and the products that need them on the context's second stream."""
+    ffa = _ffa()
+    n, k = 300, 520
+    A = si.uniform_residues(n, k, p, 700 + p + levels)
+    if p == 65519:
+        Ai = si.uniform_residues(n, k, p, 701 + p + levels)
+        check_herk(A, Ai, p, dt, levels=levels, streams=ffa.STREAMS_TWO)
+    else:
+        check_syrk(A, p, dt, torch.uint8 if p < 256 else torch.uint16, levels=levels,
+                   streams=ffa.STREAMS_TWO)
+
+
 @pytest.mark.parametrize("p", [3, 5, 13, 241])
 def test_int8_small_primes(p):
     # p = 3 and 251 use Y = [[a,b],[-b,a]] (x) I; p = 5, 13, 241 use Y = sqrt(-1) I

@@ -95,8 +95,11 @@ def test_plan_operand_source():
 
 def test_plan_product_groups_and_streams():
     # one level: P1, P2 read only A (group 1), P3, P4, P5 need the pre-additions
-    st, d = ffa.plan_describe(4096, 4096, 251, dA=ffa.I8_CENTRED, dC=ffa.U8, opts=ffa.make_opts(levels=1))
+    st, d = ffa.plan_describe(4096, 4096, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
+                              opts=ffa.make_opts(levels=1, streams=ffa.STREAMS_TWO))
     assert st == 0 and d["streams"] == 2
+    assert ffa.plan_describe(4096, 4096, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
+                             opts=ffa.make_opts(levels=1))[1]["streams"] == 1
     st1, d1 = ffa.plan_describe(4096, 4096, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
                                 opts=ffa.make_opts(levels=1, streams=ffa.STREAMS_ONE))
     assert st1 == 0 and d1["streams"] == 1 and d1["blocks_a_only"] == d1["blocks"]
