@@ -31,6 +31,9 @@ WORKLOADS = {
     "syrk_p251_int8": dict(n=16384, k=16384, p=251, dA="int8", carrier="int8 x1 limb"),
     "syrk_p65521_int8x2": dict(n=16384, k=16384, p=65521, dA="uint16", carrier="int8 x2 limbs"),
     "syrk_p65521_f64": dict(n=8192, k=8192, p=65521, dA="float64", carrier="fp64"),
+    # the paper's two primes: 131071 = 3 mod 4 needs the 2x2-block Y, 131041 = 1 mod 4 a scalar Y
+    "syrk_p131071_f64": dict(n=8192, k=8192, p=131071, dA="float64", carrier="fp64"),
+    "syrk_p131041_f64": dict(n=8192, k=8192, p=131041, dA="float64", carrier="fp64"),
     "herk_p65519_int8x2": dict(n=4096, k=8192, p=65519, dA="uint16", carrier="int8 x2 limbs, complex"),
     # 4096 independent problems, n uniform in [32, 512], k uniform in [n, 2n]
     "batch4096_p65521": dict(count=4096, nmin=32, nmax=512, p=65521, dA="uint16",

@@ -128,6 +128,18 @@ int ffa_syrk_modp(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p,
                   int dA, const void* A, int64_t lda,
                   int dC, void* C, int64_t ldc, const ffa_opts* opts);
 
+/* The SYRK update form (Section 7, schedule for alpha A A^T + beta C):
+ *   C <- alpha Low(op(A) op(A)^T) + beta Low(C)  mod p,
+ * op(A) = A (trans = 0, A is n x k, lda >= k) or A^T (trans = 1, A is k x n, lda >= n,
+ * so that C = A^T A).  alpha, beta in [0, p).  With beta != 0 the lower triangle of
+ * C must hold canonical residues; with beta = 0 it is not read.  The strict upper
+ * triangle is neither read nor written.  trans = 0, alpha = 1, beta = 0 is
+ * ffa_syrk_modp; otherwise the product goes to workspace residues and a final
+ * pass forms alpha X + beta C (alpha X + beta C < 2^53 in fp64, exact for p < 2^26). */
+int ffa_syrk_modp_ex(ffa_ctx* ctx, int trans, int64_t n, int64_t k, uint32_t p, uint32_t alpha,
+                     int dA, const void* A, int64_t lda, uint32_t beta, int dC, void* C, int64_t ldc,
+                     const ffa_opts* opts);
+
 /* C = Low(A A^H) over F_{p^2} = F_p[i]/(i^2+1), p = 3 mod 4, conj(x + iy) = x - iy
  * (Algorithm 1 with phi = conjugate transpose; Y of Section 4.4).  Planar storage:
  * A = A_re + i A_im and C = C_re + i C_im, each plane as in ffa_syrk_modp, same lda/ldc.

@@ -124,6 +124,20 @@ def syrk_modp(A, p, full=False):
     return C
 
 
+def syrk_update(A, C, p, alpha=1, beta=0, trans=False):
+    """The SYRK update form of Section 7: alpha Low(op(A) op(A)^T) + beta Low(C) mod p,
+    op(A) = A or A^T; the strict upper triangle of the result is C's."""
+    Aop = np.asarray(A, dtype=np.int64)
+    if trans:
+        Aop = Aop.T
+    X = syrk_modp(Aop, p)
+    C = _i64(C)
+    low = np.tril(np.ones(C.shape, dtype=bool))
+    out = C.copy()
+    out[low] = (alpha * X[low] + beta * C[low]) % p
+    return out
+
+
 def syrk_entries(A, p, rows, cols):
     A = _i64(A)
     n, k = A.shape

@@ -29,7 +29,7 @@ SYMBOLS = [
     "ffa_batch_offsets", "ffa_batch_syrk_exec", "ffa_batch_destroy", "ffa_plan_describe",
     "ffa_profile_enable", "ffa_profile_read", "ffa_profile_reset",
     "ffa_autotune_syrk", "ffa_batch_autotune", "ffa_tune_export", "ffa_tune_import",
-    "ffa_batch_describe",
+    "ffa_batch_describe", "ffa_syrk_modp_ex",
 ]
 PHASE_COND, PHASE_PRE, PHASE_PRODUCTS, PHASE_POST = 0, 1, 2, 3
 
@@ -76,6 +76,7 @@ def lib():
         L.ffa_skew_unitary.argtypes = [u32, i32, ctypes.POINTER(u32), ctypes.POINTER(u32),
                                        ctypes.POINTER(i32)]
         L.ffa_syrk_modp.argtypes = [P, i64, i64, u32, i32, P, i64, i32, P, i64, P]
+        L.ffa_syrk_modp_ex.argtypes = [P, i32, i64, i64, u32, u32, i32, P, i64, u32, i32, P, i64, P]
         L.ffa_herk_modp2.argtypes = [P, i64, i64, u32, i32, P, P, i64, i32, P, P, i64, P]
         L.ffa_batch_syrk_plan.argtypes = [P, i64, P, P, u32, i32, i32, P, ctypes.POINTER(P)]
         L.ffa_batch_offsets.argtypes = [P, P, P, P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -202,16 +203,24 @@ def default_out_dtype(p):
     return torch.int32
 
 
-def syrk_modp(A, p, C=None, out_dtype=None, opts=None, **kw):
-    """Lower triangle of A A^T mod p (ffa_syrk_modp).  Strict upper part of C is left as is."""
+def syrk_modp(A, p, C=None, out_dtype=None, opts=None, alpha=1, beta=0, trans=False, **kw):
+    """C = alpha Low(op(A) op(A)^T) + beta Low(C) mod p (ffa_syrk_modp, or ffa_syrk_modp_ex
+    for alpha != 1, beta != 0 or trans: op(A) = A^T, A is k x n).  The strict upper part
+    of C is left as is."""
     ctx = _prep(A)
-    n, k = A.shape
+    k, n = A.shape if trans else A.shape[::-1]
     C = _out(C, n, A.device, out_dtype or default_out_dtype(p))
     o = opts if opts is not None else make_opts(**kw)
-    st = lib().ffa_syrk_modp(ctx, n, k, p, _dtype_code(A), ctypes.c_void_p(A.data_ptr()),
-                             max(A.stride(0), k, 1), _dtype_code(C, True),
-                             ctypes.c_void_p(C.data_ptr()), max(C.stride(0), n, 1),
-                             ctypes.byref(o))
+    lda = max(A.stride(0), A.shape[1], 1)
+    if alpha == 1 and beta == 0 and not trans:
+        st = lib().ffa_syrk_modp(ctx, n, k, p, _dtype_code(A), ctypes.c_void_p(A.data_ptr()), lda,
+                                 _dtype_code(C, True), ctypes.c_void_p(C.data_ptr()),
+                                 max(C.stride(0), n, 1), ctypes.byref(o))
+    else:
+        st = lib().ffa_syrk_modp_ex(ctx, int(bool(trans)), n, k, p, alpha, _dtype_code(A),
+                                    ctypes.c_void_p(A.data_ptr()), lda, beta, _dtype_code(C, True),
+                                    ctypes.c_void_p(C.data_ptr()), max(C.stride(0), n, 1),
+                                    ctypes.byref(o))
     _check(st, f"(device error {lib().ffa_last_device_error(ctx)})" if st == EDEVICE else "")
     return C
 

@@ -69,10 +69,10 @@ ffa_opts default_opts()
 std::string key_of(const Problem& p)
 {
     char buf[256];
-    snprintf(buf, sizeof(buf), "%lld|%lld|%lld|%lld|%u|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d", (long long)p.n,
-             (long long)p.k, (long long)p.lda, (long long)p.ldc, p.p, p.herm, p.dA, p.dC,
-             p.opts.algo, p.opts.levels, p.opts.cutoff, p.opts.carrier, p.opts.check_inputs,
-             p.opts.kernel, p.aligned ? 1 : 0);
+    snprintf(buf, sizeof(buf), "%lld|%lld|%lld|%lld|%u|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%u|%u",
+             (long long)p.n, (long long)p.k, (long long)p.lda, (long long)p.ldc, p.p, p.herm, p.dA,
+             p.dC, p.opts.algo, p.opts.levels, p.opts.cutoff, p.opts.carrier, p.opts.check_inputs,
+             p.opts.kernel, p.opts.operands, p.opts.streams, p.aligned ? 1 : 0, p.trans, p.alpha, p.beta);
     return buf;
 }
 
@@ -224,8 +224,11 @@ int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws)
     if (!pl.cond.empty()) {
         if (pl.check_inputs && (e = launch_zero_flag(c->d_err, s))) return dev_fail(c, e);
         hipEvent_t ev = phase_begin(c, ms);
-        e = launch_condition((const CondTask*)(blob + pl.off_cond), (int)pl.cond.size(),
-                             pl.cond_max_blocks, pl.cond[0].dt_in, b, pl.fp, pl.carrier, c->d_err, s);
+        const CondTask* ct = (const CondTask*)(blob + pl.off_cond);
+        e = pl.cond_trans ? launch_condition_trans(ct, (int)pl.cond.size(), pl.cond_max_blocks,
+                                                   pl.cond[0].dt_in, b, pl.fp, pl.carrier, c->d_err, s)
+                          : launch_condition(ct, (int)pl.cond.size(), pl.cond_max_blocks,
+                                             pl.cond[0].dt_in, b, pl.fp, pl.carrier, c->d_err, s);
         if (e) return dev_fail(c, e);
         phase_end(c, ms, ev, 0);
         if (pl.check_inputs) {
@@ -280,6 +283,13 @@ int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws)
         // product residues below
         e = launch_postadd((const PostaddTask*)(blob + pl.off_post[l]), (int)pl.post[l].size(),
                            pl.post_max_h[l], pl.post[l][0].c.dt, b, pl.fp, s);
+        if (e) return dev_fail(c, e);
+    }
+    if (!pl.upd.empty()) {
+        // C <- alpha X + beta C (counted with the post-additions)
+        if (!ev) ev = phase_begin(c, ms);
+        e = launch_update((const UpdateTask*)(blob + pl.off_upd), (int)pl.upd.size(), pl.upd_max_n,
+                          pl.upd[0].x.dt, pl.upd[0].c.dt, b, pl.fp, s);
         if (e) return dev_fail(c, e);
     }
     phase_end(c, ms, ev, 3);
@@ -529,6 +539,27 @@ int ffa_syrk_modp(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA, const 
     pr.p = p;
     pr.dA = dA;
     pr.dC = dC;
+    pr.opts = opts ? *opts : default_opts();
+    if (!opts && ctx) (void)tuned_opts(ctx, n, k, p, 0, dA, dC, &pr.opts);
+    pr.aligned = ((uintptr_t)A % 16) == 0;
+    return run_call(ctx, pr, A, nullptr, C, nullptr);
+}
+
+int ffa_syrk_modp_ex(ffa_ctx* ctx, int trans, int64_t n, int64_t k, uint32_t p, uint32_t alpha, int dA,
+                     const void* A, int64_t lda, uint32_t beta, int dC, void* C, int64_t ldc,
+                     const ffa_opts* opts)
+{
+    Problem pr;
+    pr.n = n;
+    pr.k = k;
+    pr.lda = lda;
+    pr.ldc = ldc;
+    pr.p = p;
+    pr.dA = dA;
+    pr.dC = dC;
+    pr.trans = trans;
+    pr.alpha = alpha;
+    pr.beta = beta;
     pr.opts = opts ? *opts : default_opts();
     if (!opts && ctx) (void)tuned_opts(ctx, n, k, p, 0, dA, dC, &pr.opts);
     pr.aligned = ((uintptr_t)A % 16) == 0;

@@ -557,6 +557,118 @@ __global__ void __launch_bounds__(512) postadd(const PostaddTask* tasks, Bases b
 }
 
 // ============================================================================
+// transposed conditioning and the final update C <- alpha X + beta C
+// ============================================================================
+
+// Canonical residue of one caller element (range-checked).
+template <typename IT>
+__device__ __forceinline__ int32_t canon_in(IT raw, int32_t p, int32_t half, bool centred, bool& ok)
+{
+    if (centred) {
+        const int32_t x = (int32_t)raw;
+        ok &= (x >= -half) & (x <= half);
+        return x < 0 ? x + p : x;
+    }
+    const double xd = (double)raw;
+    const int32_t x = (int32_t)raw;
+    ok &= (xd >= 0.0) & (xd < (double)p) & ((double)x == xd);
+    return x;
+}
+
+// Carrier tile of 64 x 64 from the transpose of the caller's k x n matrix: the
+// block of A rows C0.. (carrier columns) and A columns R0.. (carrier rows) is
+// read row by row into LDS and written out transposed, 16 carrier columns per
+// thread.  Carrier: NL int8 limbs (F64C = 0) or centred doubles (F64C = 1).
+template <typename IT, int NL, int F64C>
+__global__ void __launch_bounds__(256) condition_t(const CondTask* tasks, Bases b, FieldParams fp,
+                                                   int32_t* err)
+{
+    __shared__ int32_t tile[64][65];
+    const CondTask& t = tasks[blockIdx.y];
+    const int tcols = (t.kpad + 63) / 64;
+    const int ntile = ((t.npad + 63) / 64) * tcols;
+    if ((int)blockIdx.x >= ntile) return;
+    const int R0 = ((int)blockIdx.x / tcols) * 64, C0 = ((int)blockIdx.x % tcols) * 64;
+    const IT* A = reinterpret_cast<const IT*>(b.p[t.buf_re] + t.off_re);
+    const int p = fp.p, half = fp.half;
+    const bool centred = t.dt_in == DT_I8C;
+    const int tid = threadIdx.x;
+    bool ok = true;
+    {
+        const int ar = tid >> 2, ac = (tid & 3) * 16;
+        const int arow = C0 + ar;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int acol = R0 + ac + e;
+            int32_t v = 0;
+            if (arow < t.k && acol < t.n) v = canon_in<IT>(A[(int64_t)arow * t.lda + acol], p, half, centred, ok);
+            tile[ar][ac + e] = v;
+        }
+    }
+    if (!ok) err[0] = 1;
+    __syncthreads();
+    const int cr = tid >> 2, cc = (tid & 3) * 16;
+    const int crow = R0 + cr, ccol = C0 + cc;
+    if (crow >= t.npad || ccol >= t.kpad) return;
+    char* ob = b.p[t.out.buf] + t.out.off;
+    if (F64C) {
+        alignas(16) double out[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int32_t v = tile[cc + e][cr];
+            out[e] = (double)(v > half ? v - p : v);
+        }
+        double* dst = reinterpret_cast<double*>(ob) + (int64_t)crow * t.out.ld + ccol;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) reinterpret_cast<int4*>(dst)[q] = reinterpret_cast<const int4*>(out)[q];
+    } else {
+        alignas(16) int8_t out[NL][16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int32_t v = tile[cc + e][cr];
+            if (NL == 1) {
+                out[0][e] = (int8_t)(v > half ? v - p : v);
+            } else {
+                int8_t hi, lo;
+                split2(rep2(v, p), hi, lo);
+                out[0][e] = hi;
+                out[NL - 1][e] = lo;
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < NL; ++l)
+            *reinterpret_cast<int4*>(ob + (int64_t)l * t.out.ps + (int64_t)crow * t.out.ld + ccol) =
+                *reinterpret_cast<const int4*>(out[l]);
+    }
+}
+
+// C <- alpha X + beta C on the lower triangle; one thread per 8 columns of a row.
+template <typename RT, typename OT>
+__global__ void __launch_bounds__(256) update_c(const UpdateTask* tasks, Bases b, FieldParams fp)
+{
+    const UpdateTask& t = tasks[blockIdx.y];
+    const int n = t.n, gpr = (n + 7) / 8;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)n * gpr) return;
+    const int i = (int)(idx / gpr), j0 = (int)(idx % gpr) * 8;
+    if (j0 > i) return;
+    const RT* x = reinterpret_cast<const RT*>(b.p[t.x.buf] + t.x.off) + (int64_t)i * t.x.ld;
+    OT* c = reinterpret_cast<OT*>(b.p[t.c.buf] + t.c.off) + (int64_t)i * t.c.ld;
+    const int p = fp.p;
+    const double al = (double)fp.alpha, be = (double)fp.beta;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int j = j0 + e;
+        if (j > i) break;
+        // alpha x + beta c < 2^53 for p < 2^26: exact in fp64
+        // beta = 0: C is not read (it may hold anything)
+        const double cv = fp.beta ? be * (double)(int64_t)c[j] : 0.0;
+        const double v = al * (double)(int64_t)x[j] + cv;
+        c[j] = (OT)mod_canon(v, p, fp.inv_p);
+    }
+}
+
+// ============================================================================
 // launch wrappers
 // ============================================================================
 
@@ -666,6 +778,67 @@ int launch_postadd(const PostaddTask* d_tasks, int ntasks, int h, int out_dt, co
         else launch_post_rt<int32_t, 0>(g, s, d_tasks, b, fp, out_dt);
     }
     return (int)hipGetLastError();
+}
+
+template <typename IT>
+static void launch_cond_t_typed(dim3 g, hipStream_t s, const CondTask* d_tasks, const Bases& b,
+                                const FieldParams& fp, int carrier, int32_t* d_err)
+{
+    if (carrier == CAR_F64)
+        hipLaunchKernelGGL((condition_t<IT, 1, 1>), g, dim3(256), 0, s, d_tasks, b, fp, d_err);
+    else if (fp.nl == 1)
+        hipLaunchKernelGGL((condition_t<IT, 1, 0>), g, dim3(256), 0, s, d_tasks, b, fp, d_err);
+    else
+        hipLaunchKernelGGL((condition_t<IT, 2, 0>), g, dim3(256), 0, s, d_tasks, b, fp, d_err);
+}
+
+int launch_condition_trans(const CondTask* d_tasks, int ntasks, int max_tiles, int dt_in, const Bases& b,
+                           const FieldParams& fp, int carrier, int32_t* d_err, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if (ntasks <= 0 || max_tiles <= 0) return 0;
+    if (fp.cplx) return (int)hipErrorInvalidValue;
+    const dim3 g(max_tiles, ntasks);
+    switch (dt_in) {
+    case DT_I8C: launch_cond_t_typed<int8_t>(g, s, d_tasks, b, fp, carrier, d_err); break;
+    case DT_U8: launch_cond_t_typed<uint8_t>(g, s, d_tasks, b, fp, carrier, d_err); break;
+    case DT_U16: launch_cond_t_typed<uint16_t>(g, s, d_tasks, b, fp, carrier, d_err); break;
+    case DT_I32: launch_cond_t_typed<int32_t>(g, s, d_tasks, b, fp, carrier, d_err); break;
+    case DT_I64: launch_cond_t_typed<int64_t>(g, s, d_tasks, b, fp, carrier, d_err); break;
+    case DT_F64: launch_cond_t_typed<double>(g, s, d_tasks, b, fp, carrier, d_err); break;
+    default: return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
+}
+
+template <typename RT>
+static int launch_update_rt(dim3 g, hipStream_t s, const UpdateTask* d, int c_dt, const Bases& b,
+                            const FieldParams& fp)
+{
+    switch (c_dt) {
+    case DT_U8: hipLaunchKernelGGL((update_c<RT, uint8_t>), g, dim3(256), 0, s, d, b, fp); break;
+    case DT_U16: hipLaunchKernelGGL((update_c<RT, uint16_t>), g, dim3(256), 0, s, d, b, fp); break;
+    case DT_I32: hipLaunchKernelGGL((update_c<RT, int32_t>), g, dim3(256), 0, s, d, b, fp); break;
+    case DT_I64: hipLaunchKernelGGL((update_c<RT, int64_t>), g, dim3(256), 0, s, d, b, fp); break;
+    case DT_F64: hipLaunchKernelGGL((update_c<RT, double>), g, dim3(256), 0, s, d, b, fp); break;
+    default: return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_update(const UpdateTask* d_tasks, int ntasks, int max_n, int x_dt, int c_dt, const Bases& b,
+                  const FieldParams& fp, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if (ntasks <= 0 || max_n <= 0) return 0;
+    const int64_t threads = (int64_t)max_n * ((max_n + 7) / 8);
+    const dim3 g((unsigned)((threads + 255) / 256), ntasks);
+    switch (x_dt) {
+    case DT_U8: return launch_update_rt<uint8_t>(g, s, d_tasks, c_dt, b, fp);
+    case DT_U16: return launch_update_rt<uint16_t>(g, s, d_tasks, c_dt, b, fp);
+    case DT_I32: return launch_update_rt<int32_t>(g, s, d_tasks, c_dt, b, fp);
+    default: return (int)hipErrorInvalidValue;
+    }
 }
 
 }  // namespace ffa

@@ -100,6 +100,7 @@ struct FieldParams {
     int32_t nl;        // limbs per plane (carrier CAR_I8)
     int32_t cplx;      // 1 for F_p[i]
     double inv_p;      // 1.0 / p
+    int32_t alpha, beta;  // C <- alpha X + beta C (canonical) in the update pass
 };
 
 // ---- tasks ----------------------------------------------------------------
@@ -149,12 +150,21 @@ struct TileEnt {
 
 // Conditioning: caller's A (n x k, format dt_in) into a carrier matrix of
 // npad x kpad (zero padded), planes re (and im, -re for F_p[i]).
+// trans: the caller's A is k x n and the carrier receives its transpose.
 struct CondTask {
     int32_t n, k, npad, kpad;
     int32_t lda, dt_in;
     int32_t buf_re, buf_im;
     int64_t off_re, off_im;
     CarRef out;
+    int32_t trans, pad_;
+};
+
+// Final update C <- alpha X + beta C on the lower triangle of an n x n result:
+// X is the product's residues (workspace), C the caller's matrix.
+struct UpdateTask {
+    ResRef x, c;
+    int32_t n, pad_;
 };
 
 // ---- launch wrappers (defined in the .hip files) ---------------------------
@@ -163,6 +173,11 @@ int launch_zero_flag(int32_t* d_flag, void* stream);
 // dt_in: the caller's input format (every task of a launch shares it)
 int launch_condition(const CondTask* d_tasks, int ntasks, int max_blocks, int dt_in, const Bases& b,
                      const FieldParams& fp, int carrier, int32_t* d_err, void* stream);
+// one launch for every task with trans = 1 (the others go to launch_condition)
+int launch_condition_trans(const CondTask* d_tasks, int ntasks, int max_tiles, int dt_in, const Bases& b,
+                           const FieldParams& fp, int carrier, int32_t* d_err, void* stream);
+int launch_update(const UpdateTask* d_tasks, int ntasks, int max_n, int x_dt, int c_dt, const Bases& b,
+                  const FieldParams& fp, void* stream);
 int launch_preadd(const PreaddTask* d_tasks, int ntasks, int h, int w, const Bases& b,
                   const FieldParams& fp, int carrier, void* stream);
 // out_dt: format of the outputs of this level (every task of a launch shares it)

@@ -327,6 +327,28 @@ void size_grids(Plan& pl)
     schedule_products(pl);
 }
 
+// Where the product of a whole problem goes: the caller's C, or, when the call
+// asks for C <- alpha Low(A A^T) + beta C, a workspace residue matrix that the
+// final update pass combines with C.
+ResRef root_output(Plan& pl, Builder& B, const Problem& pr)
+{
+    ResRef c;
+    c.buf = BUF_C;
+    c.buf2 = BUF_C2;
+    c.off = c.off2 = pr.c_off * dtype_size(pr.dC);
+    c.ld = (int32_t)pr.ldc;
+    c.dt = pr.dC;
+    if (pr.alpha == 1 && pr.beta == 0) return c;
+    const ResRef x = B.new_res(pr.n);
+    UpdateTask u{};
+    u.x = x;
+    u.c = c;
+    u.n = (int32_t)pr.n;
+    pl.upd.push_back(u);
+    pl.upd_max_n = std::max<int>(pl.upd_max_n, (int)pr.n);
+    return x;
+}
+
 // Adds one problem's conditioning and recursion tree to the plan.
 int add_problem(Plan& pl, Builder& B, const Problem& pr, int levels, bool allow_direct)
 {
@@ -348,18 +370,13 @@ int add_problem(Plan& pl, Builder& B, const Problem& pr, int levels, bool allow_
         a.ld = (int32_t)(pr.lda * in_size);
         pl.direct = true;
         pl.max_abs = std::max<int>(pl.max_abs, 32896);
-        ResRef c;
-        c.buf = BUF_C;
-        c.buf2 = BUF_C2;
-        c.off = c.off2 = pr.c_off * dtype_size(pr.dC);
-        c.ld = (int32_t)pr.ldc;
-        c.dt = pr.dC;
+        const ResRef c = root_output(pl, B, pr);
         B.add_gemm(a, a, c, pr.n, pr.n, kpad, true, true, pr.k);
         return FFA_OK;
     }
     const bool in_matches = (pl.carrier == CAR_I8 && pl.nl == 1 && !pl.cplx && pr.dA == FFA_I8_CENTRED) ||
                             (pl.carrier == CAR_F64 && pr.dA == FFA_F64);
-    const bool direct = allow_direct && in_matches && !pl.check_inputs && npad == pr.n &&
+    const bool direct = allow_direct && in_matches && !pr.trans && !pl.check_inputs && npad == pr.n &&
                         kpad == pr.k && pr.aligned && ((pr.lda * in_size) % 16 == 0) &&
                         ((pr.a_off * in_size) % 16 == 0);
     CarRef a;
@@ -382,21 +399,24 @@ int add_problem(Plan& pl, Builder& B, const Problem& pr, int levels, bool allow_
         ct.buf_im = BUF_A2;
         ct.off_re = ct.off_im = pr.a_off * in_size;
         ct.out = a;
+        ct.trans = pr.trans;
         pl.cond.push_back(ct);
-        const int64_t vec = pl.carrier == CAR_F64 ? 1 : 16;
-        const int64_t blocks = (npad * (kpad / vec) + 255) / 256;
+        int64_t blocks;
+        if (pr.trans) {
+            // 64 x 64 tiles of the carrier
+            pl.cond_trans = true;
+            blocks = ((npad + 63) / 64) * ((kpad + 63) / 64);
+        } else {
+            const int64_t vec = pl.carrier == CAR_F64 ? 1 : 16;
+            blocks = (npad * (kpad / vec) + 255) / 256;
+        }
         if (blocks >= (1ll << 31)) return FFA_EINVAL;
         pl.cond_max_blocks = (int)std::max<int64_t>(pl.cond_max_blocks, blocks);
     }
     // largest operand magnitude: centred carriers, except direct canonical fp64
     if (pl.carrier == CAR_F64) pl.max_abs = std::max<int>(pl.max_abs, direct ? (int)pl.fp.p - 1 : pl.fp.half);
     else pl.max_abs = std::max<int>(pl.max_abs, pl.nl == 1 ? pl.fp.half : 32896);
-    ResRef c;
-    c.buf = BUF_C;
-    c.buf2 = BUF_C2;
-    c.off = c.off2 = pr.c_off * dtype_size(pr.dC);
-    c.ld = (int32_t)pr.ldc;
-    c.dt = pr.dC;
+    const ResRef c = root_output(pl, B, pr);
     if (levels == 0) {
         B.add_gemm(a, a, c, pr.n, pr.n, kpad, true, true);
     } else {
@@ -427,7 +447,7 @@ void choose_kernel(Plan& pl, int64_t max_dim)
 // and 16-byte aligned rows.
 bool raw_u16_ok(const Plan& pl, const Problem& pr, int levels)
 {
-    return pl.carrier == CAR_I8 && pl.nl == 2 && !pl.cplx && pr.dA == FFA_U16 && levels == 0 &&
+    return pl.carrier == CAR_I8 && pl.nl == 2 && !pl.cplx && pr.dA == FFA_U16 && levels == 0 && !pr.trans &&
            !pl.check_inputs && pr.k > 0 && pr.aligned && (pr.lda * 2) % 16 == 0 &&
            (pr.a_off * 2) % 16 == 0 && pr.lda * 2 < (1ll << 31) / 256;
 }
@@ -452,7 +472,10 @@ Plan make_plan(const Problem& pr)
     if (pr.n < 0 || pr.k < 0) { pl.status = FFA_EINVAL; return pl; }
     Common cm = common_setup(pr.p, pr.herm, pr.dA, pr.dC, o);
     if (cm.status) { pl.status = cm.status; return pl; }
-    if (pr.n > 0 && pr.k > 0 && pr.lda < pr.k) { pl.status = FFA_EINVAL; return pl; }
+    if (pr.trans != 0 && pr.trans != 1) { pl.status = FFA_EINVAL; return pl; }
+    if (pr.n > 0 && pr.k > 0 && pr.lda < (pr.trans ? pr.n : pr.k)) { pl.status = FFA_EINVAL; return pl; }
+    if (pr.alpha >= pr.p || pr.beta >= pr.p) { pl.status = FFA_EINVAL; return pl; }
+    if (pr.herm && (pr.trans || pr.alpha != 1 || pr.beta != 0)) { pl.status = FFA_EUNSUPPORTED; return pl; }
     if (pr.n > 0 && pr.ldc < pr.n) { pl.status = FFA_EINVAL; return pl; }
     if (pr.lda >= (1ll << 31) || pr.ldc >= (1ll << 31) || pr.n >= (1ll << 30)) { pl.status = FFA_EINVAL; return pl; }
     pl.carrier = cm.carrier;
@@ -460,6 +483,8 @@ Plan make_plan(const Problem& pr)
     pl.cplx = pr.herm ? 1 : 0;
     pl.fp = cm.fp;
     pl.check_inputs = o.check_inputs ? 1 : 0;
+    pl.fp.alpha = (int32_t)pr.alpha;
+    pl.fp.beta = (int32_t)pr.beta;
     if (pr.n == 0) return pl;
     pl.levels = choose_levels(pr.n, pr.k, o, pl.carrier, pl.nl, pl.cplx);
     pl.pre.assign(pl.levels, {});
@@ -586,6 +611,7 @@ std::vector<char> pack_tables(Plan& pl)
     pl.off_gemm = put(pl.gemm.data(), pl.gemm.size() * sizeof(GemmTask));
     pl.off_sched = put(pl.sched.data(), pl.sched.size() * sizeof(TileEnt));
     pl.off_sched2 = put(pl.sched2.data(), pl.sched2.size() * sizeof(TileEnt));
+    pl.off_upd = put(pl.upd.data(), pl.upd.size() * sizeof(UpdateTask));
     pl.blob_bytes = (int64_t)blob.size();
     return blob;
 }

@@ -21,6 +21,8 @@ struct Problem {
     bool aligned = true;       // caller's A pointer is 16-byte aligned
     int64_t a_off = 0;         // element offsets in the caller's buffers (batches)
     int64_t c_off = 0;
+    int trans = 0;             // A is k x n and the product is A^T A
+    uint32_t alpha = 1, beta = 0;  // C <- alpha Low(A A^T) + beta C
 };
 
 struct Plan {
@@ -36,6 +38,9 @@ struct Plan {
     // task tables
     std::vector<CondTask> cond;
     int cond_max_blocks = 0;
+    bool cond_trans = false;           // conditioning reads the transpose (tiles of 64 x 64)
+    std::vector<UpdateTask> upd;       // final C <- alpha X + beta C
+    int upd_max_n = 0;
     std::vector<std::vector<PreaddTask>> pre;   // per level, top-down
     std::vector<std::vector<PostaddTask>> post; // per level
     std::vector<int> pre_max_hw, post_max_h;    // grid sizing per level
@@ -64,7 +69,7 @@ struct Plan {
     // device copy of the tables (filled by the API layer)
     void* d_blob = nullptr;
     int64_t blob_bytes = 0;
-    int64_t off_cond = 0, off_gemm = 0, off_sched = 0, off_sched2 = 0;
+    int64_t off_cond = 0, off_gemm = 0, off_sched = 0, off_sched2 = 0, off_upd = 0;
     std::vector<int64_t> off_pre, off_post;
 };
 

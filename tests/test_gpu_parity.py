@@ -218,6 +218,70 @@ def test_deterministic_repeats():
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
+# ------------------------------------------------------------------ SYRK update form, transpose
+
+UPDATE_CASES = [
+    # p, input dtype, output dtype, alpha, beta
+    (251, torch.int8, torch.uint8, 1, 0),
+    (251, torch.int8, torch.uint8, 250, 17),
+    (251, torch.uint8, torch.int64, 0, 3),
+    (65521, torch.uint16, torch.uint16, 40000, 65520),
+    (65521, torch.float64, torch.float64, 12345, 54321),
+    (131071, torch.float64, torch.int64, 131070, 2),
+]
+
+
+@pytest.mark.parametrize("trans", [False, True])
+@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("case", range(len(UPDATE_CASES)))
+def test_syrk_update_and_trans(case, levels, trans):
+    """C <- alpha Low(op(A) op(A)^T) + beta Low(C); op(A) = A^T with trans (A is k x n)."""
+    ffa = _ffa()
+    p, dA, dC, alpha, beta = UPDATE_CASES[case]
+    n, k = 203, 330
+    shape = (k, n) if trans else (n, k)
+    A_res = si.uniform_residues(*shape, p, 800 + case * 7 + levels)
+    C_res = si.uniform_residues(n, n, p, 900 + case)
+    _say("update", p, dA, dC, alpha, beta, levels, trans)
+    if dA == torch.int8:
+        A = _dev(si.to_centred(A_res, p).astype(np.int8), torch.int8)
+    else:
+        A = _dev(A_res, dA)
+    C = _dev(C_res, dC)
+    kw = dict(algo=ffa.ALGO_CLASSICAL) if levels == 0 else dict(levels=levels)
+    if dA == torch.float64 and p > 65535:
+        kw["carrier"] = ffa.CARRIER_F64
+    ffa.syrk_modp(A, p, C=C, alpha=alpha, beta=beta, trans=trans, **kw)
+    torch.cuda.synchronize()
+    exp = oracle.syrk_update(A_res, C_res, p, alpha=alpha, beta=beta, trans=trans)
+    assert np.array_equal(_host(C), exp)
+
+
+def test_syrk_update_degenerate():
+    ffa = _ffa()
+    p = 251
+    # k = 0: C <- beta C on the lower triangle
+    C_res = si.uniform_residues(7, 7, p, 950)
+    C = _dev(C_res, torch.int64)
+    ffa.syrk_modp(torch.zeros((7, 0), dtype=torch.int64, device="cuda"), p, C=C, alpha=5, beta=9)
+    torch.cuda.synchronize()
+    low = np.tril(np.ones((7, 7), dtype=bool))
+    got = _host(C)
+    assert np.array_equal(got[low], (9 * C_res[low]) % p) and np.array_equal(got[~low], C_res[~low])
+    # beta = 0: C is not read (it may hold values outside [0, p))
+    A_res = si.uniform_residues(6, 5, p, 951)
+    C = torch.full((6, 6), -12345, dtype=torch.int64, device="cuda")
+    ffa.syrk_modp(_dev(A_res, torch.int64), p, C=C, alpha=3, beta=0)
+    torch.cuda.synchronize()
+    got = _host(C)
+    low = np.tril(np.ones((6, 6), dtype=bool))
+    assert np.array_equal(got[low], (3 * oracle.syrk_modp(A_res, p)[low]) % p)
+    assert (got[~low] == -12345).all()
+    # alpha or beta outside [0, p) is refused
+    with pytest.raises(ffa.FfaError):
+        ffa.syrk_modp(_dev(A_res, torch.int64), p, C=C, alpha=p, beta=0)
+
+
 # ------------------------------------------------------------------ raw uint16 operands
 
 @pytest.mark.parametrize("n", [1, 5, 130, 257])

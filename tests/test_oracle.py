@@ -382,3 +382,37 @@ def test_operation_counts_against_paper():
     assert abs(2 * f(60) - target) < 1e-12
     # depth 0 is the classical SYRK: n^3/2 MACs = n^3 operations, the prior row of the table
     assert abs(2 * f(0) - consts["aat_leading_ops_prior"]["value"]) < 1e-12
+
+
+# ------------------------------------------------------------------ SYRK update form
+
+def test_syrk_update_special_cases():
+    p = 251
+    A = si.uniform_residues(9, 7, p, 41)
+    C = si.uniform_residues(9, 9, p, 42)
+    full = oracle.syrk_modp(A, p)
+    low = np.tril(np.ones((9, 9), dtype=bool))
+    # alpha = 1, beta = 0: the plain product; the strict upper triangle is C's
+    U = oracle.syrk_update(A, C, p)
+    assert np.array_equal(U[low], full[low]) and np.array_equal(U[~low], C[~low])
+    # alpha = 0: beta Low(C)
+    U = oracle.syrk_update(A, C, p, alpha=0, beta=7)
+    assert np.array_equal(U[low], (7 * C[low]) % p)
+    # alpha = c^2: the product of cA (a square alpha scales A)
+    c = 11
+    U = oracle.syrk_update(A, C, p, alpha=c * c % p, beta=0)
+    assert np.array_equal(U[low], oracle.syrk_modp((c * A) % p, p)[low])
+
+
+def test_syrk_update_trans_and_brute_force():
+    p = 13
+    A = si.uniform_residues(5, 4, p, 43)          # k x n with trans: C = A^T A (4 x 4)
+    C = si.uniform_residues(4, 4, p, 44)
+    U = oracle.syrk_update(A, C, p, alpha=3, beta=5, trans=True)
+    for i in range(4):
+        for j in range(4):
+            if j <= i:
+                s = sum(int(A[t, i]) * int(A[t, j]) for t in range(5))
+                assert U[i, j] == (3 * s + 5 * int(C[i, j])) % p
+            else:
+                assert U[i, j] == C[i, j]
