@@ -87,8 +87,13 @@ enum { FFA_CARRIER_AUTO = 0, FFA_CARRIER_INT8 = 1, FFA_CARRIER_F64 = 2 };
  *                 caller's stream; FFA_STREAMS_TWO: with recursion, the pre-additions and
  *                 the products that need them run on a second stream of the context while
  *                 the products that read only A run on the caller's stream (joined before
- *                 the post-additions) */
+ *                 the post-additions)
+ *   herk_base     base case of ffa_herk_modp2: FFA_HERK_AUTO / FFA_HERK_2M = the 2M method
+ *                 (Section 6, Algorithm 3 with epsilon = 1): one real SYRK of Xr + Xi and one
+ *                 real GEMM Xr Xi^T, 1.5 n^2 k products over F_p; FFA_HERK_4M = the four real
+ *                 products of the complex kernel, 2 n^2 k */
 enum { FFA_LAUNCH_GRAPH = 0, FFA_LAUNCH_DIRECT = 1 };
+enum { FFA_HERK_AUTO = 0, FFA_HERK_2M = 1, FFA_HERK_4M = 2 };
 enum { FFA_OPERANDS_AUTO = 0, FFA_OPERANDS_PLANES = 1, FFA_OPERANDS_RAW = 2 };
 enum { FFA_STREAMS_AUTO = 0, FFA_STREAMS_ONE = 1, FFA_STREAMS_TWO = 2 };
 typedef struct {
@@ -101,7 +106,8 @@ typedef struct {
     int32_t launch;
     int32_t operands;
     int32_t streams;
-    int32_t reserved[3];
+    int32_t herk_base;
+    int32_t reserved[2];
 } ffa_opts;
 
 /* Context bound to a HIP device and stream (stream NULL = the null stream).

@@ -22,6 +22,7 @@ CARRIER_AUTO, CARRIER_INT8, CARRIER_F64 = 0, 1, 2
 LAUNCH_GRAPH, LAUNCH_DIRECT = 0, 1
 OPERANDS_AUTO, OPERANDS_PLANES, OPERANDS_RAW = 0, 1, 2
 STREAMS_AUTO, STREAMS_ONE, STREAMS_TWO = 0, 1, 2
+HERK_AUTO, HERK_2M, HERK_4M = 0, 1, 2
 
 SYMBOLS = [
     "ffa_create", "ffa_destroy", "ffa_set_stream", "ffa_last_device_error", "ffa_status_string",
@@ -44,16 +45,18 @@ class Opts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("levels", ctypes.c_int32), ("cutoff", ctypes.c_int32),
                 ("carrier", ctypes.c_int32), ("check_inputs", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("launch", ctypes.c_int32), ("operands", ctypes.c_int32),
-                ("streams", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("streams", ctypes.c_int32), ("herk_base", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 def make_opts(algo=ALGO_AUTO, levels=-1, cutoff=0, carrier=CARRIER_AUTO, check_inputs=False,
-              kernel=0, launch=LAUNCH_GRAPH, operands=OPERANDS_AUTO, streams=STREAMS_AUTO):
+              kernel=0, launch=LAUNCH_GRAPH, operands=OPERANDS_AUTO, streams=STREAMS_AUTO,
+              herk_base=0):
     return Opts(algo, levels, cutoff, carrier, int(bool(check_inputs)), kernel, launch, operands,
-                streams)
+                streams, herk_base)
 
 
 _lib = None

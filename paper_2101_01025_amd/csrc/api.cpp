@@ -272,6 +272,17 @@ int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws)
         if (he != hipSuccess) return dev_fail(c, he);
     }
     if ((e = products(ms, pl.off_sched, pl.sched.size()))) return dev_fail(c, e);
+    if (!pl.gemm_r.empty()) {
+        // the real products of the 2M base case, then their combination into the leaves
+        hipEvent_t pev = phase_begin(c, ms);
+        e = launch_gemm_i8(pl.gemm_cfg_r, SRC_CARRIER, (const GemmTask*)(blob + pl.off_gemm_r),
+                           (const TileEnt*)(blob + pl.off_sched_r), (int)pl.sched_r.size(), b, pl.fp, s);
+        if (e) return dev_fail(c, e);
+        phase_end(c, ms, pev, 2);
+        e = launch_herk2m((const Herk2mTask*)(blob + pl.off_h2m), (int)pl.h2m.size(), pl.h2m_max_n,
+                          pl.h2m[0].g.dt, pl.h2m[0].out.dt, b, pl.fp, s);
+        if (e) return dev_fail(c, e);
+    }
     if (fork) {
         hipError_t he = hipStreamWaitEvent(ms, c->ev_join, 0);
         if (he != hipSuccess) return dev_fail(c, he);

@@ -92,7 +92,8 @@ __global__ void __launch_bounds__(256) condition_i8(const CondTask* tasks, Bases
     const int r = (int)(idx / gpr), c0 = (int)(idx % gpr) * VEC;
     const int p = fp.p;
     const bool centred = t.dt_in == DT_I8C;
-    constexpr int NPL = CPLX ? 3 : 1;
+    constexpr int NPL = CPLX ? 4 : 1;  // re, im, -re, re + im (the last for the 2M base case)
+    const int npl = CPLX ? fp.npo : 1;
     int32_t vr[16], vi[16];
     bool ok = true;
     const int valid = (r < t.n) ? max(0, min(VEC, t.k - c0)) : 0;
@@ -108,7 +109,7 @@ __global__ void __launch_bounds__(256) condition_i8(const CondTask* tasks, Bases
     alignas(16) int8_t out[NPL][NL][VEC];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
-        const int32_t vals[3] = {vr[e], CPLX ? vi[e] : 0, neg_mod(vr[e], p)};
+        const int32_t vals[4] = {vr[e], CPLX ? vi[e] : 0, neg_mod(vr[e], p), add_mod(vr[e], CPLX ? vi[e] : 0, p)};
 #pragma unroll
         for (int q = 0; q < NPL; ++q) {
             if (NL == 1) {
@@ -126,8 +127,9 @@ __global__ void __launch_bounds__(256) condition_i8(const CondTask* tasks, Bases
     for (int q = 0; q < NPL; ++q)
 #pragma unroll
         for (int l = 0; l < NL; ++l)
-            *reinterpret_cast<int4*>(ob + (int64_t)(q * NL + l) * t.out.ps) =
-                *reinterpret_cast<const int4*>(out[q][l]);
+            if (q < npl)
+                *reinterpret_cast<int4*>(ob + (int64_t)(q * NL + l) * t.out.ps) =
+                    *reinterpret_cast<const int4*>(out[q][l]);
 }
 
 __global__ void __launch_bounds__(256) condition_f64(const CondTask* tasks, Bases b, FieldParams fp,
@@ -188,7 +190,7 @@ __global__ void __launch_bounds__(256) preadd_i8(const PreaddTask* tasks, Bases 
     if (idx >= h * gpr) return;
     const int r = idx / gpr, c = (idx % gpr) * VEC;
     constexpr int NPI = CPLX ? 2 : 1;  // planes read (re, im)
-    constexpr int NPO = CPLX ? 3 : 1;  // planes written (re, im, -re)
+    constexpr int NPO = CPLX ? 4 : 1;  // planes written (re, im, -re; re + im for S3 in the 2M mode)
     typedef int8_t vec_t[VEC];
 
     // load A11, A12, A21, A22 (index blk = 2*row_half + col_half), left/right column halves
@@ -312,21 +314,27 @@ __global__ void __launch_bounds__(256) preadd_i8(const PreaddTask* tasks, Bases 
 #pragma unroll
                 for (int q = 0; q < NPI; ++q)
                     put_canon<NL>(s[j][half][q], p, fp.half, out[j][half][q][0], out[j][half][q][NL - 1], e);
-                // the "-re" plane used by the imaginary part of complex products
-                if (CPLX)
-                    put_canon<NL>(neg_mod(s[j][half][0], p), p, fp.half, out[j][half][NPO - 1][0],
-                                  out[j][half][NPO - 1][NL - 1], e);
+                // the "-re" plane used by the imaginary part of complex products, and
+                // re + im, which the 2M base case squares
+                if (CPLX) {
+                    put_canon<NL>(neg_mod(s[j][half][0], p), p, fp.half, out[j][half][2][0],
+                                  out[j][half][2][NL - 1], e);
+                    put_canon<NL>(add_mod(s[j][half][0], s[j][half][NPI - 1], p), p, fp.half,
+                                  out[j][half][NPO - 1][0], out[j][half][NPO - 1][NL - 1], e);
+                }
             }
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         char* sbase = b.p[T.s[j].buf] + T.s[j].off + (int64_t)r * T.s[j].ld + c;
+        const int nplanes = !CPLX ? 1 : (j == 2 ? fp.npo : 3);
 #pragma unroll
         for (int half = 0; half < 2; ++half)
 #pragma unroll
             for (int q = 0; q < NPO; ++q)
 #pragma unroll
                 for (int l = 0; l < NL; ++l) {
+                    if (q >= nplanes) continue;
                     char* dst = sbase + (int64_t)(q * NL + l) * T.s[j].ps + half * hw;
                     if (VEC == 16)
                         *reinterpret_cast<int4*>(dst) =
@@ -642,6 +650,58 @@ __global__ void __launch_bounds__(256) condition_t(const CondTask* tasks, Bases 
     }
 }
 
+// 2M base case: tile (R, C), R >= C, of 64 x 64 of a leaf's lower triangle, one
+// workgroup of 256 threads (row tr, 16 columns), 16-element vector loads and
+// stores; the mirrored tile of H is read transposed through LDS.
+template <typename RT, typename OT>
+__global__ void __launch_bounds__(256) herk2m_combine(const Herk2mTask* tasks, Bases b, FieldParams fp)
+{
+    constexpr int TS = 64, V = 16;
+    __shared__ int32_t ht[TS][TS + 1];
+    const Herk2mTask& T = tasks[blockIdx.y];
+    const int n = T.n, nt = (n + TS - 1) / TS;
+    const int t = blockIdx.x;
+    int R = (int)((sqrtf(8.f * t + 1.f) - 1.f) * 0.5f);
+    while ((R + 1) * (R + 2) / 2 <= t) ++R;
+    while (R * (R + 1) / 2 > t) --R;
+    const int C = t - R * (R + 1) / 2;
+    if (R >= nt) return;
+    const int p = fp.p;
+    const int tr = threadIdx.x >> 2, tc = (threadIdx.x & 3) * V;
+    const char* gb = b.p[T.g.buf] + T.g.off;
+    const char* hb = b.p[T.h.buf] + T.h.off;
+    // H on the mirrored tile (C, R): row C*TS + tr, columns R*TS + tc ..; the
+    // residue matrices have ld a multiple of 64, so whole 16-element groups are in
+    // bounds of the allocation (entries past n are never used)
+    {
+        const int mi = C * TS + tr;
+        RowV<RT, V> hm;
+        if (mi < n) hm.load(hb, T.h.ld, mi, R * TS + tc);
+        else hm.zero();
+#pragma unroll
+        for (int e = 0; e < V; ++e) ht[tr][tc + e] = hm[e];
+    }
+    __syncthreads();
+    const int i = R * TS + tr, j0 = C * TS + tc;
+    const int lim = min(n, T.nvalid);
+    if (i >= lim || j0 > i) return;
+    RowV<RT, V> g, h;
+    g.load(gb, T.g.ld, i, j0);
+    h.load(hb, T.h.ld, i, j0);
+    int32_t re[V], im[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        const int32_t hji = ht[tc + e][tr];  // H[j][i]
+        re[e] = sub_mod(sub_mod(g[e], h[e], p), hji, p);  // Re = G - H - H^T
+        im[e] = sub_mod(hji, h[e], p);                    // Im = H^T - H
+    }
+    const int want = min(V, min(lim, i + 1) - j0);  // columns j <= i inside the leaf
+    char* ore = b.p[T.out.buf] + T.out.off;
+    char* oim = b.p[T.out.buf2] + T.out.off2;
+    store_rowv<OT, V>(ore, (int64_t)i * T.out.ld + j0, re, want);
+    store_rowv<OT, V>(oim, (int64_t)i * T.out.ld + j0, im, want);
+}
+
 // C <- alpha X + beta C on the lower triangle; one thread per 8 columns of a row.
 template <typename RT, typename OT>
 __global__ void __launch_bounds__(256) update_c(const UpdateTask* tasks, Bases b, FieldParams fp)
@@ -809,6 +869,36 @@ int launch_condition_trans(const CondTask* d_tasks, int ntasks, int max_tiles, i
     default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();
+}
+
+template <typename RT>
+static int launch_herk2m_rt(dim3 g, hipStream_t s, const Herk2mTask* d, int out_dt, const Bases& b,
+                            const FieldParams& fp)
+{
+    switch (out_dt) {
+    case DT_U8: hipLaunchKernelGGL((herk2m_combine<RT, uint8_t>), g, dim3(256), 0, s, d, b, fp); break;
+    case DT_U16: hipLaunchKernelGGL((herk2m_combine<RT, uint16_t>), g, dim3(256), 0, s, d, b, fp); break;
+    case DT_I32: hipLaunchKernelGGL((herk2m_combine<RT, int32_t>), g, dim3(256), 0, s, d, b, fp); break;
+    case DT_I64: hipLaunchKernelGGL((herk2m_combine<RT, int64_t>), g, dim3(256), 0, s, d, b, fp); break;
+    case DT_F64: hipLaunchKernelGGL((herk2m_combine<RT, double>), g, dim3(256), 0, s, d, b, fp); break;
+    default: return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_herk2m(const Herk2mTask* d_tasks, int ntasks, int max_n, int res_dt, int out_dt,
+                  const Bases& b, const FieldParams& fp, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if (ntasks <= 0 || max_n <= 0) return 0;
+    const int nt = (max_n + 63) / 64;
+    const dim3 g((unsigned)(nt * (nt + 1) / 2), ntasks);
+    switch (res_dt) {
+    case DT_U8: return launch_herk2m_rt<uint8_t>(g, s, d_tasks, out_dt, b, fp);
+    case DT_U16: return launch_herk2m_rt<uint16_t>(g, s, d_tasks, out_dt, b, fp);
+    case DT_I32: return launch_herk2m_rt<int32_t>(g, s, d_tasks, out_dt, b, fp);
+    default: return (int)hipErrorInvalidValue;
+    }
 }
 
 template <typename RT>

@@ -101,6 +101,8 @@ struct FieldParams {
     int32_t cplx;      // 1 for F_p[i]
     double inv_p;      // 1.0 / p
     int32_t alpha, beta;  // C <- alpha X + beta C (canonical) in the update pass
+    int32_t npo;          // complex carriers: 4 = planes re, im, -re and re + im (2M base case)
+    int32_t pad_;
 };
 
 // ---- tasks ----------------------------------------------------------------
@@ -160,6 +162,15 @@ struct CondTask {
     int32_t trans, pad_;
 };
 
+// 2M base case of a Hermitian leaf (Algorithm 3 with epsilon = 1): from the real
+// residues G = (Xr + Xi)(Xr + Xi)^T (lower triangle) and H = Xr Xi^T (whole),
+// Low(X X^H) = Low(G - H - H^T) + i Low(H^T - H) into out (rows and columns
+// >= nvalid are not written).
+struct Herk2mTask {
+    ResRef g, h, out;
+    int32_t n, nvalid;
+};
+
 // Final update C <- alpha X + beta C on the lower triangle of an n x n result:
 // X is the product's residues (workspace), C the caller's matrix.
 struct UpdateTask {
@@ -176,6 +187,8 @@ int launch_condition(const CondTask* d_tasks, int ntasks, int max_blocks, int dt
 // one launch for every task with trans = 1 (the others go to launch_condition)
 int launch_condition_trans(const CondTask* d_tasks, int ntasks, int max_tiles, int dt_in, const Bases& b,
                            const FieldParams& fp, int carrier, int32_t* d_err, void* stream);
+int launch_herk2m(const Herk2mTask* d_tasks, int ntasks, int max_n, int res_dt, int out_dt,
+                  const Bases& b, const FieldParams& fp, void* stream);
 int launch_update(const UpdateTask* d_tasks, int ntasks, int max_n, int x_dt, int c_dt, const Bases& b,
                   const FieldParams& fp, void* stream);
 int launch_preadd(const PreaddTask* d_tasks, int ntasks, int h, int w, const Bases& b,

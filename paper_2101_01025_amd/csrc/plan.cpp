@@ -48,9 +48,11 @@ struct Builder {
     Plan& pl;
     int esize;   // carrier element size in bytes
     int npo;     // planes per carrier matrix: re, or re, im, -re
+    int npo_leaf;  // planes of carriers that feed base cases (re + im added for 2M)
     int rdt;     // residue storage of products
     int rsize;
     int bt;      // product tile edge
+    int bt_r;    // tile edge of the real launch of the 2M base case
     int64_t ws = 0;
 
     int64_t alloc(int64_t bytes)
@@ -59,14 +61,24 @@ struct Builder {
         ws += round_up(std::max<int64_t>(bytes, 1), 256);
         return o;
     }
-    CarRef new_car(int64_t rows, int64_t cols)
+    CarRef new_car(int64_t rows, int64_t cols, int planes = 0)
     {
         CarRef c;
         c.buf = BUF_WS;
         c.ld = (int32_t)cols;
         c.ps = round_up(rows * cols * esize, 256);
-        c.off = alloc(c.ps * npo * pl.nl);
+        c.off = alloc(c.ps * (planes ? planes : npo) * pl.nl);
         return c;
+    }
+    // one plane of residues (the real products of the 2M base case)
+    ResRef new_res_real(int64_t h)
+    {
+        ResRef r;
+        r.buf = r.buf2 = BUF_WS;
+        r.ld = (int32_t)round_up(h, 64);
+        r.dt = rdt;
+        r.off = r.off2 = alloc(h * r.ld * rsize);
+        return r;
     }
     ResRef new_res(int64_t h)
     {
@@ -110,6 +122,29 @@ struct Builder {
         pl.gemm.push_back(g);
         pl.gemm_aonly.push_back(aonly ? 1 : 0);
         pl.max_k = std::max(pl.max_k, K);
+        // real multiply-accumulates (a complex task is four real products)
+        pl.products_macs += (syrk ? M * (M + 1) / 2 * K : M * N * K) * (pl.cplx ? 4 : 1);
+    }
+    // A real product of the 2M base case: sub-planes x.off + l * x.ps (limbs).
+    void add_gemm_real(const CarRef& x, const CarRef& z, const ResRef& c, int64_t M, int64_t N,
+                       int64_t K, bool syrk)
+    {
+        GemmTask g{};
+        g.x = x;
+        g.z = z;
+        g.c = c;
+        g.M = (int32_t)M;
+        g.N = (int32_t)N;
+        g.K = (int32_t)K;
+        g.syrk = syrk ? 1 : 0;
+        g.kvalid = (int32_t)K;
+        g.tiles_m = (int32_t)((M + bt_r - 1) / bt_r);
+        g.tiles_n = (int32_t)((N + bt_r - 1) / bt_r);
+        const int64_t ea = (pl.nl - 1) * x.ps + (int64_t)bt_r * x.ld + K;
+        const int64_t eb = (pl.nl - 1) * z.ps + (int64_t)bt_r * z.ld + K;
+        if (ea >= (1ll << 31) || eb >= (1ll << 31)) pl.status = FFA_EUNSUPPORTED;
+        pl.gemm_r.push_back(g);
+        pl.max_k = std::max(pl.max_k, K);
         pl.products_macs += syrk ? M * (M + 1) / 2 * K : M * N * K;
     }
     // One node of the recursion: a is rows x cols, its result goes to c.
@@ -118,13 +153,32 @@ struct Builder {
               int64_t nvalid, bool aonly)
     {
         if (level == pl.levels) {
+            if (pl.herk2m) {
+                // Algorithm 3 with epsilon = 1: G = (Xr + Xi)(Xr + Xi)^T, H = Xr Xi^T
+                CarRef re = a, im = a, sum = a;
+                im.off += pl.nl * a.ps;
+                sum.off += 3 * pl.nl * a.ps;
+                const ResRef G = new_res_real(rows), H = new_res_real(rows);
+                add_gemm_real(sum, sum, G, rows, rows, cols, true);
+                add_gemm_real(re, im, H, rows, rows, cols, false);
+                Herk2mTask t{};
+                t.g = G;
+                t.h = H;
+                t.out = c;
+                t.n = (int32_t)rows;
+                t.nvalid = (int32_t)nvalid;
+                pl.h2m.push_back(t);
+                pl.h2m_max_n = std::max<int>(pl.h2m_max_n, (int)rows);
+                return;
+            }
             add_gemm(a, a, c, rows, rows, cols, true, aonly);
             return;
         }
         const int64_t h = rows / 2, w = cols / 2;
         PreaddTask pt{};
         pt.a = a;
-        for (int j = 0; j < 4; ++j) pt.s[j] = new_car(h, w);
+        // S3 feeds the base case P5 (and, below, further leaves)
+        for (int j = 0; j < 4; ++j) pt.s[j] = new_car(h, w, j == 2 ? npo_leaf : npo);
         pt.h = (int32_t)h;
         pt.w = (int32_t)w;
         pl.pre[level].push_back(pt);
@@ -192,19 +246,22 @@ Common common_setup(uint32_t p, int herm, int dA, int dC, const ffa_opts& o)
     fp.nl = cm.nl;
     fp.cplx = herm ? 1 : 0;
     fp.inv_p = 1.0 / (double)p;
+    fp.npo = herm ? 3 : 1;
     return cm;
 }
 
 // Built-in recursion cutoffs (measured on MI355X: one level wins at n = 16384 for
 // the INT8 carriers, four levels at n = 8192 for fp64, one level at n = 4096 for F_p[i]).
-int default_cutoff(int carrier, int nl, int cplx)
+int default_cutoff(int carrier, int nl, int cplx, bool herk2m)
 {
     if (carrier == CAR_F64) return 512;
-    if (cplx) return 2048;
+    // F_p[i]: with the 2M base case (1.5 n^2 k real products) one level of Algorithm 1,
+    // whose P3, P4 are complex products of four real ones, costs 1.04x more products
+    if (cplx) return herk2m ? (1 << 30) : 2048;
     return 8192;
 }
 
-int choose_levels(int64_t n, int64_t k, const ffa_opts& o, int carrier, int nl, int cplx)
+int choose_levels(int64_t n, int64_t k, const ffa_opts& o, int carrier, int nl, int cplx, bool herk2m)
 {
     if (n < 2 || k == 0) return 0;
     if (o.algo == FFA_ALGO_CLASSICAL) return 0;
@@ -212,7 +269,7 @@ int choose_levels(int64_t n, int64_t k, const ffa_opts& o, int carrier, int nl, 
     if (o.levels >= 0) {
         L = o.levels;
     } else {
-        const int64_t cut = o.cutoff > 0 ? o.cutoff : default_cutoff(carrier, nl, cplx);
+        const int64_t cut = o.cutoff > 0 ? o.cutoff : default_cutoff(carrier, nl, cplx, herk2m);
         L = 0;
         for (int64_t m = n; m > cut && L < 10; m = (m + 1) / 2) ++L;
         if (o.algo == FFA_ALGO_RECURSIVE && L == 0) L = 1;
@@ -245,7 +302,8 @@ int check_bound(const Plan& pl)
 // XCD with the least work so far (workgroup b runs on XCD b mod 8), and the
 // schedule interleaves the eight per-XCD lists; shorter lists are padded with
 // idle entries.
-int build_schedule(const Plan& pl, size_t first, size_t last, std::vector<TileEnt>& sched)
+int build_schedule(const std::vector<GemmTask>& tasks, bool cplx, size_t first, size_t last,
+                   std::vector<TileEnt>& sched)
 {
     constexpr int GR = 4, GC = 8, NX = 8;
     struct Group {
@@ -255,8 +313,8 @@ int build_schedule(const Plan& pl, size_t first, size_t last, std::vector<TileEn
     std::vector<Group> groups;
     int tiles = 0;
     for (size_t t = first; t < last; ++t) {
-        const GemmTask& g = pl.gemm[t];
-        const double kcost = (double)g.K * (pl.cplx ? 2 : 1) + 64.0;
+        const GemmTask& g = tasks[t];
+        const double kcost = (double)g.K * (cplx ? 2 : 1) + 64.0;
         for (int bi = 0; bi < g.tiles_m; bi += GR) {
             const int bj_end = g.syrk ? std::min(bi + GR, g.tiles_n) : g.tiles_n;
             for (int bj = 0; bj < bj_end; bj += GC) {
@@ -297,7 +355,8 @@ void schedule_products(Plan& pl)
 {
     if (!pl.fork) {
         pl.gemm_split = (int)pl.gemm.size();
-        pl.total_tiles = build_schedule(pl, 0, pl.gemm.size(), pl.sched);
+        pl.total_tiles = build_schedule(pl.gemm, pl.cplx, 0, pl.gemm.size(), pl.sched);
+        pl.total_tiles += build_schedule(pl.gemm_r, false, 0, pl.gemm_r.size(), pl.sched_r);
         pl.sched2.clear();
         return;
     }
@@ -308,8 +367,8 @@ void schedule_products(Plan& pl)
     pl.gemm.insert(pl.gemm.end(), g2.begin(), g2.end());
     pl.gemm_aonly.assign(pl.gemm_split, 1);
     pl.gemm_aonly.resize(pl.gemm.size(), 0);
-    pl.total_tiles = build_schedule(pl, 0, pl.gemm_split, pl.sched);
-    pl.total_tiles += build_schedule(pl, pl.gemm_split, pl.gemm.size(), pl.sched2);
+    pl.total_tiles = build_schedule(pl.gemm, pl.cplx, 0, pl.gemm_split, pl.sched);
+    pl.total_tiles += build_schedule(pl.gemm, pl.cplx, pl.gemm_split, pl.gemm.size(), pl.sched2);
 }
 
 void size_grids(Plan& pl)
@@ -387,7 +446,7 @@ int add_problem(Plan& pl, Builder& B, const Problem& pr, int levels, bool allow_
         a.ld = (int32_t)pr.lda;
         pl.direct = true;
     } else {
-        a = B.new_car(npad, kpad);
+        a = B.new_car(npad, kpad, B.npo_leaf);
         CondTask ct{};
         ct.n = (int32_t)pr.n;
         ct.k = (int32_t)pr.k;
@@ -417,11 +476,7 @@ int add_problem(Plan& pl, Builder& B, const Problem& pr, int levels, bool allow_
     if (pl.carrier == CAR_F64) pl.max_abs = std::max<int>(pl.max_abs, direct ? (int)pl.fp.p - 1 : pl.fp.half);
     else pl.max_abs = std::max<int>(pl.max_abs, pl.nl == 1 ? pl.fp.half : 32896);
     const ResRef c = root_output(pl, B, pr);
-    if (levels == 0) {
-        B.add_gemm(a, a, c, pr.n, pr.n, kpad, true, true);
-    } else {
-        B.node(0, a, npad, kpad, c, pr.n, true);
-    }
+    B.node(0, a, npad, kpad, c, pr.n, true);  // with no recursion: the base case itself
     return FFA_OK;
 }
 
@@ -440,6 +495,11 @@ void choose_kernel(Plan& pl, int64_t max_dim)
     pl.gemm_cfg = cfg;
     pl.tile = gemm_i8_config_tile(cfg);
     pl.ktile = gemm_i8_config_ktile(cfg);
+    if (pl.herk2m) {
+        // the real launch of the 2M base case; K is padded for both k-tiles
+        pl.gemm_cfg_r = gemm_i8_default_config(pl.nl, 0, max_dim);
+        pl.ktile = std::max(pl.ktile, gemm_i8_config_ktile(pl.gemm_cfg_r));
+    }
 }
 
 // Whether a problem's products can read the caller's uint16 rows directly: two
@@ -457,9 +517,11 @@ Builder make_builder(Plan& pl)
     Builder B{pl};
     B.esize = pl.carrier == CAR_F64 ? 8 : 1;
     B.npo = pl.cplx ? 3 : 1;
+    B.npo_leaf = pl.herk2m ? 4 : B.npo;
     B.rdt = pl.fp.p < 256 ? DT_U8 : (pl.fp.p < 65536 ? DT_U16 : DT_I32);
     B.rsize = dtype_size(B.rdt);
     B.bt = pl.tile;
+    B.bt_r = pl.herk2m ? gemm_i8_config_tile(pl.gemm_cfg_r) : pl.tile;
     return B;
 }
 
@@ -486,7 +548,10 @@ Plan make_plan(const Problem& pr)
     pl.fp.alpha = (int32_t)pr.alpha;
     pl.fp.beta = (int32_t)pr.beta;
     if (pr.n == 0) return pl;
-    pl.levels = choose_levels(pr.n, pr.k, o, pl.carrier, pl.nl, pl.cplx);
+    if (o.herk_base < FFA_HERK_AUTO || o.herk_base > FFA_HERK_4M) { pl.status = FFA_EINVAL; return pl; }
+    pl.herk2m = pl.cplx && pl.carrier == CAR_I8 && o.herk_base != FFA_HERK_4M;
+    pl.fp.npo = pl.herk2m ? 4 : 3;
+    pl.levels = choose_levels(pr.n, pr.k, o, pl.carrier, pl.nl, pl.cplx, pl.herk2m);
     pl.pre.assign(pl.levels, {});
     pl.post.assign(pl.levels, {});
     pl.kernel_req = o.kernel;
@@ -512,7 +577,7 @@ Plan make_plan(const Problem& pr)
     if (pl.status != FFA_OK && pl.status != FFA_EBOUND && pl.status != FFA_EUNSUPPORTED) return pl;
     if (pl.status == FFA_OK) pl.status = check_bound(pl);
     pl.zero_fill = pr.k == 0;
-    pl.fork = o.streams == FFA_STREAMS_TWO && pl.levels > 0;
+    pl.fork = o.streams == FFA_STREAMS_TWO && pl.levels > 0 && !pl.herk2m;
     size_grids(pl);
     return pl;
 }
@@ -536,7 +601,7 @@ Plan make_batch_plan(const std::vector<Problem>& prs)
             pl.status = FFA_EINVAL;
             return pl;
         }
-        L[i] = choose_levels(prs[i].n, prs[i].k, p0.opts, pl.carrier, pl.nl, pl.cplx);
+        L[i] = choose_levels(prs[i].n, prs[i].k, p0.opts, pl.carrier, pl.nl, pl.cplx, false);
         maxL = std::max(maxL, L[i]);
     }
     pl.levels = maxL;
@@ -612,6 +677,9 @@ std::vector<char> pack_tables(Plan& pl)
     pl.off_sched = put(pl.sched.data(), pl.sched.size() * sizeof(TileEnt));
     pl.off_sched2 = put(pl.sched2.data(), pl.sched2.size() * sizeof(TileEnt));
     pl.off_upd = put(pl.upd.data(), pl.upd.size() * sizeof(UpdateTask));
+    pl.off_gemm_r = put(pl.gemm_r.data(), pl.gemm_r.size() * sizeof(GemmTask));
+    pl.off_sched_r = put(pl.sched_r.data(), pl.sched_r.size() * sizeof(TileEnt));
+    pl.off_h2m = put(pl.h2m.data(), pl.h2m.size() * sizeof(Herk2mTask));
     pl.blob_bytes = (int64_t)blob.size();
     return blob;
 }
@@ -632,14 +700,14 @@ std::string describe(const Plan& pl)
              "\"ws_bytes\":%lld,\"conditioning\":%zu,\"preadd_tasks\":%s,\"postadd_tasks\":%s,"
              "\"gemm_tasks\":%zu,\"tiles\":%d,\"blocks\":%zu,\"cfg\":%d,\"tile\":%d,"
              "\"macs\":%lld,\"ykind\":%d,\"ya\":%d,\"yb\":%d,\"src\":\"%s\",\"streams\":%d,"
-             "\"blocks_a_only\":%zu}",
+             "\"blocks_a_only\":%zu,\"herk_base\":\"%s\",\"real_tasks\":%zu}",
              pl.status, pl.levels, pl.carrier == CAR_F64 ? "f64" : "int8", pl.nl, pl.cplx,
              (long long)pl.npad, (long long)pl.kpad, pl.direct ? 1 : 0, pl.max_abs,
              (long long)pl.max_k, (long long)pl.ws_bytes, pl.cond.size(), pre.c_str(), post.c_str(),
              pl.gemm.size(), pl.total_tiles, pl.sched.size() + pl.sched2.size(), pl.gemm_cfg, pl.tile,
              (long long)pl.products_macs, pl.fp.ykind, pl.fp.ya,
              pl.fp.yb, pl.gemm_src == SRC_RAW_U16 ? "raw_u16" : "carrier", pl.fork ? 2 : 1,
-             pl.sched.size());
+             pl.sched.size(), pl.herk2m ? "2m" : (pl.cplx ? "4m" : "none"), pl.gemm_r.size());
     return buf;
 }
 

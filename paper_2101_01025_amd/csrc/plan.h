@@ -39,6 +39,14 @@ struct Plan {
     std::vector<CondTask> cond;
     int cond_max_blocks = 0;
     bool cond_trans = false;           // conditioning reads the transpose (tiles of 64 x 64)
+    // 2M Hermitian base case: real products (their own launch and schedule) and
+    // the combination into each leaf's complex result
+    bool herk2m = false;
+    std::vector<GemmTask> gemm_r;
+    std::vector<TileEnt> sched_r;
+    int gemm_cfg_r = 0;
+    std::vector<Herk2mTask> h2m;
+    int h2m_max_n = 0;
     std::vector<UpdateTask> upd;       // final C <- alpha X + beta C
     int upd_max_n = 0;
     std::vector<std::vector<PreaddTask>> pre;   // per level, top-down
@@ -70,6 +78,7 @@ struct Plan {
     void* d_blob = nullptr;
     int64_t blob_bytes = 0;
     int64_t off_cond = 0, off_gemm = 0, off_sched = 0, off_sched2 = 0, off_upd = 0;
+    int64_t off_gemm_r = 0, off_sched_r = 0, off_h2m = 0;
     std::vector<int64_t> off_pre, off_post;
 };
 

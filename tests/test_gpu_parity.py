@@ -161,19 +161,27 @@ def check_herk(Ar, Ai, p, dt, **kw):
         assert (gr[~low] == np.int64(SENTINEL[dt])).all() and (gi[~low] == np.int64(SENTINEL[dt])).all()
 
 
+@pytest.mark.parametrize("base", ["2m", "4m"])
 @pytest.mark.parametrize("levels", [0, 1, 2])
 @pytest.mark.parametrize("shape", [(130, 70), (257, 200)])
-def test_herk_p65519(levels, shape):
+def test_herk_p65519(levels, shape, base):
+    """Base case by the 2M method (Algorithm 3, one real SYRK + one real GEMM) or by
+    the four real products of the complex kernel."""
+    ffa = _ffa()
     n, k = shape
     Ar, Ai = si.complex_residues(n, k, 65519, 400 + n)
-    check_herk(Ar, Ai, 65519, torch.uint16, levels=levels)
+    hb = ffa.HERK_2M if base == "2m" else ffa.HERK_4M
+    check_herk(Ar, Ai, 65519, torch.uint16, levels=levels, herk_base=hb)
 
 
+@pytest.mark.parametrize("base", ["2m", "4m"])
 @pytest.mark.parametrize("p", [251, 7])
-def test_herk_single_limb(p):
+def test_herk_single_limb(p, base):
+    ffa = _ffa()
     Ar, Ai = si.complex_residues(200, 130, p, 500 + p)
+    hb = ffa.HERK_2M if base == "2m" else ffa.HERK_4M
     for levels in (0, 1, 2):
-        check_herk(Ar, Ai, p, torch.int64, levels=levels)
+        check_herk(Ar, Ai, p, torch.int64, levels=levels, herk_base=hb)
 
 
 # ------------------------------------------------------------------ degenerate cases, errors

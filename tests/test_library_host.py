@@ -112,6 +112,25 @@ def test_plan_product_groups_and_streams():
     assert ffa.plan_describe(10, 10, 251, opts=ffa.make_opts(operands=3))[0] == ffa.EINVAL
 
 
+def test_plan_herk_base_case_2m():
+    # no recursion: 2M = one real SYRK (n(n+1)/2 k) + one real GEMM (n^2 k); 4M = four
+    # real products on the lower triangle
+    n, k = 512, 384
+    st, d = ffa.plan_describe(n, k, 65519, hermitian=True, dA=ffa.U16, dC=ffa.U16,
+                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
+    assert st == 0 and d["herk_base"] == "2m" and d["real_tasks"] == 2 and d["gemm_tasks"] == 0
+    assert d["macs"] == n * (n + 1) // 2 * k + n * n * k
+    st, d = ffa.plan_describe(n, k, 65519, hermitian=True, dA=ffa.U16, dC=ffa.U16,
+                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL, herk_base=ffa.HERK_4M))
+    assert st == 0 and d["herk_base"] == "4m" and d["real_tasks"] == 0
+    assert d["macs"] == 4 * n * (n + 1) // 2 * k
+    # one level: three 2M leaves, the general products P3, P4 stay complex
+    st, d = ffa.plan_describe(n, k, 65519, hermitian=True, dA=ffa.U16, dC=ffa.U16,
+                              opts=ffa.make_opts(levels=1))
+    assert st == 0 and d["real_tasks"] == 6 and d["gemm_tasks"] == 2
+    assert ffa.plan_describe(n, k, 65519, hermitian=True, opts=ffa.make_opts(herk_base=3))[0] == ffa.EINVAL
+
+
 def test_plan_macs_follow_recursion():
     # products MACs = 3^l leaf SYRKs + 2 * 3^i general products of level i
     for L in range(0, 4):
