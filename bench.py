@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="syrk_p251_int8", choices=sorted(WORKLOADS))
     ap.add_argument("--levels", type=int, default=-1, help="recursion depth (-1: library default)")
+    ap.add_argument("--kernel", type=int, default=0,
+                    help="INT8 product-kernel configuration + 1 for both plans (0: built-in choice)")
     ap.add_argument("--herk-base", choices=["auto", "2m", "4m"], default="auto",
                     help="Hermitian base case: the 2M method or four real products")
     ap.add_argument("--streams", choices=["auto", "one", "two"], default="auto",
@@ -362,13 +364,14 @@ def main():
 
     streams = {"auto": ffa.STREAMS_AUTO, "one": ffa.STREAMS_ONE, "two": ffa.STREAMS_TWO}[args.streams]
     hb = {"auto": ffa.HERK_AUTO, "2m": ffa.HERK_2M, "4m": ffa.HERK_4M}[args.herk_base]
-    opts = ffa.make_opts(levels=args.levels, streams=streams, herk_base=hb)
+    opts = ffa.make_opts(levels=args.levels, streams=streams, herk_base=hb, kernel=args.kernel)
     dA_code = ffa._dtype_code(A)
     _, plan = ffa.plan_describe(n, k, p, hermitian=herm, dA=dA_code, dC=ffa._dtype_code(C, True),
                                 opts=opts)
     # comparator: the plain classical product; over F_p[i] that is four real products per
     # complex product (the 2M base case is part of the method under test)
-    classical = ffa.make_opts(algo=ffa.ALGO_CLASSICAL, herk_base=ffa.HERK_4M if herm else hb)
+    classical = ffa.make_opts(algo=ffa.ALGO_CLASSICAL, herk_base=ffa.HERK_4M if herm else hb,
+                              kernel=args.kernel)
     plans = [opts] if args.no_classical else [opts, classical]
     res = timed_steps(ffa, torch, w, A, Ai, C, Ci, plans, args.steps, args.warmup)
     ms, phases, launches = res[0]

@@ -189,7 +189,8 @@ int ffa_profile_reset(ffa_ctx* ctx);
 
 /* Autotuner.  Times every candidate plan for this call (recursion depth 0..4 that
  * the sizes allow x carrier (INT8 limbs, and FP64 where its bound holds) x every
- * INT8 product-kernel configuration of the carrier) on the caller's own buffers
+ * INT8 product-kernel configuration of the carrier x operand source, raw uint16 rows
+ * where the planner allows them) on the caller's own buffers
  * with HIP events, `reps` timed calls each, and records the fastest for the shape
  * (n, k, p, formats) in the context: later calls with opts = NULL use it, and
  * so do other shapes of the same size class (n and k within the same half-octave)
@@ -199,8 +200,9 @@ int ffa_profile_reset(ffa_ctx* ctx);
 int ffa_autotune_syrk(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p,
                       int dA, const void* A, int64_t lda, int dC, void* C, int64_t ldc,
                       int reps, ffa_opts* best, double* best_ms);
-/* Same for a batch plan: re-plans with each carrier, product-kernel configuration
- * and recursion cutoff (classical, 256, 384), keeps the fastest in the plan. */
+/* Same for a batch plan: re-plans with each carrier, product-kernel configuration,
+ * recursion cutoff (classical, 256, 384) and operand source (limb planes, or raw
+ * uint16 rows where the planner allows them), keeps the fastest in the plan. */
 int ffa_batch_autotune(ffa_batch* b, const void* A_packed, void* C_packed, int reps,
                        ffa_opts* best, double* best_ms);
 

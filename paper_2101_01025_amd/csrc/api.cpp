@@ -791,14 +791,18 @@ int ffa_autotune_syrk(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA, co
         if (cprobe.status) continue;
         for (int L = 0; L <= 4; ++L) {
             if (L > 0 && ((n >> L) < 64 || k == 0)) break;
-            for (int kc : kernel_candidates(cprobe)) {
+            for (int kc : kernel_candidates(cprobe))
+            for (int opr : {FFA_OPERANDS_PLANES, FFA_OPERANDS_RAW}) {
                 ffa_opts o = default_opts();
                 o.algo = L == 0 ? FFA_ALGO_CLASSICAL : FFA_ALGO_RECURSIVE;
                 o.levels = L;
                 o.kernel = kc;
                 o.carrier = car;
+                o.operands = opr;
                 Problem pr = base;
                 pr.opts = o;
+                // raw operands only where the planner takes them
+                if (opr == FFA_OPERANDS_RAW && make_plan(pr).gemm_src != SRC_RAW_U16) continue;
                 double ms = 0;
                 const int st =
                     time_calls(ctx, reps, [&] { return run_call(ctx, pr, A, nullptr, C, nullptr); }, &ms);
@@ -834,19 +838,25 @@ int ffa_batch_autotune(ffa_batch* b, const void* A_packed, void* C_packed, int r
         const Plan cprobe = make_batch_plan(cprs);
         if (cprobe.status) continue;
         for (int kc : kernel_candidates(cprobe)) {
-            for (int64_t cut : cutoffs) {
+            for (int64_t cut : cutoffs)
+            for (int opr : {FFA_OPERANDS_PLANES, FFA_OPERANDS_RAW}) {
                 std::vector<Problem> prs = cprs;
                 for (auto& q : prs) {
                     q.opts.kernel = kc;
                     q.opts.cutoff = (int32_t)cut;
                     q.opts.levels = -1;
                     q.opts.algo = cut == 0 ? FFA_ALGO_CLASSICAL : FFA_ALGO_AUTO;
+                    q.opts.operands = opr;
                 }
                 ffa_batch trial;
                 trial.ctx = c;
                 trial.prs = prs;
                 trial.plan = make_batch_plan(prs);
                 if (trial.plan.status) continue;
+                if (opr == FFA_OPERANDS_RAW && trial.plan.gemm_src != SRC_RAW_U16) {
+                    free_tables(trial.plan);
+                    continue;
+                }
                 if (trial.plan.a_total != b->plan.a_total || trial.plan.c_total != b->plan.c_total) continue;
                 int st = batch_workspace(&trial);
                 if (!st) st = upload_tables(c, trial.plan);

@@ -78,16 +78,28 @@ __device__ __forceinline__ bool load_input16(const char* base, int64_t idx, int 
     return ok;
 }
 
+// The task owning block blk of a one-dimensional grid (tasks in order of blk0).
+__device__ __forceinline__ int cond_task_of(const CondTask* tasks, int ntasks, int blk)
+{
+    int lo = 0, hi = ntasks - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tasks[mid].blk0 <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // One thread converts 16 consecutive columns of one row into every carrier
 // sub-plane (limbs of re, and of im and -re for F_p[i]).
 template <typename IT, int NL, int CPLX>
-__global__ void __launch_bounds__(256) condition_i8(const CondTask* tasks, Bases b, FieldParams fp,
-                                                    int32_t* err)
+__global__ void __launch_bounds__(256) condition_i8(const CondTask* tasks, int ntasks, Bases b,
+                                                    FieldParams fp, int32_t* err)
 {
     constexpr int VEC = 16;
-    const CondTask& t = tasks[blockIdx.y];
+    const CondTask& t = tasks[cond_task_of(tasks, ntasks, (int)blockIdx.x)];
     const int gpr = t.kpad / VEC;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t idx = (int64_t)((int)blockIdx.x - t.blk0) * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)t.npad * gpr) return;
     const int r = (int)(idx / gpr), c0 = (int)(idx % gpr) * VEC;
     const int p = fp.p;
@@ -132,11 +144,11 @@ __global__ void __launch_bounds__(256) condition_i8(const CondTask* tasks, Bases
                     *reinterpret_cast<const int4*>(out[q][l]);
 }
 
-__global__ void __launch_bounds__(256) condition_f64(const CondTask* tasks, Bases b, FieldParams fp,
-                                                     int32_t* err)
+__global__ void __launch_bounds__(256) condition_f64(const CondTask* tasks, int ntasks, Bases b,
+                                                     FieldParams fp, int32_t* err)
 {
-    const CondTask& t = tasks[blockIdx.y];
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const CondTask& t = tasks[cond_task_of(tasks, ntasks, (int)blockIdx.x)];
+    const int64_t idx = (int64_t)((int)blockIdx.x - t.blk0) * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)t.npad * t.kpad) return;
     const int r = (int)(idx / t.kpad), c = (int)(idx % t.kpad);
     int32_t v = 0;
@@ -741,35 +753,35 @@ int launch_zero_flag(int32_t* d_flag, void* stream)
 }
 
 template <typename IT>
-static void launch_cond_typed(dim3 g, hipStream_t s, const CondTask* d_tasks, const Bases& b,
+static void launch_cond_typed(dim3 g, hipStream_t s, const CondTask* d_tasks, int ntasks, const Bases& b,
                               const FieldParams& fp, int32_t* d_err)
 {
     if (fp.nl == 1 && !fp.cplx)
-        hipLaunchKernelGGL((condition_i8<IT, 1, 0>), g, dim3(256), 0, s, d_tasks, b, fp, d_err);
+        hipLaunchKernelGGL((condition_i8<IT, 1, 0>), g, dim3(256), 0, s, d_tasks, ntasks, b, fp, d_err);
     else if (fp.nl == 2 && !fp.cplx)
-        hipLaunchKernelGGL((condition_i8<IT, 2, 0>), g, dim3(256), 0, s, d_tasks, b, fp, d_err);
+        hipLaunchKernelGGL((condition_i8<IT, 2, 0>), g, dim3(256), 0, s, d_tasks, ntasks, b, fp, d_err);
     else if (fp.nl == 1)
-        hipLaunchKernelGGL((condition_i8<IT, 1, 1>), g, dim3(256), 0, s, d_tasks, b, fp, d_err);
+        hipLaunchKernelGGL((condition_i8<IT, 1, 1>), g, dim3(256), 0, s, d_tasks, ntasks, b, fp, d_err);
     else
-        hipLaunchKernelGGL((condition_i8<IT, 2, 1>), g, dim3(256), 0, s, d_tasks, b, fp, d_err);
+        hipLaunchKernelGGL((condition_i8<IT, 2, 1>), g, dim3(256), 0, s, d_tasks, ntasks, b, fp, d_err);
 }
 
-int launch_condition(const CondTask* d_tasks, int ntasks, int max_blocks, int dt_in, const Bases& b,
+int launch_condition(const CondTask* d_tasks, int ntasks, int nblocks, int dt_in, const Bases& b,
                      const FieldParams& fp, int carrier, int32_t* d_err, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
-    if (ntasks <= 0 || max_blocks <= 0) return 0;
-    dim3 g(max_blocks, ntasks);
+    if (ntasks <= 0 || nblocks <= 0) return 0;
+    const dim3 g(nblocks);
     if (carrier == CAR_F64) {
-        hipLaunchKernelGGL(condition_f64, g, dim3(256), 0, s, d_tasks, b, fp, d_err);
+        hipLaunchKernelGGL(condition_f64, g, dim3(256), 0, s, d_tasks, ntasks, b, fp, d_err);
     } else {
         switch (dt_in) {
-        case DT_I8C: launch_cond_typed<int8_t>(g, s, d_tasks, b, fp, d_err); break;
-        case DT_U8: launch_cond_typed<uint8_t>(g, s, d_tasks, b, fp, d_err); break;
-        case DT_U16: launch_cond_typed<uint16_t>(g, s, d_tasks, b, fp, d_err); break;
-        case DT_I32: launch_cond_typed<int32_t>(g, s, d_tasks, b, fp, d_err); break;
-        case DT_I64: launch_cond_typed<int64_t>(g, s, d_tasks, b, fp, d_err); break;
-        case DT_F64: launch_cond_typed<double>(g, s, d_tasks, b, fp, d_err); break;
+        case DT_I8C: launch_cond_typed<int8_t>(g, s, d_tasks, ntasks, b, fp, d_err); break;
+        case DT_U8: launch_cond_typed<uint8_t>(g, s, d_tasks, ntasks, b, fp, d_err); break;
+        case DT_U16: launch_cond_typed<uint16_t>(g, s, d_tasks, ntasks, b, fp, d_err); break;
+        case DT_I32: launch_cond_typed<int32_t>(g, s, d_tasks, ntasks, b, fp, d_err); break;
+        case DT_I64: launch_cond_typed<int64_t>(g, s, d_tasks, ntasks, b, fp, d_err); break;
+        case DT_F64: launch_cond_typed<double>(g, s, d_tasks, ntasks, b, fp, d_err); break;
         default: return (int)hipErrorInvalidValue;
         }
     }

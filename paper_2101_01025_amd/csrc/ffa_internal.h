@@ -159,7 +159,8 @@ struct CondTask {
     int32_t buf_re, buf_im;
     int64_t off_re, off_im;
     CarRef out;
-    int32_t trans, pad_;
+    int32_t trans;
+    int32_t blk0;  // first block of this task in the one-dimensional grid of the launch
 };
 
 // 2M base case of a Hermitian leaf (Algorithm 3 with epsilon = 1): from the real
@@ -182,7 +183,8 @@ struct UpdateTask {
 // All return a hipError_t value cast to int.
 int launch_zero_flag(int32_t* d_flag, void* stream);
 // dt_in: the caller's input format (every task of a launch shares it)
-int launch_condition(const CondTask* d_tasks, int ntasks, int max_blocks, int dt_in, const Bases& b,
+// nblocks: total blocks of all tasks (task t owns blocks blk0 .. of the 1-D grid)
+int launch_condition(const CondTask* d_tasks, int ntasks, int nblocks, int dt_in, const Bases& b,
                      const FieldParams& fp, int carrier, int32_t* d_err, void* stream);
 // one launch for every task with trans = 1 (the others go to launch_condition)
 int launch_condition_trans(const CondTask* d_tasks, int ntasks, int max_tiles, int dt_in, const Bases& b,

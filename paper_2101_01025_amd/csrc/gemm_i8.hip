@@ -506,7 +506,10 @@ struct CfgInfo {
     X(9, 2, 0, 128, 2, 2, 128, 1)         \
     X(10, 1, 0, 256, 2, 4, 128, 2)        \
     X(11, 1, 0, 256, 2, 4, 64, 3)         \
-    X(12, 1, 0, 256, 4, 2, 64, 2)
+    X(12, 1, 0, 256, 4, 2, 64, 2)         \
+    X(13, 2, 0, 64, 2, 2, 128, 2)         \
+    X(14, 1, 0, 64, 2, 2, 128, 2)         \
+    X(15, 2, 0, 128, 2, 4, 128, 1)
 
 static CfgInfo cfg_info(int id)
 {

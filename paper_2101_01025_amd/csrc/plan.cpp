@@ -459,18 +459,21 @@ int add_problem(Plan& pl, Builder& B, const Problem& pr, int levels, bool allow_
         ct.off_re = ct.off_im = pr.a_off * in_size;
         ct.out = a;
         ct.trans = pr.trans;
-        pl.cond.push_back(ct);
-        int64_t blocks;
         if (pr.trans) {
-            // 64 x 64 tiles of the carrier
+            // 64 x 64 tiles of the carrier; grid (largest task, tasks)
             pl.cond_trans = true;
-            blocks = ((npad + 63) / 64) * ((kpad + 63) / 64);
+            const int64_t tiles = ((npad + 63) / 64) * ((kpad + 63) / 64);
+            if (tiles >= (1ll << 31)) return FFA_EINVAL;
+            pl.cond_max_blocks = (int)std::max<int64_t>(pl.cond_max_blocks, tiles);
         } else {
+            // blocks of 256 threads x 16 (fp64: 1) carrier columns, one grid for all tasks
             const int64_t vec = pl.carrier == CAR_F64 ? 1 : 16;
-            blocks = (npad * (kpad / vec) + 255) / 256;
+            const int64_t blocks = (npad * (kpad / vec) + 255) / 256;
+            if ((int64_t)pl.cond_max_blocks + blocks >= (1ll << 31)) return FFA_EINVAL;
+            ct.blk0 = pl.cond_max_blocks;
+            pl.cond_max_blocks += (int)blocks;
         }
-        if (blocks >= (1ll << 31)) return FFA_EINVAL;
-        pl.cond_max_blocks = (int)std::max<int64_t>(pl.cond_max_blocks, blocks);
+        pl.cond.push_back(ct);
     }
     // largest operand magnitude: centred carriers, except direct canonical fp64
     if (pl.carrier == CAR_F64) pl.max_abs = std::max<int>(pl.max_abs, direct ? (int)pl.fp.p - 1 : pl.fp.half);

@@ -37,7 +37,7 @@ struct Plan {
     int zero_fill = 0;                 // k == 0: the output is Low(0)
     // task tables
     std::vector<CondTask> cond;
-    int cond_max_blocks = 0;
+    int cond_max_blocks = 0;           // total blocks (transposed: blocks of the largest task)
     bool cond_trans = false;           // conditioning reads the transpose (tiles of 64 x 64)
     // 2M Hermitian base case: real products (their own launch and schedule) and
     // the combination into each leaf's complex result
