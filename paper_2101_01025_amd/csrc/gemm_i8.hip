@@ -51,18 +51,19 @@ __device__ __forceinline__ int swz(int r, int seg)
     return r * KT + ((seg ^ ((r / RPB) & (NSEG - 1))) << 4);
 }
 
-// Canonical residue of an int32 for p < 2^8 with full-rate 24-bit arithmetic:
-// x = hi 2^16 + lo, v = hi (2^16 mod p) + lo has |v| < 2^24 (exact in fp32), one
-// fp32 quotient within one of v / p, then a correction.  c16 = 2^16 mod p.
-__device__ __forceinline__ int32_t mod_small_p(int32_t x, int32_t p, int32_t c16, float inv_p)
+// Canonical residue of an int32 x (|x| < 2^31) for p < 2^8, in full-rate 32-bit
+// and 24-bit operations:
+//   v = (x >> 16) (2^16 mod p) + (x & 0xffff) + off, off = ceil(2^23 / p) p,
+// so 0 <= v < 2^24 is exact in fp32; q = floor(v inv_lo) with inv_lo a little
+// below 1/p is the quotient or one less, so r = v - q p lies in [0, 2p) and one
+// unsigned minimum finishes.
+__device__ __forceinline__ int32_t mod_small_p(int32_t x, int32_t p, int32_t c16, int32_t off, float inv_lo)
 {
-    const int32_t hi = x >> 16, lo = x & 0xffff;
-    const int32_t v = __mul24(hi, c16) + lo;
-    const int32_t q = (int32_t)floorf((float)v * inv_p);
-    int32_t r = v - __mul24(q, p);
-    r += (r < 0) ? p : 0;
-    r -= (r >= p) ? p : 0;
-    return r;
+    // (the mask tells the compiler that the product fits its 24-bit multiplier)
+    const int32_t v = (x >> 16) * (c16 & 0xff) + (x & 0xffff) + off;
+    const int32_t q = (int32_t)floorf((float)v * inv_lo);
+    const uint32_t r = (uint32_t)(v - __mul24(q, p));
+    return (int32_t)min(r, r - (uint32_t)p);
 }
 
 // The first lim (1 <= lim < 8) uint16 elements at byte offset off, element by
@@ -378,13 +379,14 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     // 8 (v / 4) + 4 (lane / 32) + v % 4; four consecutive registers are four
     // consecutive columns of one row of C.
     const int p = fp.p;
-    const float inv_pf = (float)fp.inv_p;
     const int32_t c16 = (int32_t)(65536 % p);
+    const int32_t moff = ((1 << 23) / p + 1) * p;                 // makes v non-negative
+    const float inv_lo = (float)(fp.inv_p * (1.0 - 1.0 / 4194304.0));  // below 1/p
     const bool syrk = T.syrk != 0;
     const int ldc = T.c.ld;
     const int rows_c = min(BT, M - row0), cols_c = min(BT, N - col0);
     auto residue = [&](int r, int m, int n, int v) -> int32_t {
-        if (NL == 1) return mod_small_p(acc[r][0][m][n][v], p, c16, inv_pf);  // one limb: p < 2^8
+        if (NL == 1) return mod_small_p(acc[r][0][m][n][v], p, c16, moff, inv_lo);  // one limb: p < 2^8
         double val = 65536.0 * (double)acc[r][0][m][n][v] + 256.0 * (double)acc[r][NACC - 2][m][n][v] +
                      (double)acc[r][NACC - 1][m][n][v];
         if (RAW) {
