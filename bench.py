@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--levels", type=int, default=-1, help="recursion depth (-1: library default)")
     ap.add_argument("--kernel", type=int, default=0,
                     help="INT8 product-kernel configuration + 1 for both plans (0: built-in choice)")
+    ap.add_argument("--general", choices=["auto", "classical", "winograd"], default="auto",
+                    help="general products P3, P4: one task, or one level of Strassen-Winograd")
     ap.add_argument("--herk-base", choices=["auto", "2m", "4m"], default="auto",
                     help="Hermitian base case: the 2M method or four real products")
     ap.add_argument("--streams", choices=["auto", "one", "two"], default="auto",
@@ -364,7 +366,10 @@ def main():
 
     streams = {"auto": ffa.STREAMS_AUTO, "one": ffa.STREAMS_ONE, "two": ffa.STREAMS_TWO}[args.streams]
     hb = {"auto": ffa.HERK_AUTO, "2m": ffa.HERK_2M, "4m": ffa.HERK_4M}[args.herk_base]
-    opts = ffa.make_opts(levels=args.levels, streams=streams, herk_base=hb, kernel=args.kernel)
+    gen = {"auto": ffa.GENERAL_AUTO, "classical": ffa.GENERAL_CLASSICAL,
+           "winograd": ffa.GENERAL_WINOGRAD}[args.general]
+    opts = ffa.make_opts(levels=args.levels, streams=streams, herk_base=hb, kernel=args.kernel,
+                         general=gen)
     dA_code = ffa._dtype_code(A)
     _, plan = ffa.plan_describe(n, k, p, hermitian=herm, dA=dA_code, dC=ffa._dtype_code(C, True),
                                 opts=opts)

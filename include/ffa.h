@@ -91,9 +91,14 @@ enum { FFA_CARRIER_AUTO = 0, FFA_CARRIER_INT8 = 1, FFA_CARRIER_F64 = 2 };
  *   herk_base     base case of ffa_herk_modp2: FFA_HERK_AUTO / FFA_HERK_2M = the 2M method
  *                 (Section 6, Algorithm 3 with epsilon = 1): one real SYRK of Xr + Xi and one
  *                 real GEMM Xr Xi^T, 1.5 n^2 k products over F_p; FFA_HERK_4M = the four real
- *                 products of the complex kernel, 2 n^2 k */
+ *                 products of the complex kernel, 2 n^2 k
+ *   general       the general products P3, P4 of each recursion node: FFA_GENERAL_CLASSICAL,
+ *                 or FFA_GENERAL_WINOGRAD = one level of Strassen-Winograd (7 half-size
+ *                 products, 15 block additions; real carriers only, else ignored);
+ *                 FFA_GENERAL_AUTO = Winograd on the fp64 carrier, classical on INT8 */
 enum { FFA_LAUNCH_GRAPH = 0, FFA_LAUNCH_DIRECT = 1 };
 enum { FFA_HERK_AUTO = 0, FFA_HERK_2M = 1, FFA_HERK_4M = 2 };
+enum { FFA_GENERAL_AUTO = 0, FFA_GENERAL_CLASSICAL = 1, FFA_GENERAL_WINOGRAD = 2 };
 enum { FFA_OPERANDS_AUTO = 0, FFA_OPERANDS_PLANES = 1, FFA_OPERANDS_RAW = 2 };
 enum { FFA_STREAMS_AUTO = 0, FFA_STREAMS_ONE = 1, FFA_STREAMS_TWO = 2 };
 typedef struct {
@@ -107,7 +112,8 @@ typedef struct {
     int32_t operands;
     int32_t streams;
     int32_t herk_base;
-    int32_t reserved[2];
+    int32_t general;
+    int32_t reserved;
 } ffa_opts;
 
 /* Context bound to a HIP device and stream (stream NULL = the null stream).
@@ -190,7 +196,8 @@ int ffa_profile_reset(ffa_ctx* ctx);
 /* Autotuner.  Times every candidate plan for this call (recursion depth 0..4 that
  * the sizes allow x carrier (INT8 limbs, and FP64 where its bound holds) x every
  * INT8 product-kernel configuration of the carrier x operand source, raw uint16 rows
- * where the planner allows them) on the caller's own buffers
+ * where the planner allows them x general products, classical or Strassen-Winograd
+ * where the recursion has general products on a real carrier) on the caller's own buffers
  * with HIP events, `reps` timed calls each, and records the fastest for the shape
  * (n, k, p, formats) in the context: later calls with opts = NULL use it, and
  * so do other shapes of the same size class (n and k within the same half-octave)
@@ -208,7 +215,9 @@ int ffa_batch_autotune(ffa_batch* b, const void* A_packed, void* C_packed, int r
 
 /* The context's autotuner records as JSON text
  *   {"arch":"gfx950","records":[{"n":..,"k":..,"p":..,"herm":..,"dA":..,"dC":..,
- *    "algo":..,"levels":..,"cutoff":..,"carrier":..,"kernel":..}, ...]}
+ *    "algo":..,"levels":..,"cutoff":..,"carrier":..,"kernel":..,"operands":..,
+ *    "general":..}, ...]}
+ * ("operands" and "general" may be absent on import: the built-in choice then).
  * ffa_tune_export writes it into buf (NUL-terminated; nothing written when size is
  * too small) and returns the length it needs without the NUL, or a negative status.
  * ffa_tune_import adds the records of such a text (records for another arch are

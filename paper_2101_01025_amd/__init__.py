@@ -23,6 +23,7 @@ LAUNCH_GRAPH, LAUNCH_DIRECT = 0, 1
 OPERANDS_AUTO, OPERANDS_PLANES, OPERANDS_RAW = 0, 1, 2
 STREAMS_AUTO, STREAMS_ONE, STREAMS_TWO = 0, 1, 2
 HERK_AUTO, HERK_2M, HERK_4M = 0, 1, 2
+GENERAL_AUTO, GENERAL_CLASSICAL, GENERAL_WINOGRAD = 0, 1, 2
 
 SYMBOLS = [
     "ffa_create", "ffa_destroy", "ffa_set_stream", "ffa_last_device_error", "ffa_status_string",
@@ -46,7 +47,7 @@ class Opts(ctypes.Structure):
                 ("carrier", ctypes.c_int32), ("check_inputs", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("launch", ctypes.c_int32), ("operands", ctypes.c_int32),
                 ("streams", ctypes.c_int32), ("herk_base", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("general", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -54,9 +55,9 @@ class Opts(ctypes.Structure):
 
 def make_opts(algo=ALGO_AUTO, levels=-1, cutoff=0, carrier=CARRIER_AUTO, check_inputs=False,
               kernel=0, launch=LAUNCH_GRAPH, operands=OPERANDS_AUTO, streams=STREAMS_AUTO,
-              herk_base=0):
+              herk_base=0, general=0):
     return Opts(algo, levels, cutoff, carrier, int(bool(check_inputs)), kernel, launch, operands,
-                streams, herk_base)
+                streams, herk_base, general)
 
 
 _lib = None

@@ -72,7 +72,8 @@ std::string key_of(const Problem& p)
     snprintf(buf, sizeof(buf), "%lld|%lld|%lld|%lld|%u|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%u|%u",
              (long long)p.n, (long long)p.k, (long long)p.lda, (long long)p.ldc, p.p, p.herm, p.dA,
              p.dC, p.opts.algo, p.opts.levels, p.opts.cutoff, p.opts.carrier, p.opts.check_inputs,
-             p.opts.kernel, p.opts.operands, p.opts.streams, p.aligned ? 1 : 0, p.trans, p.alpha, p.beta);
+             p.opts.kernel, p.opts.operands, p.opts.streams * 16 + p.opts.herk_base * 4 + p.opts.general,
+             p.aligned ? 1 : 0, p.trans, p.alpha, p.beta);
     return buf;
 }
 
@@ -265,6 +266,12 @@ int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws)
                           pl.pre_max_h[l], pl.pre_max_w[l], b, pl.fp, pl.carrier, (void*)ps);
         if (e) return dev_fail(c, e);
     }
+    if (!pl.wpre.empty()) {
+        // Strassen-Winograd operand sums (after every pre-addition, before the products)
+        e = launch_wino_pre((const WinoPreTask*)(blob + pl.off_wpre), (int)pl.wpre.size(), pl.wpre_max_h,
+                            pl.wpre_max_w, b, pl.fp, pl.carrier, (void*)ps);
+        if (e) return dev_fail(c, e);
+    }
     phase_end(c, ps, ev, 1);
     if (fork) {
         if ((e = products(ps, pl.off_sched2, pl.sched2.size()))) return dev_fail(c, e);
@@ -288,6 +295,12 @@ int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws)
         if (he != hipSuccess) return dev_fail(c, he);
     }
     ev = pl.levels > 0 ? phase_begin(c, ms) : nullptr;
+    if (!pl.wpost.empty()) {
+        // Strassen-Winograd combinations (before the post-additions that read P3, P4)
+        e = launch_wino_post((const WinoPostTask*)(blob + pl.off_wpost), (int)pl.wpost.size(),
+                             pl.wpost_max_h, b, pl.fp, s);
+        if (e) return dev_fail(c, e);
+    }
     for (int l = pl.levels - 1; l >= 0; --l) {
         if (pl.post[l].empty()) continue;
         // every task of a level writes the same format: the caller's C at level 0,
@@ -792,17 +805,21 @@ int ffa_autotune_syrk(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA, co
         for (int L = 0; L <= 4; ++L) {
             if (L > 0 && ((n >> L) < 64 || k == 0)) break;
             for (int kc : kernel_candidates(cprobe))
-            for (int opr : {FFA_OPERANDS_PLANES, FFA_OPERANDS_RAW}) {
+            for (int opr : {FFA_OPERANDS_PLANES, FFA_OPERANDS_RAW})
+            for (int gen : {FFA_GENERAL_CLASSICAL, FFA_GENERAL_WINOGRAD}) {
                 ffa_opts o = default_opts();
                 o.algo = L == 0 ? FFA_ALGO_CLASSICAL : FFA_ALGO_RECURSIVE;
                 o.levels = L;
                 o.kernel = kc;
                 o.carrier = car;
                 o.operands = opr;
+                o.general = gen;
                 Problem pr = base;
                 pr.opts = o;
-                // raw operands only where the planner takes them
-                if (opr == FFA_OPERANDS_RAW && make_plan(pr).gemm_src != SRC_RAW_U16) continue;
+                // raw operands and Winograd only where the planner takes them
+                const Plan tp = make_plan(pr);
+                if (opr == FFA_OPERANDS_RAW && tp.gemm_src != SRC_RAW_U16) continue;
+                if (gen == FFA_GENERAL_WINOGRAD && !tp.wino) continue;
                 double ms = 0;
                 const int st =
                     time_calls(ctx, reps, [&] { return run_call(ctx, pr, A, nullptr, C, nullptr); }, &ms);
@@ -934,8 +951,10 @@ int64_t ffa_tune_export(const ffa_ctx* c, char* buf, int64_t size)
         char rec[320];
         snprintf(rec, sizeof(rec),
                  "%s{\"n\":%lld,\"k\":%lld,\"p\":%u,\"herm\":%d,\"dA\":%d,\"dC\":%d,\"algo\":%d,"
-                 "\"levels\":%d,\"cutoff\":%d,\"carrier\":%d,\"kernel\":%d}",
-                 first ? "" : ",", n, k, p, herm, dA, dC, o.algo, o.levels, o.cutoff, o.carrier, o.kernel);
+                 "\"levels\":%d,\"cutoff\":%d,\"carrier\":%d,\"kernel\":%d,\"operands\":%d,"
+                 "\"general\":%d}",
+                 first ? "" : ",", n, k, p, herm, dA, dC, o.algo, o.levels, o.cutoff, o.carrier, o.kernel,
+                 o.operands, o.general);
         s += rec;
         first = false;
     }
@@ -973,6 +992,9 @@ int ffa_tune_import(ffa_ctx* c, const char* json)
         o.cutoff = (int32_t)cutoff;
         o.carrier = (int32_t)carrier;
         o.kernel = (int32_t)kernel;
+        long long v;  // fields added later: absent means the built-in choice
+        if (json_int(p, e, "operands", &v)) o.operands = (int32_t)v;
+        if (json_int(p, e, "general", &v)) o.general = (int32_t)v;
         record_tuned(c, n, k, (uint32_t)pp, (int)herm, (int)dA, (int)dC, o);
         ++taken;
         p = e + 1;

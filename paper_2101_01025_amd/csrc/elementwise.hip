@@ -577,6 +577,164 @@ __global__ void __launch_bounds__(512) postadd(const PostaddTask* tasks, Bases b
 }
 
 // ============================================================================
+// Strassen-Winograd operand sums and result combination
+// ============================================================================
+
+// One thread: VEC columns of one row of the h x w half-blocks; the 8 operand
+// blocks are read as carriers (canonical residues), the 8 sums written back.
+template <int NL, int VEC>
+__global__ void __launch_bounds__(256) wino_pre(const WinoPreTask* tasks, Bases b, FieldParams fp)
+{
+    const WinoPreTask& T = tasks[blockIdx.y];
+    const int h = T.h, w = T.w, gpr = w / VEC;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= h * gpr) return;
+    const int r = idx / gpr, c = (idx % gpr) * VEC;
+    const int32_t p = fp.p;
+    typedef int8_t vec_t[VEC];
+    // [operand (x, z)][block (11, 12, 21, 22)][limb]
+    alignas(16) vec_t in[2][4][NL];
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+        const CarRef& a = o == 0 ? T.x : T.z;
+        const char* base = b.p[a.buf] + a.off;
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                const char* src = base + (int64_t)l * a.ps + (int64_t)((blk >> 1) * h + r) * a.ld +
+                                  (blk & 1) * w + c;
+                *reinterpret_cast<int4*>(in[o][blk][l]) = *reinterpret_cast<const int4*>(src);
+            }
+    }
+    alignas(16) vec_t out[2][4][NL];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        int32_t x[4], z[4];
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk) {
+            x[blk] = car_canon<NL>(in[0][blk][0], in[0][blk][NL - 1], e, p);
+            z[blk] = car_canon<NL>(in[1][blk][0], in[1][blk][NL - 1], e, p);
+        }
+        int32_t s[4], t[4];
+        s[0] = add_mod(x[2], x[3], p);  // S1 = X21 + X22
+        s[1] = sub_mod(s[0], x[0], p);  // S2 = S1 - X11
+        s[2] = sub_mod(x[0], x[2], p);  // S3 = X11 - X21
+        s[3] = sub_mod(x[1], s[1], p);  // S4 = X12 - S2
+        t[0] = sub_mod(z[2], z[0], p);  // T1 = Z21 - Z11
+        t[1] = sub_mod(z[3], t[0], p);  // T2 = Z22 - T1
+        t[2] = sub_mod(z[3], z[2], p);  // T3 = Z22 - Z21
+        t[3] = sub_mod(t[1], z[1], p);  // T4 = T2 - Z12
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            put_canon<NL>(s[j], p, fp.half, out[0][j][0], out[0][j][NL - 1], e);
+            put_canon<NL>(t[j], p, fp.half, out[1][j][0], out[1][j][NL - 1], e);
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < 2; ++o)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const CarRef& d = o == 0 ? T.s[j] : T.t[j];
+#pragma unroll
+            for (int l = 0; l < NL; ++l)
+                *reinterpret_cast<int4*>(b.p[d.buf] + d.off + (int64_t)l * d.ps + (int64_t)r * d.ld + c) =
+                    *reinterpret_cast<const int4*>(out[o][j][l]);
+        }
+}
+
+// fp64 carrier: centred residues held as doubles, 4 consecutive columns per thread
+// (w is a multiple of the 16-column k-tile, rows are 32-byte aligned).
+__global__ void __launch_bounds__(256) wino_pre_f64(const WinoPreTask* tasks, Bases b, FieldParams fp)
+{
+    constexpr int V = 4;
+    const WinoPreTask& T = tasks[blockIdx.y];
+    const int h = T.h, w = T.w, gpr = w / V;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)h * gpr) return;
+    const int r = (int)(idx / gpr), c = (int)(idx % gpr) * V;
+    const int32_t p = fp.p;
+    auto ld = [&](const CarRef& a, int blk, int32_t* v) {
+        const double* src = reinterpret_cast<const double*>(b.p[a.buf] + a.off) +
+                            (int64_t)((blk >> 1) * h + r) * a.ld + (blk & 1) * w + c;
+        alignas(16) double t[V];
+        reinterpret_cast<int4*>(t)[0] = reinterpret_cast<const int4*>(src)[0];
+        reinterpret_cast<int4*>(t)[1] = reinterpret_cast<const int4*>(src)[1];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const int32_t iv = (int32_t)t[e];
+            v[e] = iv < 0 ? iv + p : iv;
+        }
+    };
+    auto st = [&](const CarRef& d, const int32_t* v) {
+        alignas(16) double t[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) t[e] = (double)(v[e] > fp.half ? v[e] - p : v[e]);
+        double* dst = reinterpret_cast<double*>(b.p[d.buf] + d.off) + (int64_t)r * d.ld + c;
+        reinterpret_cast<int4*>(dst)[0] = reinterpret_cast<const int4*>(t)[0];
+        reinterpret_cast<int4*>(dst)[1] = reinterpret_cast<const int4*>(t)[1];
+    };
+    int32_t x[4][V], z[4][V];
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) {
+        ld(T.x, blk, x[blk]);
+        ld(T.z, blk, z[blk]);
+    }
+    int32_t s[4][V], t[4][V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        s[0][e] = add_mod(x[2][e], x[3][e], p);
+        s[1][e] = sub_mod(s[0][e], x[0][e], p);
+        s[2][e] = sub_mod(x[0][e], x[2][e], p);
+        s[3][e] = sub_mod(x[1][e], s[1][e], p);
+        t[0][e] = sub_mod(z[2][e], z[0][e], p);
+        t[1][e] = sub_mod(z[3][e], t[0][e], p);
+        t[2][e] = sub_mod(z[3][e], z[2][e], p);
+        t[3][e] = sub_mod(t[1][e], z[1][e], p);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        st(T.s[j], s[j]);
+        st(T.t[j], t[j]);
+    }
+}
+
+// One thread: 8 consecutive columns of one row of the h x h results, vector
+// loads of the seven products; the four blocks of C (vector stores where aligned).
+template <typename RT>
+__global__ void __launch_bounds__(256) wino_post(const WinoPostTask* tasks, Bases b, FieldParams fp)
+{
+    constexpr int V = 8;
+    const WinoPostTask& T = tasks[blockIdx.y];
+    const int h = T.h, gpr = (h + V - 1) / V;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= h * gpr) return;
+    const int r = idx / gpr, c0 = (idx % gpr) * V;
+    const int32_t p = fp.p;
+    // residue rows are padded to a multiple of 64 elements: whole groups are inside them
+    RowV<RT, V> R[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) R[q].load(b.p[T.r[q].buf] + T.r[q].off, T.r[q].ld, r, c0);
+    int32_t c11[V], c12[V], c21[V], c22[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        const int32_t u2 = add_mod(R[0][e], R[5][e], p), u3 = add_mod(u2, R[6][e], p);
+        const int32_t u4 = add_mod(u2, R[4][e], p);
+        c11[e] = add_mod(R[0][e], R[1][e], p);  // C11 = R1 + R2
+        c12[e] = add_mod(u4, R[2][e], p);       // C12 = U4 + R3
+        c21[e] = sub_mod(u3, R[3][e], p);       // C21 = U3 - R4
+        c22[e] = add_mod(u3, R[4][e], p);       // C22 = U3 + R5
+    }
+    const int want = min(V, h - c0);
+    char* cb = b.p[T.c.buf] + T.c.off;
+    const int64_t ldc = T.c.ld;
+    store_rowv<RT, V>(cb, (int64_t)r * ldc + c0, c11, want);
+    store_rowv<RT, V>(cb, (int64_t)r * ldc + h + c0, c12, want);
+    store_rowv<RT, V>(cb, (int64_t)(h + r) * ldc + c0, c21, want);
+    store_rowv<RT, V>(cb, (int64_t)(h + r) * ldc + h + c0, c22, want);
+}
+
+// ============================================================================
 // transposed conditioning and the final update C <- alpha X + beta C
 // ============================================================================
 
@@ -880,6 +1038,37 @@ int launch_condition_trans(const CondTask* d_tasks, int ntasks, int max_tiles, i
     case DT_F64: launch_cond_t_typed<double>(g, s, d_tasks, b, fp, carrier, d_err); break;
     default: return (int)hipErrorInvalidValue;
     }
+    return (int)hipGetLastError();
+}
+
+int launch_wino_pre(const WinoPreTask* d_tasks, int ntasks, int max_h, int max_w, const Bases& b,
+                    const FieldParams& fp, int carrier, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if (ntasks <= 0 || max_h <= 0 || max_w <= 0) return 0;
+    if (carrier == CAR_F64) {
+        const int64_t total = (int64_t)max_h * (max_w / 4);
+        hipLaunchKernelGGL(wino_pre_f64, dim3((unsigned)((total + 255) / 256), ntasks), dim3(256), 0, s,
+                           d_tasks, b, fp);
+    } else {
+        const int64_t total = (int64_t)max_h * (max_w / 16);
+        const dim3 g((unsigned)((total + 255) / 256), ntasks);
+        if (fp.nl == 1) hipLaunchKernelGGL((wino_pre<1, 16>), g, dim3(256), 0, s, d_tasks, b, fp);
+        else hipLaunchKernelGGL((wino_pre<2, 16>), g, dim3(256), 0, s, d_tasks, b, fp);
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_wino_post(const WinoPostTask* d_tasks, int ntasks, int max_h, const Bases& b,
+                     const FieldParams& fp, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if (ntasks <= 0 || max_h <= 0) return 0;
+    const int64_t total = (int64_t)max_h * ((max_h + 7) / 8);
+    const dim3 g((unsigned)((total + 255) / 256), ntasks);
+    if (fp.p < 256) hipLaunchKernelGGL((wino_post<uint8_t>), g, dim3(256), 0, s, d_tasks, b, fp);
+    else if (fp.p < 65536) hipLaunchKernelGGL((wino_post<uint16_t>), g, dim3(256), 0, s, d_tasks, b, fp);
+    else hipLaunchKernelGGL((wino_post<int32_t>), g, dim3(256), 0, s, d_tasks, b, fp);
     return (int)hipGetLastError();
 }
 

@@ -172,6 +172,25 @@ struct Herk2mTask {
     int32_t n, nvalid;
 };
 
+// One level of Strassen-Winograd for a general product C = X Z^T (X, Z: 2h x 2w
+// carriers, C: 2h x 2h residues).  With B = Z^T, the operand sums are
+//   S1 = X21 + X22, S2 = S1 - X11, S3 = X11 - X21, S4 = X12 - S2 (on X) and
+//   T1 = Z21 - Z11, T2 = Z22 - T1, T3 = Z22 - Z21, T4 = T2 - Z12 (on Z, i.e. the
+//   sums of the blocks of B transposed), each h x w;
+// the seven products R1 = X11 Z11^T, R2 = X12 Z12^T, R3 = S4 Z22^T, R4 = X22 T4^T,
+// R5 = S1 T1^T, R6 = S2 T2^T, R7 = S3 T3^T; and
+//   C11 = R1 + R2, C12 = R1 + R6 + R5 + R3, C21 = R1 + R6 + R7 - R4, C22 = R1 + R6 + R7 + R5.
+struct WinoPreTask {
+    CarRef x, z;
+    CarRef s[4], t[4];
+    int32_t h, w;
+};
+struct WinoPostTask {
+    ResRef r[7];
+    ResRef c;
+    int32_t h, pad_;
+};
+
 // Final update C <- alpha X + beta C on the lower triangle of an n x n result:
 // X is the product's residues (workspace), C the caller's matrix.
 struct UpdateTask {
@@ -189,6 +208,10 @@ int launch_condition(const CondTask* d_tasks, int ntasks, int nblocks, int dt_in
 // one launch for every task with trans = 1 (the others go to launch_condition)
 int launch_condition_trans(const CondTask* d_tasks, int ntasks, int max_tiles, int dt_in, const Bases& b,
                            const FieldParams& fp, int carrier, int32_t* d_err, void* stream);
+int launch_wino_pre(const WinoPreTask* d_tasks, int ntasks, int max_h, int max_w, const Bases& b,
+                    const FieldParams& fp, int carrier, void* stream);
+int launch_wino_post(const WinoPostTask* d_tasks, int ntasks, int max_h, const Bases& b,
+                     const FieldParams& fp, void* stream);
 int launch_herk2m(const Herk2mTask* d_tasks, int ntasks, int max_n, int res_dt, int out_dt,
                   const Bases& b, const FieldParams& fp, void* stream);
 int launch_update(const UpdateTask* d_tasks, int ntasks, int max_n, int x_dt, int c_dt, const Bases& b,

@@ -147,6 +147,40 @@ struct Builder {
         pl.max_k = std::max(pl.max_k, K);
         pl.products_macs += syrk ? M * (M + 1) / 2 * K : M * N * K;
     }
+    // A general product c = x z^T (h x h from h x w operands): one task, or one
+    // level of Strassen-Winograd (operand sums, seven half-size products, combination).
+    void general(const CarRef& x, const CarRef& z, const ResRef& c, int64_t h, int64_t w)
+    {
+        if (!pl.wino) {
+            add_gemm(x, z, c, h, h, w, false, false);
+            return;
+        }
+        const int64_t h2 = h / 2, w2 = w / 2;
+        WinoPreTask wt{};
+        wt.x = x;
+        wt.z = z;
+        for (int j = 0; j < 4; ++j) {
+            wt.s[j] = new_car(h2, w2);
+            wt.t[j] = new_car(h2, w2);
+        }
+        wt.h = (int32_t)h2;
+        wt.w = (int32_t)w2;
+        pl.wpre.push_back(wt);
+        WinoPostTask wp{};
+        for (int j = 0; j < 7; ++j) wp.r[j] = new_res(h2);
+        wp.c = c;
+        wp.h = (int32_t)h2;
+        pl.wpost.push_back(wp);
+        const CarRef X11 = view(x, 0, 0), X12 = view(x, 0, w2), X22 = view(x, h2, w2);
+        const CarRef Z11 = view(z, 0, 0), Z12 = view(z, 0, w2), Z22 = view(z, h2, w2);
+        add_gemm(X11, Z11, wp.r[0], h2, h2, w2, false, false);        // R1 = X11 Z11^T
+        add_gemm(X12, Z12, wp.r[1], h2, h2, w2, false, false);        // R2 = X12 Z12^T
+        add_gemm(wt.s[3], Z22, wp.r[2], h2, h2, w2, false, false);    // R3 = S4 Z22^T
+        add_gemm(X22, wt.t[3], wp.r[3], h2, h2, w2, false, false);    // R4 = X22 T4^T
+        add_gemm(wt.s[0], wt.t[0], wp.r[4], h2, h2, w2, false, false);  // R5 = S1 T1^T
+        add_gemm(wt.s[1], wt.t[1], wp.r[5], h2, h2, w2, false, false);  // R6 = S2 T2^T
+        add_gemm(wt.s[2], wt.t[2], wp.r[6], h2, h2, w2, false, false);  // R7 = S3 T3^T
+    }
     // One node of the recursion: a is rows x cols, its result goes to c.
     // aonly: a is a block of the (conditioned) input itself.
     void node(int level, const CarRef& a, int64_t rows, int64_t cols, const ResRef& c,
@@ -185,8 +219,8 @@ struct Builder {
         ResRef P[5];
         for (int j = 0; j < 5; ++j) P[j] = new_res(h);
         const CarRef A11 = view(a, 0, 0), A12 = view(a, 0, w), A22 = view(a, h, w);
-        add_gemm(A22, pt.s[3], P[2], h, h, w, false, false);   // P3 = A22 phi(S4)
-        add_gemm(pt.s[0], pt.s[1], P[3], h, h, w, false, false);  // P4 = S1 phi(S2)
+        general(A22, pt.s[3], P[2], h, w);     // P3 = A22 phi(S4)
+        general(pt.s[0], pt.s[1], P[3], h, w);  // P4 = S1 phi(S2)
         node(level + 1, A11, h, w, P[0], h, aonly);               // P1 = A11 phi(A11)
         node(level + 1, A12, h, w, P[1], h, aonly);               // P2 = A12 phi(A12)
         node(level + 1, pt.s[2], h, w, P[4], h, false);           // P5 = S3 phi(S3)
@@ -383,6 +417,11 @@ void size_grids(Plan& pl)
         }
         for (const auto& t : pl.post[l]) pl.post_max_h[l] = std::max(pl.post_max_h[l], t.h);
     }
+    for (const auto& t : pl.wpre) {
+        pl.wpre_max_h = std::max<int>(pl.wpre_max_h, t.h);
+        pl.wpre_max_w = std::max<int>(pl.wpre_max_w, t.w);
+    }
+    for (const auto& t : pl.wpost) pl.wpost_max_h = std::max<int>(pl.wpost_max_h, t.h);
     schedule_products(pl);
 }
 
@@ -412,8 +451,10 @@ ResRef root_output(Plan& pl, Builder& B, const Problem& pr)
 int add_problem(Plan& pl, Builder& B, const Problem& pr, int levels, bool allow_direct)
 {
     const int ktile = pl.ktile;
-    const int64_t npad = round_up(pr.n, (int64_t)1 << levels);
-    const int64_t kpad = round_up(pr.k, (int64_t)ktile << levels);
+    // one more halving for Strassen-Winograd below the deepest general products
+    const int depth = levels + (pl.wino ? 1 : 0);
+    const int64_t npad = round_up(pr.n, (int64_t)1 << depth);
+    const int64_t kpad = round_up(pr.k, (int64_t)ktile << depth);
     if (npad >= (1ll << 31) || kpad >= (1ll << 31)) return FFA_EINVAL;
     if (pl.npad == 0) {
         pl.npad = npad;
@@ -558,6 +599,12 @@ Plan make_plan(const Problem& pr)
     pl.pre.assign(pl.levels, {});
     pl.post.assign(pl.levels, {});
     pl.kernel_req = o.kernel;
+    if (o.general < FFA_GENERAL_AUTO || o.general > FFA_GENERAL_WINOGRAD) { pl.status = FFA_EINVAL; return pl; }
+    // measured: Winograd's block additions pay off for the fp64 products (9.84 vs 10.11 ms
+    // at 8192^2), not for the faster INT8 ones
+    const bool wino_default = pl.carrier == CAR_F64;
+    pl.wino = (o.general == FFA_GENERAL_WINOGRAD || (o.general == FFA_GENERAL_AUTO && wino_default)) &&
+              !pl.cplx && pl.levels > 0;
     choose_kernel(pl, pr.n >> pl.levels);
     // the problem's tasks on top of the settings above (pl is copied so that a
     // second attempt starts from the same state)
@@ -580,7 +627,7 @@ Plan make_plan(const Problem& pr)
     if (pl.status != FFA_OK && pl.status != FFA_EBOUND && pl.status != FFA_EUNSUPPORTED) return pl;
     if (pl.status == FFA_OK) pl.status = check_bound(pl);
     pl.zero_fill = pr.k == 0;
-    pl.fork = o.streams == FFA_STREAMS_TWO && pl.levels > 0 && !pl.herk2m;
+    pl.fork = o.streams == FFA_STREAMS_TWO && pl.levels > 0 && !pl.herk2m && !pl.wino;
     size_grids(pl);
     return pl;
 }
@@ -683,6 +730,8 @@ std::vector<char> pack_tables(Plan& pl)
     pl.off_gemm_r = put(pl.gemm_r.data(), pl.gemm_r.size() * sizeof(GemmTask));
     pl.off_sched_r = put(pl.sched_r.data(), pl.sched_r.size() * sizeof(TileEnt));
     pl.off_h2m = put(pl.h2m.data(), pl.h2m.size() * sizeof(Herk2mTask));
+    pl.off_wpre = put(pl.wpre.data(), pl.wpre.size() * sizeof(WinoPreTask));
+    pl.off_wpost = put(pl.wpost.data(), pl.wpost.size() * sizeof(WinoPostTask));
     pl.blob_bytes = (int64_t)blob.size();
     return blob;
 }
@@ -703,14 +752,16 @@ std::string describe(const Plan& pl)
              "\"ws_bytes\":%lld,\"conditioning\":%zu,\"preadd_tasks\":%s,\"postadd_tasks\":%s,"
              "\"gemm_tasks\":%zu,\"tiles\":%d,\"blocks\":%zu,\"cfg\":%d,\"tile\":%d,"
              "\"macs\":%lld,\"ykind\":%d,\"ya\":%d,\"yb\":%d,\"src\":\"%s\",\"streams\":%d,"
-             "\"blocks_a_only\":%zu,\"herk_base\":\"%s\",\"real_tasks\":%zu}",
+             "\"blocks_a_only\":%zu,\"herk_base\":\"%s\",\"real_tasks\":%zu,\"general\":\"%s\","
+             "\"wino_tasks\":%zu}",
              pl.status, pl.levels, pl.carrier == CAR_F64 ? "f64" : "int8", pl.nl, pl.cplx,
              (long long)pl.npad, (long long)pl.kpad, pl.direct ? 1 : 0, pl.max_abs,
              (long long)pl.max_k, (long long)pl.ws_bytes, pl.cond.size(), pre.c_str(), post.c_str(),
              pl.gemm.size(), pl.total_tiles, pl.sched.size() + pl.sched2.size(), pl.gemm_cfg, pl.tile,
              (long long)pl.products_macs, pl.fp.ykind, pl.fp.ya,
              pl.fp.yb, pl.gemm_src == SRC_RAW_U16 ? "raw_u16" : "carrier", pl.fork ? 2 : 1,
-             pl.sched.size(), pl.herk2m ? "2m" : (pl.cplx ? "4m" : "none"), pl.gemm_r.size());
+             pl.sched.size(), pl.herk2m ? "2m" : (pl.cplx ? "4m" : "none"), pl.gemm_r.size(),
+             pl.wino ? "winograd" : "classical", pl.wpre.size());
     return buf;
 }
 

@@ -47,6 +47,11 @@ struct Plan {
     int gemm_cfg_r = 0;
     std::vector<Herk2mTask> h2m;
     int h2m_max_n = 0;
+    // Strassen-Winograd for the general products
+    bool wino = false;
+    std::vector<WinoPreTask> wpre;
+    std::vector<WinoPostTask> wpost;
+    int wpre_max_h = 0, wpre_max_w = 0, wpost_max_h = 0;
     std::vector<UpdateTask> upd;       // final C <- alpha X + beta C
     int upd_max_n = 0;
     std::vector<std::vector<PreaddTask>> pre;   // per level, top-down
@@ -78,7 +83,7 @@ struct Plan {
     void* d_blob = nullptr;
     int64_t blob_bytes = 0;
     int64_t off_cond = 0, off_gemm = 0, off_sched = 0, off_sched2 = 0, off_upd = 0;
-    int64_t off_gemm_r = 0, off_sched_r = 0, off_h2m = 0;
+    int64_t off_gemm_r = 0, off_sched_r = 0, off_h2m = 0, off_wpre = 0, off_wpost = 0;
     std::vector<int64_t> off_pre, off_post;
 };
 

@@ -162,6 +162,7 @@ def test_autotune_syrk_and_tuned_default(p, n, k, dt):
     assert rec["arch"].startswith("gfx")
     mine = [r for r in rec["records"] if (r["n"], r["k"], r["p"]) == (n, k, p)]
     assert mine and mine[0]["levels"] == best.levels and mine[0]["kernel"] == best.kernel
+    assert mine[0]["operands"] == best.operands and mine[0]["general"] == best.general
     assert ffa.tune_import(json.dumps(rec)) == len(rec["records"])
     # a shape of the same size class without a record of its own uses the class record
     A2 = A[: n - 3, : k - 5].contiguous()

@@ -87,9 +87,10 @@ def test_small_256_int64_one_level():
     assert (got[~low] == -7).all()
 
 
-@pytest.mark.parametrize("algo", ["recursive", "classical"])
+@pytest.mark.parametrize("algo", ["recursive", "recursive_plain_general", "classical"])
 def test_f64_8192_p65521(algo):
-    """8192 x 8192, p = 65521, fp64 storage on the fp64 carrier, cutoff 512 (four levels)."""
+    """8192 x 8192, p = 65521, fp64 storage on the fp64 carrier, cutoff 512 (four levels);
+    general products by Strassen-Winograd (the default here) or as single products."""
     ffa = _ffa()
     n = k = 8192
     p = 65521
@@ -98,16 +99,20 @@ def test_f64_8192_p65521(algo):
     A = torch.from_numpy(Ares.astype(np.float64)).to("cuda")
     C = torch.full((n, n), -7.0, dtype=torch.float64, device="cuda")
     kw = dict(algo=ffa.ALGO_CLASSICAL) if algo == "classical" else dict(cutoff=512)
-    if algo == "recursive":
-        _, d = ffa.plan_describe(n, k, p, dA=ffa.F64, dC=ffa.F64, opts=ffa.make_opts(cutoff=512))
+    if algo == "recursive_plain_general":
+        kw["general"] = ffa.GENERAL_CLASSICAL
+    if algo != "classical":
+        _, d = ffa.plan_describe(n, k, p, dA=ffa.F64, dC=ffa.F64,
+                                 opts=ffa.make_opts(**{"cutoff": 512, **kw}))
         assert d["levels"] == 4 and d["carrier"] == "f64"
+        assert d["general"] == ("winograd" if algo == "recursive" else "classical")
     ffa.syrk_modp(A, p, C=C, **kw)
     torch.cuda.synchronize()
     _upper_untouched(C, -7, n)
     _check_syrk_large(Ares, C, p, np.random.default_rng(11))
 
 
-@pytest.mark.parametrize("algo", ["recursive", "classical"])
+@pytest.mark.parametrize("algo", ["recursive", "classical", "winograd"])
 def test_int8x2_16384_p65521(algo):
     """16384 x 16384, p = 65521, two balanced int8 limbs on INT8 MFMA."""
     ffa = _ffa()
@@ -118,6 +123,8 @@ def test_int8x2_16384_p65521(algo):
     A = _u16(Ares)
     C = torch.full((n, n), 0xBEEF, dtype=torch.int32, device="cuda").to(torch.uint16)
     kw = dict(algo=ffa.ALGO_CLASSICAL) if algo == "classical" else dict()
+    if algo == "winograd":
+        kw = dict(general=ffa.GENERAL_WINOGRAD)
     ffa.syrk_modp(A, p, C=C, **kw)
     torch.cuda.synchronize()
     del A

@@ -91,6 +91,22 @@ def test_two_streams(levels, p, dt):
                    streams=ffa.STREAMS_TWO)
 
 
+@pytest.mark.parametrize("levels", [1, 2, 3])
+@pytest.mark.parametrize("p,dt", [(251, torch.int8), (13, torch.int64), (65521, torch.uint16),
+                                  (65521, torch.float64), (131071, torch.float64)])
+@pytest.mark.parametrize("shape", [(300, 520), (257, 1000)])
+def test_winograd_general_products(levels, p, dt, shape):
+    """P3 and P4 of every node by one level of Strassen-Winograd (seven half-size products)."""
+    ffa = _ffa()
+    n, k = shape
+    A = si.uniform_residues(n, k, p, 1200 + levels * 7 + p % 97 + n)
+    kw = dict(levels=levels, general=ffa.GENERAL_WINOGRAD)
+    if dt == torch.float64:
+        kw["carrier"] = ffa.CARRIER_F64
+    out = torch.uint8 if p < 256 else (torch.uint16 if p < 65536 else torch.int64)
+    check_syrk(A, p, dt, out, **kw)
+
+
 @pytest.mark.parametrize("p", [3, 5, 13, 241])
 def test_int8_small_primes(p):
     # p = 3 and 251 use Y = [[a,b],[-b,a]] (x) I; p = 5, 13, 241 use Y = sqrt(-1) I

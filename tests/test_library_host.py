@@ -131,6 +131,29 @@ def test_plan_herk_base_case_2m():
     assert ffa.plan_describe(n, k, 65519, hermitian=True, opts=ffa.make_opts(herk_base=3))[0] == ffa.EINVAL
 
 
+def test_plan_winograd_general_products():
+    # one level of Algorithm 1, P3 and P4 each by Strassen-Winograd: 3 leaves + 2 x 7 products
+    n = k = 4096
+    st, d = ffa.plan_describe(n, k, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
+                              opts=ffa.make_opts(levels=1, general=ffa.GENERAL_WINOGRAD))
+    assert st == 0 and d["general"] == "winograd" and d["wino_tasks"] == 2 and d["gemm_tasks"] == 17
+    h, w = n // 2, k // 2
+    assert d["macs"] == 3 * (h * (h + 1) // 2) * w + 2 * 7 * (h // 2) ** 2 * (w // 2)
+    # rows and columns are padded one halving deeper
+    st, d = ffa.plan_describe(1000, 333, 65521, dA=ffa.U16, dC=ffa.U16,
+                              opts=ffa.make_opts(levels=2, general=ffa.GENERAL_WINOGRAD))
+    assert st == 0 and d["npad"] % 8 == 0 and d["kpad"] % (128 << 3) == 0
+    # no recursion: no general products, nothing changes
+    st, d = ffa.plan_describe(n, k, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
+                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL, general=ffa.GENERAL_WINOGRAD))
+    assert st == 0 and d["general"] == "classical"
+    assert ffa.plan_describe(10, 10, 251, opts=ffa.make_opts(general=3))[0] == ffa.EINVAL
+    # default: Winograd on the fp64 carrier only
+    assert ffa.plan_describe(8192, 8192, 65521, dA=ffa.F64, dC=ffa.F64)[1]["general"] == "winograd"
+    assert ffa.plan_describe(8192, 8192, 65521, dA=ffa.U16, dC=ffa.U16,
+                             opts=ffa.make_opts(levels=1))[1]["general"] == "classical"
+
+
 def test_plan_macs_follow_recursion():
     # products MACs = 3^l leaf SYRKs + 2 * 3^i general products of level i
     for L in range(0, 4):
