@@ -52,6 +52,9 @@ def parse():
                     help="INT8 product-kernel configuration + 1 for both plans (0: built-in choice)")
     ap.add_argument("--general", choices=["auto", "classical", "winograd"], default="auto",
                     help="general products P3, P4: one task, or one level of Strassen-Winograd")
+    ap.add_argument("--wino-min", type=int, default=0,
+                    help="Strassen-Winograd only on general products of at least this many rows "
+                         "(0: the library's choice)")
     ap.add_argument("--herk-base", choices=["auto", "2m", "4m"], default="auto",
                     help="Hermitian base case: the 2M method or four real products")
     ap.add_argument("--streams", choices=["auto", "one", "two"], default="auto",
@@ -369,7 +372,7 @@ def main():
     gen = {"auto": ffa.GENERAL_AUTO, "classical": ffa.GENERAL_CLASSICAL,
            "winograd": ffa.GENERAL_WINOGRAD}[args.general]
     opts = ffa.make_opts(levels=args.levels, streams=streams, herk_base=hb, kernel=args.kernel,
-                         general=gen)
+                         general=gen, wino_min=args.wino_min)
     dA_code = ffa._dtype_code(A)
     _, plan = ffa.plan_describe(n, k, p, hermitian=herm, dA=dA_code, dC=ffa._dtype_code(C, True),
                                 opts=opts)

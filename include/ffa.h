@@ -95,7 +95,12 @@ enum { FFA_CARRIER_AUTO = 0, FFA_CARRIER_INT8 = 1, FFA_CARRIER_F64 = 2 };
  *   general       the general products P3, P4 of each recursion node: FFA_GENERAL_CLASSICAL,
  *                 or FFA_GENERAL_WINOGRAD = one level of Strassen-Winograd (7 half-size
  *                 products, 15 block additions; real carriers only, else ignored);
- *                 FFA_GENERAL_AUTO = Winograd on the fp64 carrier, classical on INT8 */
+ *                 FFA_GENERAL_AUTO = Winograd on the fp64 carrier, classical on INT8
+ *   wino_min      Winograd applies to general products of at least this many rows; the
+ *                 smaller ones stay single products (their block additions cost more HBM
+ *                 time than the multiplications they save).  0 = built-in: every general
+ *                 product under FFA_GENERAL_WINOGRAD, 2048 rows under FFA_GENERAL_AUTO.
+ *                 Negative: FFA_EINVAL. */
 enum { FFA_LAUNCH_GRAPH = 0, FFA_LAUNCH_DIRECT = 1 };
 enum { FFA_HERK_AUTO = 0, FFA_HERK_2M = 1, FFA_HERK_4M = 2 };
 enum { FFA_GENERAL_AUTO = 0, FFA_GENERAL_CLASSICAL = 1, FFA_GENERAL_WINOGRAD = 2 };
@@ -113,7 +118,7 @@ typedef struct {
     int32_t streams;
     int32_t herk_base;
     int32_t general;
-    int32_t reserved;
+    int32_t wino_min;
 } ffa_opts;
 
 /* Context bound to a HIP device and stream (stream NULL = the null stream).

@@ -47,17 +47,17 @@ class Opts(ctypes.Structure):
                 ("carrier", ctypes.c_int32), ("check_inputs", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("launch", ctypes.c_int32), ("operands", ctypes.c_int32),
                 ("streams", ctypes.c_int32), ("herk_base", ctypes.c_int32),
-                ("general", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("general", ctypes.c_int32), ("wino_min", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 def make_opts(algo=ALGO_AUTO, levels=-1, cutoff=0, carrier=CARRIER_AUTO, check_inputs=False,
               kernel=0, launch=LAUNCH_GRAPH, operands=OPERANDS_AUTO, streams=STREAMS_AUTO,
-              herk_base=0, general=0):
+              herk_base=0, general=0, wino_min=0):
     return Opts(algo, levels, cutoff, carrier, int(bool(check_inputs)), kernel, launch, operands,
-                streams, herk_base, general)
+                streams, herk_base, general, wino_min)
 
 
 _lib = None

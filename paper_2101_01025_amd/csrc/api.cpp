@@ -2,6 +2,7 @@
 // the launch sequence of a plan on the context's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -69,11 +70,11 @@ ffa_opts default_opts()
 std::string key_of(const Problem& p)
 {
     char buf[256];
-    snprintf(buf, sizeof(buf), "%lld|%lld|%lld|%lld|%u|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%u|%u",
+    snprintf(buf, sizeof(buf), "%lld|%lld|%lld|%lld|%u|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%u|%u",
              (long long)p.n, (long long)p.k, (long long)p.lda, (long long)p.ldc, p.p, p.herm, p.dA,
              p.dC, p.opts.algo, p.opts.levels, p.opts.cutoff, p.opts.carrier, p.opts.check_inputs,
              p.opts.kernel, p.opts.operands, p.opts.streams * 16 + p.opts.herk_base * 4 + p.opts.general,
-             p.aligned ? 1 : 0, p.trans, p.alpha, p.beta);
+             p.opts.wino_min, p.aligned ? 1 : 0, p.trans, p.alpha, p.beta);
     return buf;
 }
 
@@ -805,8 +806,13 @@ int ffa_autotune_syrk(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA, co
         for (int L = 0; L <= 4; ++L) {
             if (L > 0 && ((n >> L) < 64 || k == 0)) break;
             for (int kc : kernel_candidates(cprobe))
-            for (int opr : {FFA_OPERANDS_PLANES, FFA_OPERANDS_RAW})
-            for (int gen : {FFA_GENERAL_CLASSICAL, FFA_GENERAL_WINOGRAD}) {
+            for (int opr : {FFA_OPERANDS_PLANES, FFA_OPERANDS_RAW}) {
+            // general products: single tasks, or Winograd down to 0 / 2048 / 4096 rows
+            // (each distinct plan timed once)
+            std::vector<size_t> wino_seen;
+            for (int wi = 0; wi < 4; ++wi) {
+                const int gen = wi == 0 ? FFA_GENERAL_CLASSICAL : FFA_GENERAL_WINOGRAD;
+                const int wmin = wi <= 1 ? 0 : (wi == 2 ? 2048 : 4096);
                 ffa_opts o = default_opts();
                 o.algo = L == 0 ? FFA_ALGO_CLASSICAL : FFA_ALGO_RECURSIVE;
                 o.levels = L;
@@ -814,12 +820,18 @@ int ffa_autotune_syrk(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA, co
                 o.carrier = car;
                 o.operands = opr;
                 o.general = gen;
+                o.wino_min = wmin;
                 Problem pr = base;
                 pr.opts = o;
                 // raw operands and Winograd only where the planner takes them
                 const Plan tp = make_plan(pr);
                 if (opr == FFA_OPERANDS_RAW && tp.gemm_src != SRC_RAW_U16) continue;
-                if (gen == FFA_GENERAL_WINOGRAD && !tp.wino) continue;
+                if (gen == FFA_GENERAL_WINOGRAD) {
+                    if (tp.wpre.empty() || std::find(wino_seen.begin(), wino_seen.end(), tp.wpre.size()) !=
+                                               wino_seen.end())
+                        continue;
+                    wino_seen.push_back(tp.wpre.size());
+                }
                 double ms = 0;
                 const int st =
                     time_calls(ctx, reps, [&] { return run_call(ctx, pr, A, nullptr, C, nullptr); }, &ms);
@@ -830,6 +842,7 @@ int ffa_autotune_syrk(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA, co
                     best_o = o;
                     found = true;
                 }
+            }
             }
         }
     }
@@ -952,9 +965,9 @@ int64_t ffa_tune_export(const ffa_ctx* c, char* buf, int64_t size)
         snprintf(rec, sizeof(rec),
                  "%s{\"n\":%lld,\"k\":%lld,\"p\":%u,\"herm\":%d,\"dA\":%d,\"dC\":%d,\"algo\":%d,"
                  "\"levels\":%d,\"cutoff\":%d,\"carrier\":%d,\"kernel\":%d,\"operands\":%d,"
-                 "\"general\":%d}",
+                 "\"general\":%d,\"wino_min\":%d}",
                  first ? "" : ",", n, k, p, herm, dA, dC, o.algo, o.levels, o.cutoff, o.carrier, o.kernel,
-                 o.operands, o.general);
+                 o.operands, o.general, o.wino_min);
         s += rec;
         first = false;
     }
@@ -995,6 +1008,7 @@ int ffa_tune_import(ffa_ctx* c, const char* json)
         long long v;  // fields added later: absent means the built-in choice
         if (json_int(p, e, "operands", &v)) o.operands = (int32_t)v;
         if (json_int(p, e, "general", &v)) o.general = (int32_t)v;
+        if (json_int(p, e, "wino_min", &v)) o.wino_min = (int32_t)v;
         record_tuned(c, n, k, (uint32_t)pp, (int)herm, (int)dA, (int)dC, o);
         ++taken;
         p = e + 1;

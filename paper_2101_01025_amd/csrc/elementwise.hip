@@ -464,10 +464,22 @@ struct RowV {
     }
 };
 
+// Workgroup w of a launch runs on XCD w mod 8.  Renumbers the grid so that each
+// XCD takes one contiguous range of work items: neighbouring items then share
+// that XCD's L2 (a bijection of [0, total)).
+__device__ __forceinline__ int xcd_contiguous(int lin, int total)
+{
+    const int q = total >> 3, r = total & 7;
+    const int xcd = lin & 7, slot = lin >> 3;
+    return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+}
+
 // Lower tile pairs (R, C), R >= C, of 64 x 64 tiles of the h x h blocks; one
 // workgroup of 512 threads per pair; thread = (row tr, 8-column group).  All
 // loads and stores move 8 consecutive elements of a row; loaded rows stay
-// packed in registers.
+// packed in registers.  Tiles are renumbered per XCD so that the tiles
+// sharing cache lines (narrow residues fill half a line per tile row) are
+// read through one L2.
 template <typename RT, typename OT, int CPLX>
 __global__ void __launch_bounds__(512) postadd(const PostaddTask* tasks, Bases b, FieldParams fp)
 {
@@ -476,9 +488,11 @@ __global__ void __launch_bounds__(512) postadd(const PostaddTask* tasks, Bases b
     __shared__ int32_t u1s[NP][TS][TS + 1];
     __shared__ int32_t p4s[NP][TS][TS + 1];
 
-    const PostaddTask& T = tasks[blockIdx.y];
+    const int gx = (int)gridDim.x;
+    const int logical = xcd_contiguous((int)(blockIdx.y * gx + blockIdx.x), gx * (int)gridDim.y);
+    const PostaddTask& T = tasks[logical / gx];
     const int h = T.h, nt = (h + TS - 1) / TS;
-    const int t = blockIdx.x;
+    const int t = logical % gx;
     int R = (int)((sqrtf(8.f * t + 1.f) - 1.f) * 0.5f);
     while ((R + 1) * (R + 2) / 2 <= t) ++R;
     while (R * (R + 1) / 2 > t) --R;

@@ -151,7 +151,7 @@ struct Builder {
     // level of Strassen-Winograd (operand sums, seven half-size products, combination).
     void general(const CarRef& x, const CarRef& z, const ResRef& c, int64_t h, int64_t w)
     {
-        if (!pl.wino) {
+        if (!pl.wino || h < pl.wino_min) {
             add_gemm(x, z, c, h, h, w, false, false);
             return;
         }
@@ -599,12 +599,16 @@ Plan make_plan(const Problem& pr)
     pl.pre.assign(pl.levels, {});
     pl.post.assign(pl.levels, {});
     pl.kernel_req = o.kernel;
-    if (o.general < FFA_GENERAL_AUTO || o.general > FFA_GENERAL_WINOGRAD) { pl.status = FFA_EINVAL; return pl; }
-    // measured: Winograd's block additions pay off for the fp64 products (9.84 vs 10.11 ms
-    // at 8192^2), not for the faster INT8 ones
+    if (o.general < FFA_GENERAL_AUTO || o.general > FFA_GENERAL_WINOGRAD || o.wino_min < 0) {
+        pl.status = FFA_EINVAL;
+        return pl;
+    }
+    // measured: Winograd's block additions pay off for the large fp64 products, not for
+    // the faster INT8 ones; below about 2048 rows the additions cost more than they save
     const bool wino_default = pl.carrier == CAR_F64;
     pl.wino = (o.general == FFA_GENERAL_WINOGRAD || (o.general == FFA_GENERAL_AUTO && wino_default)) &&
               !pl.cplx && pl.levels > 0;
+    pl.wino_min = o.wino_min > 0 ? o.wino_min : (o.general == FFA_GENERAL_AUTO ? 2048 : 0);
     choose_kernel(pl, pr.n >> pl.levels);
     // the problem's tasks on top of the settings above (pl is copied so that a
     // second attempt starts from the same state)
@@ -753,7 +757,7 @@ std::string describe(const Plan& pl)
              "\"gemm_tasks\":%zu,\"tiles\":%d,\"blocks\":%zu,\"cfg\":%d,\"tile\":%d,"
              "\"macs\":%lld,\"ykind\":%d,\"ya\":%d,\"yb\":%d,\"src\":\"%s\",\"streams\":%d,"
              "\"blocks_a_only\":%zu,\"herk_base\":\"%s\",\"real_tasks\":%zu,\"general\":\"%s\","
-             "\"wino_tasks\":%zu}",
+             "\"wino_tasks\":%zu,\"wino_min\":%lld}",
              pl.status, pl.levels, pl.carrier == CAR_F64 ? "f64" : "int8", pl.nl, pl.cplx,
              (long long)pl.npad, (long long)pl.kpad, pl.direct ? 1 : 0, pl.max_abs,
              (long long)pl.max_k, (long long)pl.ws_bytes, pl.cond.size(), pre.c_str(), post.c_str(),
@@ -761,7 +765,7 @@ std::string describe(const Plan& pl)
              (long long)pl.products_macs, pl.fp.ykind, pl.fp.ya,
              pl.fp.yb, pl.gemm_src == SRC_RAW_U16 ? "raw_u16" : "carrier", pl.fork ? 2 : 1,
              pl.sched.size(), pl.herk2m ? "2m" : (pl.cplx ? "4m" : "none"), pl.gemm_r.size(),
-             pl.wino ? "winograd" : "classical", pl.wpre.size());
+             pl.wpre.empty() ? "classical" : "winograd", pl.wpre.size(), (long long)pl.wino_min);
     return buf;
 }
 

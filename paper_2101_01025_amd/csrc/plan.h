@@ -49,6 +49,7 @@ struct Plan {
     int h2m_max_n = 0;
     // Strassen-Winograd for the general products
     bool wino = false;
+    int64_t wino_min = 0;              // general products with fewer rows stay one task
     std::vector<WinoPreTask> wpre;
     std::vector<WinoPostTask> wpost;
     int wpre_max_h = 0, wpre_max_w = 0, wpost_max_h = 0;

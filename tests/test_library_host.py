@@ -148,8 +148,28 @@ def test_plan_winograd_general_products():
                               opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL, general=ffa.GENERAL_WINOGRAD))
     assert st == 0 and d["general"] == "classical"
     assert ffa.plan_describe(10, 10, 251, opts=ffa.make_opts(general=3))[0] == ffa.EINVAL
-    # default: Winograd on the fp64 carrier only
-    assert ffa.plan_describe(8192, 8192, 65521, dA=ffa.F64, dC=ffa.F64)[1]["general"] == "winograd"
+    # default: Winograd on the fp64 carrier only, on general products of 2048 rows and more
+    st, d = ffa.plan_describe(8192, 8192, 65521, dA=ffa.F64, dC=ffa.F64)
+    assert st == 0 and d["levels"] == 4 and d["general"] == "winograd" and d["wino_min"] == 2048
+    assert d["wino_tasks"] == 2 + 2 * 3          # levels 0 and 1 (4096 and 2048 rows)
+    h = [8192 >> (i + 1) for i in range(4)]
+    macs = 81 * h[3] * (h[3] + 1) // 2 * h[3]          # the leaves: 512 x 512 SYRKs
+    for i in range(4):
+        m = h[i]
+        if m >= 2048:
+            macs += 2 * 3 ** i * 7 * (m // 2) ** 3
+        else:
+            macs += 2 * 3 ** i * m ** 3
+    assert d["macs"] == macs
+    # an explicit threshold, and every general product under the Winograd option
+    for wmin, tasks in ((4096, 2), (1, 2 + 6 + 18 + 54)):
+        st, d = ffa.plan_describe(8192, 8192, 65521, dA=ffa.F64, dC=ffa.F64,
+                                  opts=ffa.make_opts(wino_min=wmin))
+        assert st == 0 and d["wino_tasks"] == tasks
+    st, d = ffa.plan_describe(8192, 8192, 65521, dA=ffa.F64, dC=ffa.F64,
+                              opts=ffa.make_opts(general=ffa.GENERAL_WINOGRAD))
+    assert st == 0 and d["wino_tasks"] == 80 and d["wino_min"] == 0
+    assert ffa.plan_describe(10, 10, 251, opts=ffa.make_opts(wino_min=-1))[0] == ffa.EINVAL
     assert ffa.plan_describe(8192, 8192, 65521, dA=ffa.U16, dC=ffa.U16,
                              opts=ffa.make_opts(levels=1))[1]["general"] == "classical"
 
