@@ -310,9 +310,17 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
             }
         }
     };
-    // the fragments of k-step ks + 1 are read while the MFMAs of k-step ks run
+    // the fragments of k-step ks + 1 are read while the MFMAs of k-step ks run;
+    // hook() runs after the MFMAs of k-step HK are issued
     constexpr int NKS = KT / 32;
-    auto compute = [&](int buf) {
+    // Where stage st + 1 is written to LDS: before compute(st) when it was loaded at
+    // least one iteration earlier (PF >= 2), else halfway through compute(st) (its
+    // loads are issued at the start of the iteration).  Measured against writing it
+    // after compute(st): 1.86 vs 1.93 ms (one limb, 256-tiles, PF = 2) and 7.11 vs
+    // 7.26 ms (two limbs, PF = 1) for the products at n = k = 16384.
+    constexpr int SPOS = PF >= 2 ? 2 : 1;
+    constexpr int HK = SPOS == 1 ? NKS / 2 - 1 : -1;
+    auto compute = [&](int buf, auto hook) {
         const char* base = lds + buf * STAGE;
         v4i af[2][NA][FM], bf[2][NB][FN];
         load_frags(base, 0, af[0], bf[0]);
@@ -320,10 +328,13 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
         for (int ks = 0; ks < NKS; ++ks) {
             if (ks + 1 < NKS) load_frags(base, ks + 1, af[(ks + 1) & 1], bf[(ks + 1) & 1]);
             mfmas(af[ks & 1], bf[ks & 1]);
+            if (ks == HK) hook();
         }
     };
 
-    // ---- pipeline: PF k-tiles in flight in registers, two LDS buffers
+    // ---- pipeline: PF k-tiles in flight in registers, two LDS buffers.  Stage
+    // st + 1 goes to the buffer that compute(st - 1) read, which the barrier ending
+    // iteration st - 1 released, so it may be written while compute(st) runs.
 #pragma unroll
     for (int u = 0; u < PF; ++u)
         if (u < nst) gload(u, ra[u], rb[u]);
@@ -334,10 +345,13 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
         for (int u = 0; u < PF; ++u) {
             const int st = st0 + u;
             if (st < nst) {
+                auto next = [&] {
+                    if (st + 1 < nst) sstore((st + 1) & 1, ra[(u + 1) % PF], rb[(u + 1) % PF]);
+                };
                 // register slot u held stage st (already in LDS): refill it with stage st + PF
+                if (SPOS == 2) next();
                 if (st + PF < nst) gload(st + PF, ra[u], rb[u]);
-                compute(st & 1);
-                if (st + 1 < nst) sstore((st + 1) & 1, ra[(u + 1) % PF], rb[(u + 1) % PF]);
+                compute(st & 1, next);
                 __syncthreads();
             }
         }
@@ -503,7 +517,6 @@ struct CfgInfo {
     X(1, 1, 0, 256, 2, 4, 64, 2)          \
     X(2, 1, 0, 128, 2, 2, 128, 2)         \
     X(4, 1, 1, 128, 2, 2, 128, 2)         \
-    X(6, 2, 0, 128, 2, 2, 64, 2)          \
     X(8, 2, 1, 64, 2, 2, 128, 2)          \
     X(9, 2, 0, 128, 2, 2, 128, 1)         \
     X(10, 1, 0, 256, 2, 4, 128, 2)        \
@@ -511,7 +524,9 @@ struct CfgInfo {
     X(12, 1, 0, 256, 4, 2, 64, 2)         \
     X(13, 2, 0, 64, 2, 2, 128, 2)         \
     X(14, 1, 0, 64, 2, 2, 128, 2)         \
-    X(15, 2, 0, 128, 2, 4, 128, 1)
+    X(15, 2, 0, 128, 2, 4, 128, 1)        \
+    X(16, 2, 0, 128, 2, 4, 128, 2)        \
+    X(17, 2, 0, 64, 2, 2, 64, 2)
 
 static CfgInfo cfg_info(int id)
 {
@@ -534,7 +549,9 @@ int gemm_i8_config_valid(int cfg, int nl, int cplx)
 int gemm_i8_default_config(int nl, int cplx, int64_t max_dim)
 {
     if (cplx) return nl == 1 ? 4 : 8;
-    if (nl == 2) return 15;  // 8 waves: 7.95 ms against 8.18 ms for configuration 9 at n = k = 16384
+    // 8 waves, two k-tiles in flight: 6.85 ms against 7.11 ms for configuration 15 (one
+    // k-tile in flight) for the products at n = k = 16384
+    if (nl == 2) return 16;
     return max_dim >= 2048 ? 10 : 2;
 }
 
