@@ -320,6 +320,10 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     // 7.26 ms (two limbs, PF = 1) for the products at n = k = 16384.
     constexpr int SPOS = PF >= 2 ? 2 : 1;
     constexpr int HK = SPOS == 1 ? NKS / 2 - 1 : -1;
+    // The compiler's MFMA / LDS-read interleaving strategy 0 for the two-limb products
+    // read from carrier planes (6.40 vs 6.82 ms of products at n = k = 16384).  One
+    // limb (its 128 accumulator registers) and raw operands would spill with it.
+    constexpr bool IGLP = NL == 2 && !RAW;
     auto compute = [&](int buf, auto hook) {
         const char* base = lds + buf * STAGE;
         v4i af[2][NA][FM], bf[2][NB][FN];
@@ -330,6 +334,7 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
             mfmas(af[ks & 1], bf[ks & 1]);
             if (ks == HK) hook();
         }
+        if (IGLP) __builtin_amdgcn_iglp_opt(0);
     };
 
     // ---- pipeline: PF k-tiles in flight in registers, two LDS buffers.  Stage
