@@ -20,8 +20,13 @@ typedef double v2d __attribute__((ext_vector_type(2)));
 
 constexpr int KTD = 16;  // doubles of K per pipeline stage
 
+// Two waves per SIMD (two workgroups per CU, bounded by LDS as well): the compiler
+// then keeps the accumulators in ordinary VGPRs (212 of 256) instead of spreading
+// 330 registers over VGPRs and AGPRs at one wave per SIMD, and the second wave
+// hides the fragment-read and barrier latency of the first (products 8.48 -> 6.18 ms
+// at n = k = 8192, four levels).
 template <int BT, int WGM, int WGN>
-__global__ void __launch_bounds__(WGM* WGN * 64)
+__global__ void __launch_bounds__(WGM* WGN * 64) __attribute__((amdgpu_waves_per_eu(2, 2)))
     gemm_f64(Bases bases, const GemmTask* __restrict__ tasks, const TileEnt* __restrict__ sched,
              FieldParams fp)
 {
