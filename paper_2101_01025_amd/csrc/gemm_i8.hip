@@ -531,7 +531,9 @@ struct CfgInfo {
     X(14, 1, 0, 64, 2, 2, 128, 2)         \
     X(15, 2, 0, 128, 2, 4, 128, 1)        \
     X(16, 2, 0, 128, 2, 4, 128, 2)        \
-    X(17, 2, 0, 64, 2, 2, 64, 2)
+    X(17, 2, 0, 64, 2, 2, 64, 2)          \
+    X(18, 2, 0, 128, 2, 4, 64, 4)         \
+    X(19, 2, 0, 128, 2, 4, 64, 3)
 
 static CfgInfo cfg_info(int id)
 {

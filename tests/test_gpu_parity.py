@@ -107,6 +107,26 @@ def test_winograd_general_products(levels, p, dt, shape):
     check_syrk(A, p, dt, out, **kw)
 
 
+@pytest.mark.parametrize("p,dt", [(65521, torch.float64), (251, torch.int8)])
+@pytest.mark.parametrize("wino_min", [100, 200])
+def test_winograd_threshold_mixed_plans(p, dt, wino_min):
+    """Strassen-Winograd on the general products of at least wino_min rows only: the
+    upper levels go through it, the lower ones stay single products."""
+    ffa = _ffa()
+    n, k = 700, 650
+    dA = ffa.F64 if dt == torch.float64 else ffa.I8_CENTRED
+    st, d = ffa.plan_describe(n, k, p, dA=dA, dC=ffa.U16 if p > 255 else ffa.U8,
+                              opts=ffa.make_opts(levels=3, general=ffa.GENERAL_WINOGRAD,
+                                                 wino_min=wino_min))
+    assert st == 0 and 0 < d["wino_tasks"] < 2 + 6 + 18
+    A = si.uniform_residues(n, k, p, 1300 + wino_min)
+    out = torch.uint8 if p < 256 else torch.uint16
+    kw = dict(levels=3, general=ffa.GENERAL_WINOGRAD, wino_min=wino_min)
+    if dt == torch.float64:
+        kw["carrier"] = ffa.CARRIER_F64
+    check_syrk(A, p, dt, out, **kw)
+
+
 @pytest.mark.parametrize("p", [3, 5, 13, 241])
 def test_int8_small_primes(p):
     # p = 3 and 251 use Y = [[a,b],[-b,a]] (x) I; p = 5, 13, 241 use Y = sqrt(-1) I
