@@ -533,7 +533,7 @@ struct CfgInfo {
     X(16, 2, 0, 128, 2, 4, 128, 2)        \
     X(17, 2, 0, 64, 2, 2, 64, 2)          \
     X(18, 2, 0, 128, 2, 4, 64, 4)         \
-    X(19, 2, 0, 128, 2, 4, 64, 3)
+    X(21, 2, 0, 64, 2, 2, 64, 4)
 
 static CfgInfo cfg_info(int id)
 {
