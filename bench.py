@@ -331,7 +331,8 @@ def cpu_baseline(w, seconds):
             t0 = time.perf_counter()
             oracle.syrk_modp(a, p)
         t = time.perf_counter() - t0
-        if t > seconds / 4 or m >= n:
+        # the timed sample itself is the baseline: keep growing it to about `seconds`
+        if t > 0.6 * seconds or m >= n:
             break
         m = min(n, int(m * max(1.3, min(4.0, (seconds / max(t, 1e-3)) ** 0.5))))
     frac = (m * (m + 1) / 2) / (n * (n + 1) / 2)
