@@ -74,7 +74,9 @@ enum { FFA_CARRIER_AUTO = 0, FFA_CARRIER_INT8 = 1, FFA_CARRIER_F64 = 2 };
  *                 2 limbs for p < 2^16); F64 = doubles on FP64 MFMA (p < 2^26, real only)
  *   check_inputs  nonzero: verify every entry of A (synchronises the stream; FFA_ERANGE)
  *   kernel        INT8 product-kernel configuration + 1 (tile shape, k-tile, pipeline depth);
- *                 0 = built-in choice; a configuration that does not fit the carrier is ignored
+ *                 0 = built-in choice; a configuration that does not fit the carrier is ignored.
+ *                 Over F_p[i] with the 2M base case, a real configuration applies to the
+ *                 real products of the base case, a complex one to the complex products.
  *   launch        batched execution only: FFA_LAUNCH_GRAPH (default) replays the plan's
  *                 launch sequence as one captured hipGraph; FFA_LAUNCH_DIRECT enqueues
  *                 the kernels one by one

@@ -542,6 +542,8 @@ void choose_kernel(Plan& pl, int64_t max_dim)
     if (pl.herk2m) {
         // the real launch of the 2M base case; K is padded for both k-tiles
         pl.gemm_cfg_r = gemm_i8_default_config(pl.nl, 0, max_dim);
+        if (pl.kernel_req > 0 && gemm_i8_config_valid(pl.kernel_req - 1, pl.nl, 0))
+            pl.gemm_cfg_r = pl.kernel_req - 1;
         pl.ktile = std::max(pl.ktile, gemm_i8_config_ktile(pl.gemm_cfg_r));
     }
 }
@@ -757,7 +759,7 @@ std::string describe(const Plan& pl)
              "\"gemm_tasks\":%zu,\"tiles\":%d,\"blocks\":%zu,\"cfg\":%d,\"tile\":%d,"
              "\"macs\":%lld,\"ykind\":%d,\"ya\":%d,\"yb\":%d,\"src\":\"%s\",\"streams\":%d,"
              "\"blocks_a_only\":%zu,\"herk_base\":\"%s\",\"real_tasks\":%zu,\"general\":\"%s\","
-             "\"wino_tasks\":%zu,\"wino_min\":%lld}",
+             "\"wino_tasks\":%zu,\"wino_min\":%lld,\"cfg_real\":%d}",
              pl.status, pl.levels, pl.carrier == CAR_F64 ? "f64" : "int8", pl.nl, pl.cplx,
              (long long)pl.npad, (long long)pl.kpad, pl.direct ? 1 : 0, pl.max_abs,
              (long long)pl.max_k, (long long)pl.ws_bytes, pl.cond.size(), pre.c_str(), post.c_str(),
@@ -765,7 +767,8 @@ std::string describe(const Plan& pl)
              (long long)pl.products_macs, pl.fp.ykind, pl.fp.ya,
              pl.fp.yb, pl.gemm_src == SRC_RAW_U16 ? "raw_u16" : "carrier", pl.fork ? 2 : 1,
              pl.sched.size(), pl.herk2m ? "2m" : (pl.cplx ? "4m" : "none"), pl.gemm_r.size(),
-             pl.wpre.empty() ? "classical" : "winograd", pl.wpre.size(), (long long)pl.wino_min);
+             pl.wpre.empty() ? "classical" : "winograd", pl.wpre.size(), (long long)pl.wino_min,
+             pl.herk2m ? pl.gemm_cfg_r : -1);
     return buf;
 }
 

@@ -126,3 +126,29 @@ def test_complex_config(cfg, p):
         gr, gi = _host(Cr), _host(Ci)
         assert np.array_equal(gr[low], er[low]) and np.array_equal(gi[low], ei[low]), (cfg, levels)
         assert (gr[~low] == -7).all() and (gi[~low] == -7).all()
+
+
+_R2 = [c for c in _REAL_CASES if c[1] == 65521]
+
+
+@pytest.mark.parametrize("cfg,p", _R2, ids=_ids(_R2))
+def test_herk_2m_real_config(cfg, p):
+    """The 2M base case over F_p[i] (p = 65519) with its real products on this two-limb
+    configuration."""
+    ffa = _ffa()
+    p = 65519
+    n, k = 230, 300
+    Ar, Ai = si.complex_residues(n, k, p, 970 + cfg)
+    er, ei = oracle.herk_modp2(Ar, Ai, p)
+    low = np.tril(np.ones((n, n), dtype=bool))
+    st, d = ffa.plan_describe(n, k, p, hermitian=True, dA=ffa.U16, dC=ffa.U16,
+                              opts=ffa.make_opts(kernel=cfg + 1, herk_base=ffa.HERK_2M))
+    assert st == 0 and d["cfg_real"] == cfg
+    _say("2M real config", cfg)
+    Cr = torch.full((n, n), 0xBEEF, dtype=torch.int32, device="cuda").to(torch.uint16)
+    Ci = torch.full((n, n), 0xBEEF, dtype=torch.int32, device="cuda").to(torch.uint16)
+    ffa.herk_modp2(_u16(Ar), _u16(Ai), p, C_re=Cr, C_im=Ci, kernel=cfg + 1, herk_base=ffa.HERK_2M)
+    torch.cuda.synchronize()
+    gr, gi = _host(Cr), _host(Ci)
+    assert np.array_equal(gr[low], er[low]) and np.array_equal(gi[low], ei[low]), cfg
+    assert (gr[~low] == 0xBEEF).all() and (gi[~low] == 0xBEEF).all()

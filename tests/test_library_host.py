@@ -129,6 +129,12 @@ def test_plan_herk_base_case_2m():
                               opts=ffa.make_opts(levels=1))
     assert st == 0 and d["real_tasks"] == 6 and d["gemm_tasks"] == 2
     assert ffa.plan_describe(n, k, 65519, hermitian=True, opts=ffa.make_opts(herk_base=3))[0] == ffa.EINVAL
+    # the kernel option: a real two-limb configuration selects the 2M real products'
+    st, d0 = ffa.plan_describe(n, k, 65519, hermitian=True, dA=ffa.U16, dC=ffa.U16)
+    assert st == 0 and d0["cfg_real"] >= 0
+    st, d1 = ffa.plan_describe(n, k, 65519, hermitian=True, dA=ffa.U16, dC=ffa.U16,
+                               opts=ffa.make_opts(kernel=14))   # configuration 13: 64-tiles
+    assert st == 0 and d1["cfg_real"] == 13 and d1["cfg"] == d0["cfg"]
 
 
 def test_plan_winograd_general_products():
