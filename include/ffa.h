@@ -186,6 +186,14 @@ int ffa_batch_syrk_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int
 int ffa_batch_offsets(const ffa_batch* b, int64_t* a_off, int64_t* lda, int64_t* c_off,
                       int64_t* a_total, int64_t* c_total);
 int ffa_batch_syrk_exec(ffa_batch* b, const void* A_packed, void* C_packed);
+/* Batched C_i = Low(A_i A_i^H) over F_{p^2} (as ffa_herk_modp2, one p = 3 mod 4),
+ * with the packed layout, ownership and launch modes of the real batch.  The four
+ * buffers (A_re, A_im, C_re, C_im) each hold the planes at the offsets that
+ * ffa_batch_offsets reports, are 16-byte aligned, and key the captured graph
+ * together.  FFA_EINVAL: a plan of the other kind, or a null or misaligned buffer. */
+int ffa_batch_herk_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int64_t* k,
+                        uint32_t p, int dA, int dC, const ffa_opts* opts, ffa_batch** out);
+int ffa_batch_herk_exec(ffa_batch* b, const void* A_re, const void* A_im, void* C_re, void* C_im);
 int ffa_batch_destroy(ffa_batch* b);
 /* The batch plan as JSON (the fields of ffa_plan_describe, summed or maximal over
  * the problems: levels is the deepest recursion, macs the total per limb product). */
@@ -216,7 +224,8 @@ int ffa_autotune_syrk(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p,
                       int reps, ffa_opts* best, double* best_ms);
 /* Same for a batch plan: re-plans with each carrier, product-kernel configuration,
  * recursion cutoff (classical, 256, 384) and operand source (limb planes, or raw
- * uint16 rows where the planner allows them), keeps the fastest in the plan. */
+ * uint16 rows where the planner allows them), keeps the fastest in the plan.
+ * Hermitian batches: FFA_EUNSUPPORTED. */
 int ffa_batch_autotune(ffa_batch* b, const void* A_packed, void* C_packed, int reps,
                        ffa_opts* best, double* best_ms);
 

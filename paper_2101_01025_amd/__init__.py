@@ -31,7 +31,7 @@ SYMBOLS = [
     "ffa_batch_offsets", "ffa_batch_syrk_exec", "ffa_batch_destroy", "ffa_plan_describe",
     "ffa_profile_enable", "ffa_profile_read", "ffa_profile_reset",
     "ffa_autotune_syrk", "ffa_batch_autotune", "ffa_tune_export", "ffa_tune_import",
-    "ffa_batch_describe", "ffa_syrk_modp_ex",
+    "ffa_batch_describe", "ffa_syrk_modp_ex", "ffa_batch_herk_plan", "ffa_batch_herk_exec",
 ]
 PHASE_COND, PHASE_PRE, PHASE_PRODUCTS, PHASE_POST = 0, 1, 2, 3
 
@@ -85,6 +85,8 @@ def lib():
         L.ffa_batch_syrk_plan.argtypes = [P, i64, P, P, u32, i32, i32, P, ctypes.POINTER(P)]
         L.ffa_batch_offsets.argtypes = [P, P, P, P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.ffa_batch_syrk_exec.argtypes = [P, P, P]
+        L.ffa_batch_herk_plan.argtypes = [P, i64, P, P, u32, i32, i32, P, ctypes.POINTER(P)]
+        L.ffa_batch_herk_exec.argtypes = [P, P, P, P, P]
         L.ffa_batch_destroy.argtypes = [P]
         L.ffa_profile_enable.argtypes = [P, i32]
         L.ffa_profile_read.argtypes = [P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
@@ -288,6 +290,8 @@ def tune_import(text, device_index=0):
 class BatchSyrk:
     """Batched Low(A_i A_i^T) mod p over a packed layout (ffa_batch_syrk_*)."""
 
+    _plan_fn = "ffa_batch_syrk_plan"
+
     def __init__(self, ns, ks, p, dA, dC, device_index=0, opts=None, **kw):
         import numpy as np
         self.count = len(ns)
@@ -297,9 +301,9 @@ class BatchSyrk:
         self.ctx = context(device_index)
         self.opts = opts if opts is not None else make_opts(**kw)
         h = ctypes.c_void_p()
-        _check(lib().ffa_batch_syrk_plan(self.ctx, self.count, self.ns.ctypes.data,
-                                         self.ks.ctypes.data, p, dA, dC, ctypes.byref(self.opts),
-                                         ctypes.byref(h)), "batch plan")
+        _check(getattr(lib(), self._plan_fn)(self.ctx, self.count, self.ns.ctypes.data,
+                                             self.ks.ctypes.data, p, dA, dC, ctypes.byref(self.opts),
+                                             ctypes.byref(h)), "batch plan")
         self.handle = h
         self.a_off = np.zeros(self.count, np.int64)
         self.lda = np.zeros(self.count, np.int64)
@@ -355,3 +359,22 @@ class BatchSyrk:
             self.close()
         except Exception:
             pass
+
+
+class BatchHerk(BatchSyrk):
+    """Batched Low(A_i A_i^H) over F_p[i] (ffa_batch_herk_*): planar real and
+    imaginary parts, each in the packed layout of the plan (the same offsets in
+    the four buffers)."""
+
+    _plan_fn = "ffa_batch_herk_plan"
+
+    def run(self, A_re, A_im, C_re, C_im):
+        torch = _torch()
+        lib().ffa_set_stream(self.ctx, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        _check(lib().ffa_batch_herk_exec(self.handle, ctypes.c_void_p(A_re.data_ptr()),
+                                         ctypes.c_void_p(A_im.data_ptr()),
+                                         ctypes.c_void_p(C_re.data_ptr()),
+                                         ctypes.c_void_p(C_im.data_ptr())), "batch herk exec")
+
+    def autotune(self, *a, **kw):
+        raise FfaError(EUNSUPPORTED, "the batch autotuner covers A A^T batches")

@@ -50,11 +50,13 @@ struct ffa_batch {
     Plan plan;
     char* ws = nullptr;  // the plan's own workspace
     int64_t ws_bytes = 0;
-    // captured launch sequence for one (A, C) pair
+    // captured launch sequence for one set of buffers (A, C; and A_im, C_im over F_p[i])
     hipStream_t cap = nullptr;
     hipGraphExec_t gexec = nullptr;
     const void* gA = nullptr;
     void* gC = nullptr;
+    const void* gA2 = nullptr;
+    void* gC2 = nullptr;
 };
 
 namespace {
@@ -430,8 +432,37 @@ int capture_graph(ffa_batch* b, const Bases& bs)
     (void)hipGraphDestroy(g);
     b->gA = bs.p[BUF_A];
     b->gC = bs.p[BUF_C];
+    b->gA2 = bs.p[BUF_A2];
+    b->gC2 = bs.p[BUF_C2];
     return FFA_OK;
 }
+
+// Runs a batch plan on its packed buffers: directly, or by replaying the
+// captured graph (captured again when a buffer changes).
+int batch_exec(ffa_batch* b, const Bases& bs)
+{
+    ffa_ctx* c = b->ctx;
+    hipError_t he = hipSetDevice(c->device);
+    if (he != hipSuccess) return dev_fail(c, he);
+    bool direct = b->prs[0].opts.launch == FFA_LAUNCH_DIRECT || c->prof || b->plan.check_inputs;
+    if (!direct) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        he = hipStreamIsCapturing(c->stream, &cs);
+        if (he != hipSuccess) return dev_fail(c, he);
+        direct = cs != hipStreamCaptureStatusNone;  // the caller's capture records the kernels
+    }
+    if (direct) return run_plan(c, b->plan, bs, b->ws);
+    if (!b->gexec || b->gA != bs.p[BUF_A] || b->gC != bs.p[BUF_C] || b->gA2 != bs.p[BUF_A2] ||
+        b->gC2 != bs.p[BUF_C2]) {
+        const int st = capture_graph(b, bs);
+        if (st) return st;
+    }
+    he = hipGraphLaunch(b->gexec, c->stream);
+    return he == hipSuccess ? FFA_OK : dev_fail(c, he);
+}
+
+int batch_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int64_t* k, uint32_t p, int herm,
+               int dA, int dC, const ffa_opts* opts, ffa_batch** out);
 
 }  // namespace
 
@@ -613,6 +644,22 @@ int ffa_herk_modp2(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA, const
 int ffa_batch_syrk_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int64_t* k,
                         uint32_t p, int dA, int dC, const ffa_opts* opts, ffa_batch** out)
 {
+    return batch_plan(ctx, count, n, k, p, 0, dA, dC, opts, out);
+}
+
+int ffa_batch_herk_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int64_t* k,
+                        uint32_t p, int dA, int dC, const ffa_opts* opts, ffa_batch** out)
+{
+    return batch_plan(ctx, count, n, k, p, 1, dA, dC, opts, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+int batch_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int64_t* k, uint32_t p, int herm,
+               int dA, int dC, const ffa_opts* opts, ffa_batch** out)
+{
     if (!ctx || !out || count <= 0 || !n || !k) return FFA_EINVAL;
     *out = nullptr;
     std::vector<Problem> prs(count);
@@ -622,6 +669,7 @@ int ffa_batch_syrk_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int
         prs[i].n = n[i];
         prs[i].k = k[i];
         prs[i].p = p;
+        prs[i].herm = herm;
         prs[i].dA = dA;
         prs[i].dC = dC;
         prs[i].opts = o;
@@ -648,6 +696,10 @@ int ffa_batch_syrk_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int
     return FFA_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
 int ffa_batch_offsets(const ffa_batch* b, int64_t* a_off, int64_t* lda, int64_t* c_off,
                       int64_t* a_total, int64_t* c_total)
 {
@@ -663,28 +715,25 @@ int ffa_batch_offsets(const ffa_batch* b, int64_t* a_off, int64_t* lda, int64_t*
 
 int ffa_batch_syrk_exec(ffa_batch* b, const void* A_packed, void* C_packed)
 {
-    if (!b || !C_packed || (!A_packed && b->plan.a_total > 0)) return FFA_EINVAL;
+    if (!b || b->plan.cplx || !C_packed || (!A_packed && b->plan.a_total > 0)) return FFA_EINVAL;
     if (((uintptr_t)A_packed % 16) || ((uintptr_t)C_packed % 16)) return FFA_EINVAL;
-    ffa_ctx* c = b->ctx;
-    hipError_t he = hipSetDevice(c->device);
-    if (he != hipSuccess) return dev_fail(c, he);
     Bases bs{};
     bs.p[BUF_A] = (char*)A_packed;
     bs.p[BUF_C] = (char*)C_packed;
-    bool direct = b->prs[0].opts.launch == FFA_LAUNCH_DIRECT || c->prof || b->plan.check_inputs;
-    if (!direct) {
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        he = hipStreamIsCapturing(c->stream, &cs);
-        if (he != hipSuccess) return dev_fail(c, he);
-        direct = cs != hipStreamCaptureStatusNone;  // the caller's capture records the kernels
-    }
-    if (direct) return run_plan(c, b->plan, bs, b->ws);
-    if (!b->gexec || b->gA != A_packed || b->gC != C_packed) {
-        const int st = capture_graph(b, bs);
-        if (st) return st;
-    }
-    he = hipGraphLaunch(b->gexec, c->stream);
-    return he == hipSuccess ? FFA_OK : dev_fail(c, he);
+    return batch_exec(b, bs);
+}
+
+int ffa_batch_herk_exec(ffa_batch* b, const void* A_re, const void* A_im, void* C_re, void* C_im)
+{
+    if (!b || !b->plan.cplx || !C_re || !C_im) return FFA_EINVAL;
+    if (b->plan.a_total > 0 && (!A_re || !A_im)) return FFA_EINVAL;
+    if (((uintptr_t)A_re | (uintptr_t)A_im | (uintptr_t)C_re | (uintptr_t)C_im) % 16) return FFA_EINVAL;
+    Bases bs{};
+    bs.p[BUF_A] = (char*)A_re;
+    bs.p[BUF_A2] = (char*)A_im;
+    bs.p[BUF_C] = (char*)C_re;
+    bs.p[BUF_C2] = (char*)C_im;
+    return batch_exec(b, bs);
 }
 
 int ffa_batch_describe(const ffa_batch* b, char* buf, int64_t size)
@@ -857,6 +906,7 @@ int ffa_batch_autotune(ffa_batch* b, const void* A_packed, void* C_packed, int r
                        double* best_ms)
 {
     if (!b || reps <= 0) return FFA_EINVAL;
+    if (b->plan.cplx) return FFA_EUNSUPPORTED;
     ffa_ctx* c = b->ctx;
     const int64_t cutoffs[] = {0, 256, 384};
     double best_t = 1e30;

@@ -650,6 +650,9 @@ Plan make_batch_plan(const std::vector<Problem>& prs)
     pl.cplx = p0.herm ? 1 : 0;
     pl.fp = cm.fp;
     pl.check_inputs = p0.opts.check_inputs ? 1 : 0;
+    if (p0.opts.herk_base < FFA_HERK_AUTO || p0.opts.herk_base > FFA_HERK_4M) { pl.status = FFA_EINVAL; return pl; }
+    pl.herk2m = pl.cplx && pl.carrier == CAR_I8 && p0.opts.herk_base != FFA_HERK_4M;
+    pl.fp.npo = pl.herk2m ? 4 : 3;
     int maxL = 0;
     std::vector<int> L(prs.size());
     for (size_t i = 0; i < prs.size(); ++i) {
@@ -657,7 +660,7 @@ Plan make_batch_plan(const std::vector<Problem>& prs)
             pl.status = FFA_EINVAL;
             return pl;
         }
-        L[i] = choose_levels(prs[i].n, prs[i].k, p0.opts, pl.carrier, pl.nl, pl.cplx, false);
+        L[i] = choose_levels(prs[i].n, prs[i].k, p0.opts, pl.carrier, pl.nl, pl.cplx, pl.herk2m);
         maxL = std::max(maxL, L[i]);
     }
     pl.levels = maxL;

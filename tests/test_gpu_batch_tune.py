@@ -169,3 +169,46 @@ def test_autotune_syrk_and_tuned_default(p, n, k, dt):
     C2 = ffa.syrk_modp(A2, p)
     torch.cuda.synchronize()
     assert np.array_equal(np.tril(_host(C2)), oracle.syrk_modp(Ares[: n - 3, : k - 5], p))
+
+
+@pytest.mark.parametrize("base", ["2m", "4m"])
+@pytest.mark.parametrize("launch", ["graph", "direct"])
+def test_batch_herk(base, launch):
+    """Batched Low(A_i A_i^H) over F_p[i], p = 65519: every problem compared whole with
+    the oracle; the graph mode is replayed on changed buffers (re-capture) and
+    checked again."""
+    ffa = _ffa()
+    p = 65519
+    _say("batch herk", base, launch)
+    ns, ks = si.batch_shapes(18, 306, nmin=1, nmax=300)
+    B = ffa.BatchHerk(ns, ks, p, ffa.U16, ffa.U16,
+                      herk_base=ffa.HERK_2M if base == "2m" else ffa.HERK_4M,
+                      launch=ffa.LAUNCH_GRAPH if launch == "graph" else ffa.LAUNCH_DIRECT,
+                      cutoff=128)
+    mats = [si.complex_residues(int(n), int(k), p, 700 + i) for i, (n, k) in enumerate(zip(ns, ks))]
+    Ar = _u16(B.pack([m[0] for m in mats], np.int64))
+    Ai = _u16(B.pack([m[1] for m in mats], np.int64))
+    exp = [oracle.herk_modp2(m[0], m[1], p) for m in mats]
+
+    def check(Cr, Ci):
+        gr, gi = _host(Cr), _host(Ci)
+        for i in range(len(ns)):
+            n = int(ns[i])
+            o = int(B.c_off[i])
+            r = gr[o:o + n * n].reshape(n, n)
+            m = gi[o:o + n * n].reshape(n, n)
+            low = np.tril(np.ones((n, n), dtype=bool))
+            assert np.array_equal(r[low], exp[i][0][low]), f"re of problem {i}"
+            assert np.array_equal(m[low], exp[i][1][low]), f"im of problem {i}"
+            assert (r[~low] == 0xBEEF).all() and (m[~low] == 0xBEEF).all(), f"upper of problem {i}"
+
+    pairs = [(_sentinel(B.c_total), _sentinel(B.c_total)) for _ in range(2)]
+    for j in (0, 0, 1):
+        Cr, Ci = pairs[j]
+        B.run(Ar, Ai, Cr, Ci)
+        torch.cuda.synchronize()
+        check(Cr, Ci)
+        _busy_work()
+    with pytest.raises(ffa.FfaError):
+        B.autotune(Ar, Cr)
+    B.close()
