@@ -406,6 +406,10 @@ def main():
         "phases_ms": phases,
         "product_launches_per_step": launches["products"],
     }
+    if herm:
+        # value counts n^2 k operations of F_{p^2}; each is four products of F_p
+        out["units"] = {"value": "n^2k/s of F_p^2 operations",
+                        "fp_equivalent": 4.0 * n * n * k / (ms * 1e-3)}
     # roofline of the dominant kernel, the grouped product kernel: algorithmic ops of
     # its launches in one step over their summed durations (HIP events per launch)
     limb2 = plan["limbs"] ** 2  # macs counts real products (a complex one is four)
