@@ -149,12 +149,16 @@ int launch_gemm_f64(const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks
     if (nblocks <= 0) return 0;
     constexpr int lds_bytes = 2 * 2 * BT_F64 * KTD * 8;
     auto kern = gemm_f64<BT_F64, 2, 2>;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    // the LDS limit is raised once per device the kernel runs on
+    static uint64_t attr_devices = 0;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    const uint64_t bit = 1ull << (dev & 63);
+    if (!(attr_devices & bit)) {
+        e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         if (e != hipSuccess) return (int)e;
-        attr_set = true;
+        attr_devices |= bit;
     }
     hipLaunchKernelGGL(kern, dim3(nblocks), dim3(256), lds_bytes, (hipStream_t)stream, b,
                        d_tasks, d_sched, fp);

@@ -569,12 +569,16 @@ static int launch_cfg(const GemmTask* d_tasks, const TileEnt* d_sched, int nbloc
     constexpr int NA = (CPLX ? 2 : 1) * NL, NB = NL;
     constexpr int lds_bytes = 2 * (NA + NB) * BT * KT;
     auto kern = gemm_i8<NL, CPLX, BT, WGM, WGN, KT, PF, SRC>;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    // the LDS limit is raised once per device the kernel runs on
+    static uint64_t attr_devices = 0;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    const uint64_t bit = 1ull << (dev & 63);
+    if (!(attr_devices & bit)) {
+        e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         if (e != hipSuccess) return (int)e;
-        attr_set = true;
+        attr_devices |= bit;
     }
     hipLaunchKernelGGL(kern, dim3(nblocks), dim3(WGM * WGN * 64), lds_bytes, s, b, d_tasks,
                        d_sched, fp);
