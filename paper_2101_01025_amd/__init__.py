@@ -216,17 +216,19 @@ def syrk_modp(A, p, C=None, out_dtype=None, opts=None, alpha=1, beta=0, trans=Fa
     ctx = _prep(A)
     k, n = A.shape if trans else A.shape[::-1]
     C = _out(C, n, A.device, out_dtype or default_out_dtype(p))
-    o = opts if opts is not None else make_opts(**kw)
+    # no options at all: NULL, so that the library applies an autotuned record for the shape
+    o = opts if opts is not None else (make_opts(**kw) if kw else None)
+    ob = ctypes.byref(o) if o is not None else None
     lda = max(A.stride(0), A.shape[1], 1)
     if alpha == 1 and beta == 0 and not trans:
         st = lib().ffa_syrk_modp(ctx, n, k, p, _dtype_code(A), ctypes.c_void_p(A.data_ptr()), lda,
                                  _dtype_code(C, True), ctypes.c_void_p(C.data_ptr()),
-                                 max(C.stride(0), n, 1), ctypes.byref(o))
+                                 max(C.stride(0), n, 1), ob)
     else:
         st = lib().ffa_syrk_modp_ex(ctx, int(bool(trans)), n, k, p, alpha, _dtype_code(A),
                                     ctypes.c_void_p(A.data_ptr()), lda, beta, _dtype_code(C, True),
                                     ctypes.c_void_p(C.data_ptr()), max(C.stride(0), n, 1),
-                                    ctypes.byref(o))
+                                    ob)
     _check(st, f"(device error {lib().ffa_last_device_error(ctx)})" if st == EDEVICE else "")
     return C
 
@@ -242,12 +244,14 @@ def herk_modp2(A_re, A_im, p, C_re=None, C_im=None, out_dtype=None, opts=None, *
     C_im = _out(C_im, n, A_re.device, od)
     if C_im.stride() != C_re.stride() or C_im.dtype != C_re.dtype:
         raise ValueError("C_re and C_im must have the same strides and dtype")
-    o = opts if opts is not None else make_opts(**kw)
+    # no options at all: NULL, so that the library applies an autotuned record for the shape
+    o = opts if opts is not None else (make_opts(**kw) if kw else None)
+    ob = ctypes.byref(o) if o is not None else None
     st = lib().ffa_herk_modp2(ctx, n, k, p, _dtype_code(A_re), ctypes.c_void_p(A_re.data_ptr()),
                               ctypes.c_void_p(A_im.data_ptr()), max(A_re.stride(0), k, 1),
                               _dtype_code(C_re, True), ctypes.c_void_p(C_re.data_ptr()),
                               ctypes.c_void_p(C_im.data_ptr()), max(C_re.stride(0), n, 1),
-                              ctypes.byref(o))
+                              ob)
     _check(st, f"(device error {lib().ffa_last_device_error(ctx)})" if st == EDEVICE else "")
     return C_re, C_im
 

@@ -212,3 +212,39 @@ def test_batch_herk(base, launch):
     with pytest.raises(ffa.FfaError):
         B.autotune(Ar, Cr)
     B.close()
+
+
+def test_tuned_record_applies_without_options():
+    """A call with no options runs the context's tuned record for its shape: a record
+    asking for one recursion level shows pre-additions in the phase profile, one
+    asking for none does not; an explicit option overrides the record."""
+    ffa = _ffa()
+    p, n, k = 65521, 520, 600
+    _say("tuned record without options")
+    Ares = si.uniform_residues(n, k, p, 307)
+    A = _u16(Ares)
+    exp = oracle.syrk_modp(Ares, p)
+    arch = json.loads(ffa.tune_export())["arch"]
+
+    def record(levels):
+        return json.dumps({"arch": arch, "records": [{
+            "n": n, "k": k, "p": p, "herm": 0, "dA": ffa.U16, "dC": ffa.U16,
+            "algo": ffa.ALGO_RECURSIVE if levels else ffa.ALGO_CLASSICAL, "levels": levels,
+            "cutoff": 0, "carrier": ffa.CARRIER_INT8, "kernel": 0}]})
+
+    def preadds(**kw):
+        torch.cuda.synchronize()
+        ffa.profile_reset(0)
+        ffa.profile_enable(0, True)
+        C = ffa.syrk_modp(A, p, **kw)
+        torch.cuda.synchronize()
+        _, calls = ffa.profile_read(0, ffa.PHASE_PRE)
+        ffa.profile_enable(0, False)
+        assert np.array_equal(np.tril(_host(C)), exp)
+        return calls
+
+    assert ffa.tune_import(record(1)) == 1
+    assert preadds() > 0
+    assert ffa.tune_import(record(0)) == 1
+    assert preadds() == 0
+    assert preadds(levels=1) > 0
