@@ -970,8 +970,6 @@ int launch_preadd(const PreaddTask* d_tasks, int ntasks, int h, int w, const Bas
         hipLaunchKernelGGL(preadd_f64, dim3((unsigned)((total + 255) / 256), ntasks), dim3(256), 0,
                            s, d_tasks, b, fp);
     } else if (!fp.cplx) {
-        const int64_t total = (int64_t)h * (w / 2 / 16);
-        dim3 g((unsigned)((total + 255) / 256), ntasks);
         if (fp.nl == 1) {
             const int64_t t8 = (int64_t)h * (w / 2 / 8);
             hipLaunchKernelGGL((preadd_i8<1, 0, 8>), dim3((unsigned)((t8 + 255) / 256), ntasks),

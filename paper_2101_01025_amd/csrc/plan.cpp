@@ -46,13 +46,13 @@ namespace {
 
 struct Builder {
     Plan& pl;
-    int esize;   // carrier element size in bytes
-    int npo;     // planes per carrier matrix: re, or re, im, -re
-    int npo_leaf;  // planes of carriers that feed base cases (re + im added for 2M)
-    int rdt;     // residue storage of products
-    int rsize;
-    int bt;      // product tile edge
-    int bt_r;    // tile edge of the real launch of the 2M base case
+    int esize = 1;     // carrier element size in bytes
+    int npo = 1;       // planes per carrier matrix: re, or re, im, -re
+    int npo_leaf = 1;  // planes of carriers that feed base cases (re + im added for 2M)
+    int rdt = 0;       // residue storage of products
+    int rsize = 1;
+    int bt = 0;        // product tile edge
+    int bt_r = 0;      // tile edge of the real launch of the 2M base case
     int64_t ws = 0;
 
     int64_t alloc(int64_t bytes)
