@@ -405,6 +405,53 @@ void schedule_products(Plan& pl)
     pl.total_tiles += build_schedule(pl.gemm, pl.cplx, pl.gemm_split, pl.gemm.size(), pl.sched2);
 }
 
+// Host check of every workspace reference of the product and addition tasks:
+// the bytes a kernel may touch (the planes it reads or writes, rows below the
+// task's row count, K columns) lie inside the workspace.  A failure is a
+// planner error, reported before anything is launched.
+bool extents_ok(const Plan& pl)
+{
+    const int64_t ws = pl.ws_bytes;
+    const int64_t es = pl.carrier == CAR_F64 ? 8 : 1;
+    auto car_ok = [&](const CarRef& r, int64_t rows, int64_t cols, int64_t subplanes) {
+        if (r.buf != BUF_WS || rows <= 0 || cols <= 0) return true;
+        const int64_t last = r.off + (subplanes - 1) * r.ps + ((rows - 1) * r.ld + cols) * es;
+        return r.off >= 0 && last <= ws;
+    };
+    auto res_ok = [&](const ResRef& r, int64_t rows, int64_t cols, bool both) {
+        const int64_t rs = dtype_size(r.dt);
+        auto one = [&](int32_t buf, int64_t off) {
+            return buf != BUF_WS || rows <= 0 || cols <= 0 || (off >= 0 && off + ((rows - 1) * r.ld + cols) * rs <= ws);
+        };
+        return one(r.buf, r.off) && (!both || one(r.buf2, r.off2));
+    };
+    const int64_t nl = pl.carrier == CAR_F64 ? 1 : pl.nl;
+    // complex products read planes re, im and -re; real products one plane
+    const int64_t sub_main = (pl.cplx ? 3 : 1) * nl;
+    for (const auto& g : pl.gemm) {
+        if (pl.gemm_src == SRC_RAW_U16) continue;  // reads the caller's rows
+        if (!car_ok(g.x, g.M, g.K, sub_main) || !car_ok(g.z, g.N, g.K, sub_main)) return false;
+        if (!res_ok(g.c, g.M, g.N, pl.cplx != 0)) return false;
+    }
+    for (const auto& g : pl.gemm_r)
+        if (!car_ok(g.x, g.M, g.K, nl) || !car_ok(g.z, g.N, g.K, nl) || !res_ok(g.c, g.M, g.N, false)) return false;
+    for (const auto& lv : pl.pre)
+        for (const auto& t : lv) {
+            if (!car_ok(t.a, 2 * (int64_t)t.h, 2 * (int64_t)t.w, (pl.cplx ? 2 : 1) * nl)) return false;
+            for (int j = 0; j < 4; ++j) {
+                const int64_t planes = !pl.cplx ? 1 : (j == 2 ? pl.fp.npo : 3);
+                if (!car_ok(t.s[j], t.h, t.w, planes * nl)) return false;
+            }
+        }
+    for (const auto& lv : pl.post)
+        for (const auto& t : lv) {
+            for (int j = 0; j < 5; ++j)
+                if (!res_ok(t.p[j], t.h, t.h, pl.cplx != 0)) return false;
+            if (!res_ok(t.c, 2 * (int64_t)t.h, 2 * (int64_t)t.h, pl.cplx != 0)) return false;
+        }
+    return true;
+}
+
 void size_grids(Plan& pl)
 {
     pl.pre_max_h.assign(pl.levels, 0);
@@ -423,6 +470,7 @@ void size_grids(Plan& pl)
     }
     for (const auto& t : pl.wpost) pl.wpost_max_h = std::max<int>(pl.wpost_max_h, t.h);
     schedule_products(pl);
+    if (pl.status == FFA_OK && !extents_ok(pl)) pl.status = FFA_EINVAL;
 }
 
 // Where the product of a whole problem goes: the caller's C, or, when the call

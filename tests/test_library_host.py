@@ -241,3 +241,26 @@ def test_plan_refuses_operands_beyond_32bit_offsets():
     st, d = ffa.plan_describe(50000, 50000, 65521, dA=ffa.U16, dC=ffa.U16,
                               opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
     assert st == 0 and d["src"] == "raw_u16"
+
+
+def test_plans_keep_every_task_inside_the_workspace():
+    """Every plan checks on the host that the bytes its product and addition tasks
+    touch lie inside its workspace (status EINVAL otherwise): a sweep of ragged
+    shapes, depths and options must plan cleanly."""
+    import itertools
+    cases = [
+        (251, ffa.I8_CENTRED, ffa.U8, False, {}),
+        (251, ffa.U8, ffa.U8, False, dict(general=ffa.GENERAL_WINOGRAD)),
+        (65521, ffa.U16, ffa.U16, False, {}),
+        (65521, ffa.U16, ffa.U16, False, dict(general=ffa.GENERAL_WINOGRAD)),
+        (65521, ffa.F64, ffa.F64, False, dict(carrier=ffa.CARRIER_F64)),
+        (131071, ffa.I64, ffa.I32, False, dict(carrier=ffa.CARRIER_F64)),
+        (65519, ffa.U16, ffa.U16, True, dict(herk_base=ffa.HERK_2M)),
+        (65519, ffa.U16, ffa.U16, True, dict(herk_base=ffa.HERK_4M)),
+        (251, ffa.I64, ffa.I64, True, {}),
+    ]
+    for (p, dA, dC, herm, kw), (n, k), levels in itertools.product(
+            cases, [(1, 1), (7, 300), (129, 130), (300, 520), (1000, 333), (2049, 700)], range(4)):
+        st, d = ffa.plan_describe(n, k, p, hermitian=herm, dA=dA, dC=dC,
+                                  opts=ffa.make_opts(levels=levels, **kw))
+        assert st == 0, (p, herm, kw, n, k, levels, st)
