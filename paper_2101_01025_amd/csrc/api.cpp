@@ -289,9 +289,15 @@ int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws)
                            (const TileEnt*)(blob + pl.off_sched_r), (int)pl.sched_r.size(), b, pl.fp, s);
         if (e) return dev_fail(c, e);
         phase_end(c, ms, pev, 2);
-        e = launch_herk2m((const Herk2mTask*)(blob + pl.off_h2m), (int)pl.h2m.size(), pl.h2m_max_n,
-                          pl.h2m[0].g.dt, pl.h2m[0].out.dt, b, pl.fp, s);
-        if (e) return dev_fail(c, e);
+        // one launch per output format (the planner groups the tasks by it)
+        for (size_t i0 = 0; i0 < pl.h2m.size();) {
+            size_t i1 = i0 + 1;
+            while (i1 < pl.h2m.size() && pl.h2m[i1].out.dt == pl.h2m[i0].out.dt) ++i1;
+            e = launch_herk2m((const Herk2mTask*)(blob + pl.off_h2m) + i0, (int)(i1 - i0), pl.h2m_max_n,
+                              pl.h2m[i0].g.dt, pl.h2m[i0].out.dt, b, pl.fp, s);
+            if (e) return dev_fail(c, e);
+            i0 = i1;
+        }
     }
     if (fork) {
         hipError_t he = hipStreamWaitEvent(ms, c->ev_join, 0);

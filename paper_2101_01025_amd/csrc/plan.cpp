@@ -443,6 +443,9 @@ bool extents_ok(const Plan& pl)
                 if (!car_ok(t.s[j], t.h, t.w, planes * nl)) return false;
             }
         }
+    for (const auto& t : pl.h2m)
+        if (!res_ok(t.g, t.n, t.n, false) || !res_ok(t.h, t.n, t.n, false) || !res_ok(t.out, t.n, t.n, true))
+            return false;
     for (const auto& lv : pl.post)
         for (const auto& t : lv) {
             for (int j = 0; j < 5; ++j)
@@ -469,6 +472,10 @@ void size_grids(Plan& pl)
         pl.wpre_max_w = std::max<int>(pl.wpre_max_w, t.w);
     }
     for (const auto& t : pl.wpost) pl.wpost_max_h = std::max<int>(pl.wpost_max_h, t.h);
+    // 2M combinations write leaves of recursions (workspace residues) and, in a
+    // batch, whole problems (the caller's format): one launch per output format
+    std::stable_sort(pl.h2m.begin(), pl.h2m.end(),
+                     [](const Herk2mTask& a, const Herk2mTask& b) { return a.out.dt < b.out.dt; });
     schedule_products(pl);
     if (pl.status == FFA_OK && !extents_ok(pl)) pl.status = FFA_EINVAL;
 }

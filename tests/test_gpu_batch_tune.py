@@ -173,21 +173,26 @@ def test_autotune_syrk_and_tuned_default(p, n, k, dt):
 
 @pytest.mark.parametrize("base", ["2m", "4m"])
 @pytest.mark.parametrize("launch", ["graph", "direct"])
-def test_batch_herk(base, launch):
-    """Batched Low(A_i A_i^H) over F_p[i], p = 65519: every problem compared whole with
-    the oracle; the graph mode is replayed on changed buffers (re-capture) and
-    checked again."""
+@pytest.mark.parametrize("p", [65519, 251])
+def test_batch_herk(base, launch, p):
+    """Batched Low(A_i A_i^H) over F_p[i] (two limbs at p = 65519, one at p = 251):
+    every problem compared whole with the oracle; the graph mode is replayed on
+    changed buffers (re-capture) and checked again."""
     ffa = _ffa()
-    p = 65519
-    _say("batch herk", base, launch)
+    _say("batch herk", p, base, launch)
     ns, ks = si.batch_shapes(18, 306, nmin=1, nmax=300)
-    B = ffa.BatchHerk(ns, ks, p, ffa.U16, ffa.U16,
+    dA = ffa.U16 if p > 255 else ffa.I64
+    B = ffa.BatchHerk(ns, ks, p, dA, ffa.U16,
                       herk_base=ffa.HERK_2M if base == "2m" else ffa.HERK_4M,
                       launch=ffa.LAUNCH_GRAPH if launch == "graph" else ffa.LAUNCH_DIRECT,
                       cutoff=128)
     mats = [si.complex_residues(int(n), int(k), p, 700 + i) for i, (n, k) in enumerate(zip(ns, ks))]
-    Ar = _u16(B.pack([m[0] for m in mats], np.int64))
-    Ai = _u16(B.pack([m[1] for m in mats], np.int64))
+    if p > 255:
+        Ar = _u16(B.pack([m[0] for m in mats], np.int64))
+        Ai = _u16(B.pack([m[1] for m in mats], np.int64))
+    else:
+        Ar = torch.from_numpy(B.pack([m[0] for m in mats], np.int64)).to("cuda")
+        Ai = torch.from_numpy(B.pack([m[1] for m in mats], np.int64)).to("cuda")
     exp = [oracle.herk_modp2(m[0], m[1], p) for m in mats]
 
     def check(Cr, Ci):
