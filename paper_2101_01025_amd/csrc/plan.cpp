@@ -205,7 +205,10 @@ struct Builder {
                 pl.h2m_max_n = std::max<int>(pl.h2m_max_n, (int)rows);
                 return;
             }
-            add_gemm(a, a, c, rows, rows, cols, true, aonly);
+            // a base case that writes the caller's C covers its valid rows only (the
+            // padding rows are zero and must not be stored)
+            const int64_t m = (c.buf == BUF_C || c.buf == BUF_C2) ? std::min(rows, nvalid) : rows;
+            add_gemm(a, a, c, m, m, cols, true, aonly);
             return;
         }
         const int64_t h = rows / 2, w = cols / 2;
@@ -507,7 +510,9 @@ int add_problem(Plan& pl, Builder& B, const Problem& pr, int levels, bool allow_
 {
     const int ktile = pl.ktile;
     // one more halving for Strassen-Winograd below the deepest general products
-    const int depth = levels + (pl.wino ? 1 : 0);
+    // (none without recursion: then the whole problem is one base case, whose rows
+    // must stay those of the caller's C)
+    const int depth = levels + (pl.wino && levels > 0 ? 1 : 0);
     const int64_t npad = round_up(pr.n, (int64_t)1 << depth);
     const int64_t kpad = round_up(pr.k, (int64_t)ktile << depth);
     if (npad >= (1ll << 31) || kpad >= (1ll << 31)) return FFA_EINVAL;
@@ -708,6 +713,11 @@ Plan make_batch_plan(const std::vector<Problem>& prs)
     if (p0.opts.herk_base < FFA_HERK_AUTO || p0.opts.herk_base > FFA_HERK_4M) { pl.status = FFA_EINVAL; return pl; }
     pl.herk2m = pl.cplx && pl.carrier == CAR_I8 && p0.opts.herk_base != FFA_HERK_4M;
     pl.fp.npo = pl.herk2m ? 4 : 3;
+    const ffa_opts& o0 = p0.opts;
+    if (o0.general < FFA_GENERAL_AUTO || o0.general > FFA_GENERAL_WINOGRAD || o0.wino_min < 0) {
+        pl.status = FFA_EINVAL;
+        return pl;
+    }
     int maxL = 0;
     std::vector<int> L(prs.size());
     for (size_t i = 0; i < prs.size(); ++i) {
@@ -721,6 +731,10 @@ Plan make_batch_plan(const std::vector<Problem>& prs)
     pl.levels = maxL;
     pl.pre.assign(maxL, {});
     pl.post.assign(maxL, {});
+    // Strassen-Winograd for the general products, as for single calls
+    pl.wino = (o0.general == FFA_GENERAL_WINOGRAD || (o0.general == FFA_GENERAL_AUTO && pl.carrier == CAR_F64)) &&
+              !pl.cplx && maxL > 0;
+    pl.wino_min = o0.wino_min > 0 ? o0.wino_min : (o0.general == FFA_GENERAL_AUTO ? 2048 : 0);
     int64_t maxn = 0;
     for (const auto& q : prs) maxn = std::max(maxn, q.n);
     pl.kernel_req = p0.opts.kernel;

@@ -253,3 +253,32 @@ def test_tuned_record_applies_without_options():
     assert ffa.tune_import(record(0)) == 1
     assert preadds() == 0
     assert preadds(levels=1) > 0
+
+
+@pytest.mark.parametrize("dc", ["u16", "i32"])
+@pytest.mark.parametrize("general", ["classical", "winograd"])
+def test_batch_p251_mixed_depths_and_formats(dc, general):
+    """A batch at p = 251 whose workspace residues are bytes while C is wider, with
+    problems deep enough to recurse next to ones that do not: every problem
+    compared whole with the oracle."""
+    ffa = _ffa()
+    p = 251
+    _say("batch p251", dc, general)
+    ns, ks = si.batch_shapes(14, 308, nmin=1, nmax=400)
+    mats = si.batch_residues(ns, ks, p, 308)
+    dC, tdt = (ffa.U16, torch.uint16) if dc == "u16" else (ffa.I32, torch.int32)
+    B = ffa.BatchSyrk(ns, ks, p, ffa.U8, dC, cutoff=128,
+                      general=ffa.GENERAL_WINOGRAD if general == "winograd" else ffa.GENERAL_CLASSICAL)
+    d = B.describe()
+    assert d["levels"] >= 1 and (d["wino_tasks"] > 0) == (general == "winograd")
+    A = torch.from_numpy(B.pack(mats, np.uint8)).to("cuda")
+    C = torch.full((B.c_total,), 0x1234, dtype=torch.int32, device="cuda").to(tdt)
+    B.run(A, C)
+    torch.cuda.synchronize()
+    Ch = _host(C)
+    for i, M in enumerate(mats):
+        n = int(ns[i])
+        got = Ch[B.c_off[i]:B.c_off[i] + n * n].reshape(n, n)
+        assert np.array_equal(np.tril(got), oracle.syrk_modp(M, p)), f"problem {i}"
+        assert (got[np.triu_indices(n, 1)] == 0x1234).all(), f"upper of problem {i}"
+    B.close()
