@@ -282,3 +282,29 @@ def test_batch_p251_mixed_depths_and_formats(dc, general):
         assert np.array_equal(np.tril(got), oracle.syrk_modp(M, p)), f"problem {i}"
         assert (got[np.triu_indices(n, 1)] == 0x1234).all(), f"upper of problem {i}"
     B.close()
+
+
+def test_batch_input_range_check():
+    """check_inputs on a batch: an entry outside [0, p) in one problem gives ERANGE and
+    leaves C untouched; a clean batch runs."""
+    ffa = _ffa()
+    p = 65521
+    _say("batch range check")
+    ns, ks = si.batch_shapes(6, 309, nmin=1, nmax=200)
+    mats = si.batch_residues(ns, ks, p, 309)
+    B = ffa.BatchSyrk(ns, ks, p, ffa.I32, ffa.U16, check_inputs=True)
+    packed = B.pack(mats, np.int32)
+    C = _sentinel(B.c_total)
+    B.run(torch.from_numpy(packed).to("cuda"), C)
+    torch.cuda.synchronize()
+    _check_batch(B, ns, mats, C)
+    bad = packed.copy()
+    i = 3
+    bad[B.a_off[i] + int(B.lda[i]) * (int(ns[i]) // 2)] = p  # row n/2, column 0 of problem 3
+    C2 = _sentinel(B.c_total)
+    with pytest.raises(ffa.FfaError) as e:
+        B.run(torch.from_numpy(bad).to("cuda"), C2)
+    assert e.value.status == ffa.ERANGE
+    torch.cuda.synchronize()
+    assert (_host(C2) == 0xBEEF).all()
+    B.close()
