@@ -423,3 +423,58 @@ def test_full_size_p251_sampled_and_freivalds(algo):
         x = rng.integers(0, p, n)
         yc, ya = oracle.freivalds_syrk(Ares, Cl, p, x)
         assert np.array_equal(yc, ya)
+
+
+# ------------------------------------------------------------------ strided A and C
+
+@pytest.mark.parametrize("case", ["p251-i8-0", "p251-i8-1", "p65521-u16-0", "p65521-u16-2",
+                                  "p65521-f64-2w", "p65519-herk-0", "p65519-herk-1",
+                                  "p65521-trans-1"])
+def test_strided_a_and_c(case):
+    """A and C as views into larger buffers (lda > k, ldc > n): the result lands in the
+    view's lower triangle and nothing else of the buffer changes."""
+    ffa = _ffa()
+    p = int(case.split("-")[0][1:])
+    kind, lv = case.split("-")[1], case.split("-")[2]
+    levels = int(lv[0])
+    n, k = 203, 331
+    pad_a, pad_c = 13, 21
+    _say("strided", case)
+    kw = dict(levels=levels)
+    if lv.endswith("w"):
+        kw.update(general=ffa.GENERAL_WINOGRAD, carrier=ffa.CARRIER_F64)
+    if kind == "herk":
+        Ar, Ai = si.complex_residues(n, k + pad_a, p, 1400)
+        er, ei = oracle.herk_modp2(Ar[:, :k].copy(), Ai[:, :k].copy(), p)
+        Br = torch.full((n, n + pad_c), 0xBEEF, dtype=torch.int32, device="cuda").to(torch.uint16)
+        Bi = torch.full((n, n + pad_c), 0xBEEF, dtype=torch.int32, device="cuda").to(torch.uint16)
+        ffa.herk_modp2(_dev(Ar, torch.uint16)[:, :k], _dev(Ai, torch.uint16)[:, :k], p,
+                       C_re=Br[:, :n], C_im=Bi[:, :n], **kw)
+        torch.cuda.synchronize()
+        low = np.tril(np.ones((n, n), dtype=bool))
+        for buf, exp in ((Br, er), (Bi, ei)):
+            g = _host(buf)
+            assert np.array_equal(g[:, :n][low], exp[low])
+            assert (g[:, :n][~low] == 0xBEEF).all() and (g[:, n:] == 0xBEEF).all()
+        return
+    trans = kind == "trans"
+    rows, cols = (k, n) if trans else (n, k)
+    big = si.uniform_residues(rows, cols + pad_a, p, 1401 + levels)
+    Ares = big[:, :cols].copy()
+    exp = oracle.syrk_modp(Ares.T.copy() if trans else Ares, p)
+    if kind == "i8":
+        A = _dev(si.to_centred(big, p).astype(np.int8), torch.int8)[:, :cols]
+        dt, sent = torch.uint8, 0xA5
+    elif kind == "f64":
+        A = _dev(big.astype(np.float64), torch.float64)[:, :cols]
+        dt, sent = torch.uint16, 0xBEEF
+    else:
+        A = _dev(big, torch.uint16)[:, :cols]
+        dt, sent = torch.uint16, 0xBEEF
+    Bc = torch.full((n, n + pad_c), sent, dtype=torch.int32, device="cuda").to(dt)
+    ffa.syrk_modp(A, p, C=Bc[:, :n], trans=trans, **kw)
+    torch.cuda.synchronize()
+    g = _host(Bc)
+    low = np.tril(np.ones((n, n), dtype=bool))
+    assert np.array_equal(g[:, :n][low], exp[low])
+    assert (g[:, :n][~low] == sent).all() and (g[:, n:] == sent).all()
