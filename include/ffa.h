@@ -232,8 +232,9 @@ int ffa_batch_autotune(ffa_batch* b, const void* A_packed, void* C_packed, int r
 /* The context's autotuner records as JSON text
  *   {"arch":"gfx950","records":[{"n":..,"k":..,"p":..,"herm":..,"dA":..,"dC":..,
  *    "algo":..,"levels":..,"cutoff":..,"carrier":..,"kernel":..,"operands":..,
- *    "general":..}, ...]}
- * ("operands" and "general" may be absent on import: the built-in choice then).
+ *    "general":..,"wino_min":..}, ...]}
+ * ("operands", "general" and "wino_min" may be absent on import: the built-in
+ * choice then).
  * ffa_tune_export writes it into buf (NUL-terminated; nothing written when size is
  * too small) and returns the length it needs without the NUL, or a negative status.
  * ffa_tune_import adds the records of such a text (records for another arch are
