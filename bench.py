@@ -349,8 +349,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not "
-                                   "part of this build (use --gpus 1)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (use --gpus 1); "
+                                   "the multi-GPU design is described, not built"}))
         sys.exit(2)
     import torch
 

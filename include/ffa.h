@@ -48,7 +48,7 @@ enum {
     FFA_ERANGE = -3,       /* an input entry is outside its residue range (check_inputs) */
     FFA_ENOMEM = -4,       /* device workspace could not be allocated */
     FFA_EDEVICE = -5,      /* a HIP call failed; ffa_last_device_error() has the code */
-    FFA_EUNSUPPORTED = -6, /* valid request this build does not support (e.g. herk with p = 1 mod 4) */
+    FFA_EUNSUPPORTED = -6, /* valid request this library does not support (e.g. herk with p = 1 mod 4) */
     FFA_EBOUND = -7        /* the exact-accumulation bound of the carrier is exceeded */
 };
 

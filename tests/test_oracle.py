@@ -71,7 +71,7 @@ def test_paper_lemmas_on_primes():
             assert oracle.legendre(-1, p) == -1
 
 
-def test_sos_golden_and_survey_constants():
+def test_sos_golden_constants():
     g = json.load(open(os.path.join(GOLDEN, "small_cases.json")))["sos_minus_one"]
     for p, v in g.items():
         assert oracle.sos(int(p), -1) == (v["a"], v["b"], v["s"])
