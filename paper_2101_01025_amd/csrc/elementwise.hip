@@ -854,30 +854,41 @@ __global__ void __launch_bounds__(256) herk2m_combine(const Herk2mTask* tasks, B
     const int tr = threadIdx.x >> 2, tc = (threadIdx.x & 3) * V;
     const char* gb = b.p[T.g.buf] + T.g.off;
     const char* hb = b.p[T.h.buf] + T.h.off;
+    const char* h2b = b.p[T.h2.buf] + T.h2.off;  // second half of H over K (split)
+    const bool split = T.split != 0;
     // H on the mirrored tile (C, R): row C*TS + tr, columns R*TS + tc ..; the
     // residue matrices have ld a multiple of 64, so whole 16-element groups are in
     // bounds of the allocation (entries past n are never used)
     {
         const int mi = C * TS + tr;
-        RowV<RT, V> hm;
-        if (mi < n) hm.load(hb, T.h.ld, mi, R * TS + tc);
-        else hm.zero();
+        RowV<RT, V> hm, hm2;
+        if (mi < n) {
+            hm.load(hb, T.h.ld, mi, R * TS + tc);
+            if (split) hm2.load(h2b, T.h2.ld, mi, R * TS + tc);
+            else hm2.zero();
+        } else {
+            hm.zero();
+            hm2.zero();
+        }
 #pragma unroll
-        for (int e = 0; e < V; ++e) ht[tr][tc + e] = hm[e];
+        for (int e = 0; e < V; ++e) ht[tr][tc + e] = split ? add_mod(hm[e], hm2[e], p) : hm[e];
     }
     __syncthreads();
     const int i = R * TS + tr, j0 = C * TS + tc;
     const int lim = min(n, T.nvalid);
     if (i >= lim || j0 > i) return;
-    RowV<RT, V> g, h;
+    RowV<RT, V> g, h, h2;
     g.load(gb, T.g.ld, i, j0);
     h.load(hb, T.h.ld, i, j0);
+    if (split) h2.load(h2b, T.h2.ld, i, j0);
+    else h2.zero();
     int32_t re[V], im[V];
 #pragma unroll
     for (int e = 0; e < V; ++e) {
         const int32_t hji = ht[tc + e][tr];  // H[j][i]
-        re[e] = sub_mod(sub_mod(g[e], h[e], p), hji, p);  // Re = G - H - H^T
-        im[e] = sub_mod(hji, h[e], p);                    // Im = H^T - H
+        const int32_t hij = split ? add_mod(h[e], h2[e], p) : h[e];
+        re[e] = sub_mod(sub_mod(g[e], hij, p), hji, p);  // Re = G - H - H^T
+        im[e] = sub_mod(hji, hij, p);                    // Im = H^T - H
     }
     const int want = min(V, min(lim, i + 1) - j0);  // columns j <= i inside the leaf
     char* ore = b.p[T.out.buf] + T.out.off;

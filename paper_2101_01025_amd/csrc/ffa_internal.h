@@ -167,9 +167,11 @@ struct CondTask {
 // residues G = (Xr + Xi)(Xr + Xi)^T (lower triangle) and H = Xr Xi^T (whole),
 // Low(X X^H) = Low(G - H - H^T) + i Low(H^T - H) into out (rows and columns
 // >= nvalid are not written).
+// H may come in two halves over K (h2 valid when split): H = h + h2 mod p.
 struct Herk2mTask {
-    ResRef g, h, out;
+    ResRef g, h, h2, out;
     int32_t n, nvalid;
+    int32_t split, pad_;
 };
 
 // One level of Strassen-Winograd for a general product C = X Z^T (X, Z: 2h x 2w

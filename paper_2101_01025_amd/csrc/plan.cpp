@@ -194,8 +194,21 @@ struct Builder {
                 sum.off += 3 * pl.nl * a.ps;
                 const ResRef G = new_res_real(rows), H = new_res_real(rows);
                 add_gemm_real(sum, sum, G, rows, rows, cols, true);
-                add_gemm_real(re, im, H, rows, rows, cols, false);
+                // A long H = Xr Xi^T goes in two halves over K: twice the tiles at half
+                // the length, which fill the last round of the launch (the SYRK's
+                // tiles and H's whole ones leave it nearly empty)
+                const int64_t kt_r = gemm_i8_config_ktile(pl.gemm_cfg_r);
+                const bool split = cols >= 2048 && (cols / 2) % kt_r == 0;
                 Herk2mTask t{};
+                if (split) {
+                    const ResRef H2 = new_res_real(rows);
+                    add_gemm_real(re, im, H, rows, rows, cols / 2, false);
+                    add_gemm_real(view(re, 0, cols / 2), view(im, 0, cols / 2), H2, rows, rows, cols / 2, false);
+                    t.h2 = H2;
+                    t.split = 1;
+                } else {
+                    add_gemm_real(re, im, H, rows, rows, cols, false);
+                }
                 t.g = G;
                 t.h = H;
                 t.out = c;
@@ -447,7 +460,8 @@ bool extents_ok(const Plan& pl)
             }
         }
     for (const auto& t : pl.h2m)
-        if (!res_ok(t.g, t.n, t.n, false) || !res_ok(t.h, t.n, t.n, false) || !res_ok(t.out, t.n, t.n, true))
+        if (!res_ok(t.g, t.n, t.n, false) || !res_ok(t.h, t.n, t.n, false) || !res_ok(t.out, t.n, t.n, true) ||
+            (t.split && !res_ok(t.h2, t.n, t.n, false)))
             return false;
     for (const auto& lv : pl.post)
         for (const auto& t : lv) {

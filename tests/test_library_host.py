@@ -129,6 +129,12 @@ def test_plan_herk_base_case_2m():
                               opts=ffa.make_opts(levels=1))
     assert st == 0 and d["real_tasks"] == 6 and d["gemm_tasks"] == 2
     assert ffa.plan_describe(n, k, 65519, hermitian=True, opts=ffa.make_opts(herk_base=3))[0] == ffa.EINVAL
+    # a long H = Xr Xi^T goes in two halves over K (three real products per leaf, same MACs)
+    st, d = ffa.plan_describe(4096, 8192, 65519, hermitian=True, dA=ffa.U16, dC=ffa.U16)
+    assert st == 0 and d["real_tasks"] == 3
+    assert d["macs"] == 4096 * 4097 // 2 * 8192 + 4096 * 4096 * 8192
+    st, d = ffa.plan_describe(200, 130, 65519, hermitian=True, dA=ffa.U16, dC=ffa.U16)
+    assert st == 0 and d["real_tasks"] == 2
     # the kernel option: a real two-limb configuration selects the 2M real products'
     st, d0 = ffa.plan_describe(n, k, 65519, hermitian=True, dA=ffa.U16, dC=ffa.U16)
     assert st == 0 and d0["cfg_real"] >= 0
