@@ -144,21 +144,36 @@ __global__ void __launch_bounds__(256) condition_i8(const CondTask* tasks, int n
                     *reinterpret_cast<const int4*>(out[q][l]);
 }
 
+// ST: storage of the fp64 carrier (double, or float for integers below 2^24)
+template <typename ST>
 __global__ void __launch_bounds__(256) condition_f64(const CondTask* tasks, int ntasks, Bases b,
                                                      FieldParams fp, int32_t* err)
 {
+    // four consecutive columns per thread (kpad is a multiple of the k-tile)
+    constexpr int V = 4;
     const CondTask& t = tasks[cond_task_of(tasks, ntasks, (int)blockIdx.x)];
+    const int gpr = t.kpad / V;
     const int64_t idx = (int64_t)((int)blockIdx.x - t.blk0) * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)t.npad * t.kpad) return;
-    const int r = (int)(idx / t.kpad), c = (int)(idx % t.kpad);
-    int32_t v = 0;
+    if (idx >= (int64_t)t.npad * gpr) return;
+    const int r = (int)(idx / gpr), c0 = (int)(idx % gpr) * V;
+    alignas(16) ST out[V];
     bool bad = false;
-    if (r < t.n && c < t.k)
-        bad = !read_input(b.p[t.buf_re] + t.off_re, t.dt_in, (int64_t)r * t.lda + c, fp.p,
-                          fp.half, v);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        const int c = c0 + e;
+        int32_t v = 0;
+        if (r < t.n && c < t.k)
+            bad |= !read_input(b.p[t.buf_re] + t.off_re, t.dt_in, (int64_t)r * t.lda + c, fp.p, fp.half, v);
+        out[e] = (ST)(v > fp.half ? v - fp.p : v);
+    }
     if (bad) err[0] = 1;
-    double* ob = reinterpret_cast<double*>(b.p[t.out.buf] + t.out.off);
-    ob[(int64_t)r * t.out.ld + c] = (double)(v > fp.half ? v - fp.p : v);
+    ST* ob = reinterpret_cast<ST*>(b.p[t.out.buf] + t.out.off) + (int64_t)r * t.out.ld + c0;
+    if (sizeof(ST) == 4) {
+        *reinterpret_cast<int4*>(ob) = *reinterpret_cast<const int4*>(out);
+    } else {
+        reinterpret_cast<int4*>(ob)[0] = reinterpret_cast<const int4*>(out)[0];
+        reinterpret_cast<int4*>(ob)[1] = reinterpret_cast<const int4*>(out)[1];
+    }
 }
 
 // ============================================================================
@@ -359,6 +374,7 @@ __global__ void __launch_bounds__(256) preadd_i8(const PreaddTask* tasks, Bases 
 }
 
 // fp64 carrier (real only): centred residues held as doubles.
+template <typename ST>
 __global__ void __launch_bounds__(256) preadd_f64(const PreaddTask* tasks, Bases b,
                                                   FieldParams fp)
 {
@@ -367,7 +383,7 @@ __global__ void __launch_bounds__(256) preadd_f64(const PreaddTask* tasks, Bases
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= h * hw) return;
     const int r = idx / hw, c = idx % hw;
-    const double* A = reinterpret_cast<const double*>(b.p[T.a.buf] + T.a.off);
+    const ST* A = reinterpret_cast<const ST*>(b.p[T.a.buf] + T.a.off);
     double x[4][2];
 #pragma unroll
     for (int blk = 0; blk < 4; ++blk)
@@ -398,8 +414,8 @@ __global__ void __launch_bounds__(256) preadd_f64(const PreaddTask* tasks, Bases
         const double sv[4] = {s1, s2, s3, s4};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            double* S = reinterpret_cast<double*>(b.p[T.s[j].buf] + T.s[j].off);
-            S[(int64_t)r * T.s[j].ld + c + half * hw] = sv[j];
+            ST* S = reinterpret_cast<ST*>(b.p[T.s[j].buf] + T.s[j].off);
+            S[(int64_t)r * T.s[j].ld + c + half * hw] = (ST)sv[j];
         }
     }
 }
@@ -659,9 +675,11 @@ __global__ void __launch_bounds__(256) wino_pre(const WinoPreTask* tasks, Bases 
 
 // fp64 carrier: centred residues held as doubles, 4 consecutive columns per thread
 // (w is a multiple of the 16-column k-tile, rows are 32-byte aligned).
+template <typename ST>
 __global__ void __launch_bounds__(256) wino_pre_f64(const WinoPreTask* tasks, Bases b, FieldParams fp)
 {
     constexpr int V = 4;
+    constexpr int NQ = V * (int)sizeof(ST) / 16;  // 16-byte moves per V elements
     const WinoPreTask& T = tasks[blockIdx.y];
     const int h = T.h, w = T.w, gpr = w / V;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -669,11 +687,11 @@ __global__ void __launch_bounds__(256) wino_pre_f64(const WinoPreTask* tasks, Ba
     const int r = (int)(idx / gpr), c = (int)(idx % gpr) * V;
     const int32_t p = fp.p;
     auto ld = [&](const CarRef& a, int blk, int32_t* v) {
-        const double* src = reinterpret_cast<const double*>(b.p[a.buf] + a.off) +
-                            (int64_t)((blk >> 1) * h + r) * a.ld + (blk & 1) * w + c;
-        alignas(16) double t[V];
-        reinterpret_cast<int4*>(t)[0] = reinterpret_cast<const int4*>(src)[0];
-        reinterpret_cast<int4*>(t)[1] = reinterpret_cast<const int4*>(src)[1];
+        const ST* src = reinterpret_cast<const ST*>(b.p[a.buf] + a.off) +
+                        (int64_t)((blk >> 1) * h + r) * a.ld + (blk & 1) * w + c;
+        alignas(16) ST t[V];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) reinterpret_cast<int4*>(t)[q] = reinterpret_cast<const int4*>(src)[q];
 #pragma unroll
         for (int e = 0; e < V; ++e) {
             const int32_t iv = (int32_t)t[e];
@@ -681,12 +699,12 @@ __global__ void __launch_bounds__(256) wino_pre_f64(const WinoPreTask* tasks, Ba
         }
     };
     auto st = [&](const CarRef& d, const int32_t* v) {
-        alignas(16) double t[V];
+        alignas(16) ST t[V];
 #pragma unroll
-        for (int e = 0; e < V; ++e) t[e] = (double)(v[e] > fp.half ? v[e] - p : v[e]);
-        double* dst = reinterpret_cast<double*>(b.p[d.buf] + d.off) + (int64_t)r * d.ld + c;
-        reinterpret_cast<int4*>(dst)[0] = reinterpret_cast<const int4*>(t)[0];
-        reinterpret_cast<int4*>(dst)[1] = reinterpret_cast<const int4*>(t)[1];
+        for (int e = 0; e < V; ++e) t[e] = (ST)(v[e] > fp.half ? v[e] - p : v[e]);
+        ST* dst = reinterpret_cast<ST*>(b.p[d.buf] + d.off) + (int64_t)r * d.ld + c;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) reinterpret_cast<int4*>(dst)[q] = reinterpret_cast<const int4*>(t)[q];
     };
     int32_t x[4][V], z[4][V];
 #pragma unroll
@@ -956,7 +974,8 @@ int launch_condition(const CondTask* d_tasks, int ntasks, int nblocks, int dt_in
     if (ntasks <= 0 || nblocks <= 0) return 0;
     const dim3 g(nblocks);
     if (carrier == CAR_F64) {
-        hipLaunchKernelGGL(condition_f64, g, dim3(256), 0, s, d_tasks, ntasks, b, fp, d_err);
+        if (fp.st32) hipLaunchKernelGGL(condition_f64<float>, g, dim3(256), 0, s, d_tasks, ntasks, b, fp, d_err);
+        else hipLaunchKernelGGL(condition_f64<double>, g, dim3(256), 0, s, d_tasks, ntasks, b, fp, d_err);
     } else {
         switch (dt_in) {
         case DT_I8C: launch_cond_typed<int8_t>(g, s, d_tasks, ntasks, b, fp, d_err); break;
@@ -978,8 +997,9 @@ int launch_preadd(const PreaddTask* d_tasks, int ntasks, int h, int w, const Bas
     if (ntasks <= 0 || h <= 0 || w <= 0) return 0;
     if (carrier == CAR_F64) {
         const int64_t total = (int64_t)h * (w / 2);
-        hipLaunchKernelGGL(preadd_f64, dim3((unsigned)((total + 255) / 256), ntasks), dim3(256), 0,
-                           s, d_tasks, b, fp);
+        const dim3 g((unsigned)((total + 255) / 256), ntasks);
+        if (fp.st32) hipLaunchKernelGGL(preadd_f64<float>, g, dim3(256), 0, s, d_tasks, b, fp);
+        else hipLaunchKernelGGL(preadd_f64<double>, g, dim3(256), 0, s, d_tasks, b, fp);
     } else if (!fp.cplx) {
         if (fp.nl == 1) {
             const int64_t t8 = (int64_t)h * (w / 2 / 8);
@@ -1071,8 +1091,9 @@ int launch_wino_pre(const WinoPreTask* d_tasks, int ntasks, int max_h, int max_w
     if (ntasks <= 0 || max_h <= 0 || max_w <= 0) return 0;
     if (carrier == CAR_F64) {
         const int64_t total = (int64_t)max_h * (max_w / 4);
-        hipLaunchKernelGGL(wino_pre_f64, dim3((unsigned)((total + 255) / 256), ntasks), dim3(256), 0, s,
-                           d_tasks, b, fp);
+        const dim3 g((unsigned)((total + 255) / 256), ntasks);
+        if (fp.st32) hipLaunchKernelGGL(wino_pre_f64<float>, g, dim3(256), 0, s, d_tasks, b, fp);
+        else hipLaunchKernelGGL(wino_pre_f64<double>, g, dim3(256), 0, s, d_tasks, b, fp);
     } else {
         const int64_t total = (int64_t)max_h * (max_w / 16);
         const dim3 g((unsigned)((total + 255) / 256), ntasks);

@@ -102,7 +102,7 @@ struct FieldParams {
     double inv_p;      // 1.0 / p
     int32_t alpha, beta;  // C <- alpha X + beta C (canonical) in the update pass
     int32_t npo;          // complex carriers: 4 = planes re, im, -re and re + im (2M base case)
-    int32_t pad_;
+    int32_t st32;         // fp64 carrier held in fp32 storage (exact integers below 2^24)
 };
 
 // ---- tasks ----------------------------------------------------------------

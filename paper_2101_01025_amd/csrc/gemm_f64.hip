@@ -10,6 +10,8 @@
 // fragment reads of 16 consecutive rows hit distinct banks.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.h"
 #include "ffa_internal.h"
 
@@ -25,7 +27,9 @@ constexpr int KTD = 16;  // doubles of K per pipeline stage
 // 330 registers over VGPRs and AGPRs at one wave per SIMD, and the second wave
 // hides the fragment-read and barrier latency of the first (products 8.48 -> 6.18 ms
 // at n = k = 8192, four levels).
-template <int BT, int WGM, int WGN>
+// ST: operand storage, double or float (exact integers below 2^24, widened to
+// double on the way into LDS; LDS and the MFMAs always hold doubles).
+template <int BT, int WGM, int WGN, typename ST>
 __global__ void __launch_bounds__(WGM* WGN * 64) __attribute__((amdgpu_waves_per_eu(2, 2)))
     gemm_f64(Bases bases, const GemmTask* __restrict__ tasks, const TileEnt* __restrict__ sched,
              FieldParams fp)
@@ -35,8 +39,9 @@ __global__ void __launch_bounds__(WGM* WGN * 64) __attribute__((amdgpu_waves_per
     constexpr int FM = WM / 16, FN = WN / 16;
     constexpr int TILE = BT * KTD;  // doubles
     constexpr int STAGE = 2 * TILE;
-    constexpr int CH = BT * (KTD / 2) / NT;  // 16-byte chunks per thread per operand
-    static_assert(BT * (KTD / 2) % NT == 0, "chunking");
+    constexpr int EPC = 16 / (int)sizeof(ST);  // elements per 16-byte chunk (2 or 4)
+    constexpr int CH = BT * (KTD / EPC) / NT;  // 16-byte chunks per thread per operand
+    static_assert(BT * (KTD / EPC) % NT == 0, "chunking");
 
     extern __shared__ __attribute__((aligned(16))) char lds_raw[];
     double* lds = reinterpret_cast<double*>(lds_raw);
@@ -48,41 +53,50 @@ __global__ void __launch_bounds__(WGM* WGN * 64) __attribute__((amdgpu_waves_per
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
 
-    const double* aptr[CH];
-    const double* bptr[CH];
-    int lpos[CH];
+    // each thread moves CH 16-byte chunks per operand and stage: EPC consecutive
+    // elements of row r, i.e. EPC / 2 pairs of doubles in LDS.  LDS element k of row
+    // r sits at k ^ (r & 15), so each pair lands on an aligned pair, swapped for odd r.
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    typedef typename std::conditional<sizeof(ST) == 8, v2d, v4f>::type chunk_t;
+    const ST* aptr[CH];
+    const ST* bptr[CH];
+    int lpos[CH][EPC / 2];
     bool swap[CH];
 #pragma unroll
     for (int i = 0; i < CH; ++i) {
         const int c = tid + i * NT;
-        const int r = c / (KTD / 2), s = c % (KTD / 2);
+        const int r = c / (KTD / EPC), s = c % (KTD / EPC);
         const int ga = min(row0 + r, T.M - 1), gb = min(col0 + r, T.N - 1);
-        aptr[i] = reinterpret_cast<const double*>(bases.p[T.x.buf] + T.x.off) + (int64_t)ga * T.x.ld + 2 * s;
-        bptr[i] = reinterpret_cast<const double*>(bases.p[T.z.buf] + T.z.off) + (int64_t)gb * T.z.ld + 2 * s;
-        lpos[i] = r * KTD + (((2 * s) ^ (r & 15)) & ~1);
+        aptr[i] = reinterpret_cast<const ST*>(bases.p[T.x.buf] + T.x.off) + (int64_t)ga * T.x.ld + EPC * s;
+        bptr[i] = reinterpret_cast<const ST*>(bases.p[T.z.buf] + T.z.off) + (int64_t)gb * T.z.ld + EPC * s;
+#pragma unroll
+        for (int q = 0; q < EPC / 2; ++q) lpos[i][q] = r * KTD + (((EPC * s + 2 * q) ^ (r & 15)) & ~1);
         swap[i] = (r & 1) != 0;
     }
     const int nst = T.K / KTD;
-    v2d ra[CH], rb[CH];
+    chunk_t ra[CH], rb[CH];
     auto gload = [&](int st) {
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
-            ra[i] = *reinterpret_cast<const v2d*>(aptr[i] + st * KTD);
-            rb[i] = *reinterpret_cast<const v2d*>(bptr[i] + st * KTD);
+            ra[i] = *reinterpret_cast<const chunk_t*>(aptr[i] + st * KTD);
+            rb[i] = *reinterpret_cast<const chunk_t*>(bptr[i] + st * KTD);
         }
     };
     auto sstore = [&](int buf) {
         double* base = lds + buf * STAGE;
 #pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            v2d a = ra[i], b = rb[i];
-            if (swap[i]) {
-                a = v2d{a.y, a.x};
-                b = v2d{b.y, b.x};
+        for (int i = 0; i < CH; ++i)
+#pragma unroll
+            for (int q = 0; q < EPC / 2; ++q) {
+                v2d a = v2d{(double)ra[i][2 * q], (double)ra[i][2 * q + 1]};
+                v2d b = v2d{(double)rb[i][2 * q], (double)rb[i][2 * q + 1]};
+                if (swap[i]) {
+                    a = v2d{a.y, a.x};
+                    b = v2d{b.y, b.x};
+                }
+                *reinterpret_cast<v2d*>(base + lpos[i][q]) = a;
+                *reinterpret_cast<v2d*>(base + TILE + lpos[i][q]) = b;
             }
-            *reinterpret_cast<v2d*>(base + lpos[i]) = a;
-            *reinterpret_cast<v2d*>(base + TILE + lpos[i]) = b;
-        }
     };
 
     v4d acc[FM][FN];
@@ -143,12 +157,12 @@ __global__ void __launch_bounds__(WGM* WGN * 64) __attribute__((amdgpu_waves_per
 
 constexpr int BT_F64 = 128;
 
-int launch_gemm_f64(const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks, const Bases& b,
-                    const FieldParams& fp, void* stream)
+template <typename ST>
+static int launch_f64_st(const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks, const Bases& b,
+                         const FieldParams& fp, void* stream)
 {
-    if (nblocks <= 0) return 0;
     constexpr int lds_bytes = 2 * 2 * BT_F64 * KTD * 8;
-    auto kern = gemm_f64<BT_F64, 2, 2>;
+    auto kern = gemm_f64<BT_F64, 2, 2, ST>;
     // the LDS limit is raised once per device the kernel runs on
     static uint64_t attr_devices = 0;
     int dev = 0;
@@ -163,6 +177,14 @@ int launch_gemm_f64(const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks
     hipLaunchKernelGGL(kern, dim3(nblocks), dim3(256), lds_bytes, (hipStream_t)stream, b,
                        d_tasks, d_sched, fp);
     return (int)hipGetLastError();
+}
+
+int launch_gemm_f64(const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks, const Bases& b,
+                    const FieldParams& fp, void* stream)
+{
+    if (nblocks <= 0) return 0;
+    return fp.st32 ? launch_f64_st<float>(d_tasks, d_sched, nblocks, b, fp, stream)
+                   : launch_f64_st<double>(d_tasks, d_sched, nblocks, b, fp, stream);
 }
 
 int gemm_tile_f64() { return BT_F64; }

@@ -428,7 +428,7 @@ void schedule_products(Plan& pl)
 bool extents_ok(const Plan& pl)
 {
     const int64_t ws = pl.ws_bytes;
-    const int64_t es = pl.carrier == CAR_F64 ? 8 : 1;
+    const int64_t es = pl.carrier == CAR_F64 ? (pl.fp.st32 ? 4 : 8) : 1;
     auto car_ok = [&](const CarRef& r, int64_t rows, int64_t cols, int64_t subplanes) {
         if (r.buf != BUF_WS || rows <= 0 || cols <= 0) return true;
         const int64_t last = r.off + (subplanes - 1) * r.ps + ((rows - 1) * r.ld + cols) * es;
@@ -549,7 +549,7 @@ int add_problem(Plan& pl, Builder& B, const Problem& pr, int levels, bool allow_
         return FFA_OK;
     }
     const bool in_matches = (pl.carrier == CAR_I8 && pl.nl == 1 && !pl.cplx && pr.dA == FFA_I8_CENTRED) ||
-                            (pl.carrier == CAR_F64 && pr.dA == FFA_F64);
+                            (pl.carrier == CAR_F64 && pr.dA == FFA_F64 && !pl.fp.st32);
     const bool direct = allow_direct && in_matches && !pr.trans && !pl.check_inputs && npad == pr.n &&
                         kpad == pr.k && pr.aligned && ((pr.lda * in_size) % 16 == 0) &&
                         ((pr.a_off * in_size) % 16 == 0);
@@ -581,8 +581,8 @@ int add_problem(Plan& pl, Builder& B, const Problem& pr, int levels, bool allow_
             if (tiles >= (1ll << 31)) return FFA_EINVAL;
             pl.cond_max_blocks = (int)std::max<int64_t>(pl.cond_max_blocks, tiles);
         } else {
-            // blocks of 256 threads x 16 (fp64: 1) carrier columns, one grid for all tasks
-            const int64_t vec = pl.carrier == CAR_F64 ? 1 : 16;
+            // blocks of 256 threads x 16 (fp64: 4) carrier columns, one grid for all tasks
+            const int64_t vec = pl.carrier == CAR_F64 ? 4 : 16;
             const int64_t blocks = (npad * (kpad / vec) + 255) / 256;
             if ((int64_t)pl.cond_max_blocks + blocks >= (1ll << 31)) return FFA_EINVAL;
             ct.blk0 = pl.cond_max_blocks;
@@ -635,7 +635,7 @@ bool raw_u16_ok(const Plan& pl, const Problem& pr, int levels)
 Builder make_builder(Plan& pl)
 {
     Builder B{pl};
-    B.esize = pl.carrier == CAR_F64 ? 8 : 1;
+    B.esize = pl.carrier == CAR_F64 ? (pl.fp.st32 ? 4 : 8) : 1;
     B.npo = pl.cplx ? 3 : 1;
     B.npo_leaf = pl.herk2m ? 4 : B.npo;
     B.rdt = pl.fp.p < 256 ? DT_U8 : (pl.fp.p < 65536 ? DT_U16 : DT_I32);
@@ -672,6 +672,10 @@ Plan make_plan(const Problem& pr)
     pl.herk2m = pl.cplx && pl.carrier == CAR_I8 && o.herk_base != FFA_HERK_4M;
     pl.fp.npo = pl.herk2m ? 4 : 3;
     pl.levels = choose_levels(pr.n, pr.k, o, pl.carrier, pl.nl, pl.cplx, pl.herk2m);
+    // fp64 carrier with recursion: blocks held as fp32 (exact below 2^24), which halves
+    // the traffic of the additions; without recursion the products read the caller's
+    // doubles directly
+    pl.fp.st32 = pl.carrier == CAR_F64 && pl.levels > 0 && !pr.trans && pr.p < (1u << 24) ? 1 : 0;
     pl.pre.assign(pl.levels, {});
     pl.post.assign(pl.levels, {});
     pl.kernel_req = o.kernel;
@@ -845,7 +849,7 @@ std::string describe(const Plan& pl)
              "\"gemm_tasks\":%zu,\"tiles\":%d,\"blocks\":%zu,\"cfg\":%d,\"tile\":%d,"
              "\"macs\":%lld,\"ykind\":%d,\"ya\":%d,\"yb\":%d,\"src\":\"%s\",\"streams\":%d,"
              "\"blocks_a_only\":%zu,\"herk_base\":\"%s\",\"real_tasks\":%zu,\"general\":\"%s\","
-             "\"wino_tasks\":%zu,\"wino_min\":%lld,\"cfg_real\":%d}",
+             "\"wino_tasks\":%zu,\"wino_min\":%lld,\"cfg_real\":%d,\"st32\":%d}",
              pl.status, pl.levels, pl.carrier == CAR_F64 ? "f64" : "int8", pl.nl, pl.cplx,
              (long long)pl.npad, (long long)pl.kpad, pl.direct ? 1 : 0, pl.max_abs,
              (long long)pl.max_k, (long long)pl.ws_bytes, pl.cond.size(), pre.c_str(), post.c_str(),
@@ -854,7 +858,7 @@ std::string describe(const Plan& pl)
              pl.fp.yb, pl.gemm_src == SRC_RAW_U16 ? "raw_u16" : "carrier", pl.fork ? 2 : 1,
              pl.sched.size(), pl.herk2m ? "2m" : (pl.cplx ? "4m" : "none"), pl.gemm_r.size(),
              pl.wpre.empty() ? "classical" : "winograd", pl.wpre.size(), (long long)pl.wino_min,
-             pl.herk2m ? pl.gemm_cfg_r : -1);
+             pl.herk2m ? pl.gemm_cfg_r : -1, pl.fp.st32);
     return buf;
 }
 

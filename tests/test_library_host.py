@@ -65,8 +65,14 @@ def test_plan_levels_padding_and_carriers():
     assert d["npad"] % 8 == 0 and d["kpad"] % (64 * 8) == 0 and d["kpad"] >= 333
     assert d["preadd_tasks"] == [1, 3, 9] and d["postadd_tasks"] == [1, 3, 9]
     assert d["gemm_tasks"] == 27 + 2 * (1 + 3 + 9)
+    # fp64 carrier: with recursion the blocks are conditioned into fp32 storage (exact
+    # below 2^24; half the additions' traffic), without it the products read the doubles
     st, d = ffa.plan_describe(8192, 8192, 65521, dA=ffa.F64, dC=ffa.F64)
-    assert st == 0 and d["carrier"] == "f64" and d["levels"] == 4 and d["direct"] == 1
+    assert st == 0 and d["carrier"] == "f64" and d["levels"] == 4 and d["direct"] == 0
+    assert d["conditioning"] == 1 and d["st32"] == 1
+    st, d = ffa.plan_describe(8192, 8192, 65521, dA=ffa.F64, dC=ffa.F64,
+                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
+    assert st == 0 and d["direct"] == 1 and d["st32"] == 0
     st, d = ffa.plan_describe(4096, 8192, 65519, hermitian=True, dA=ffa.U16, dC=ffa.U16)
     assert st == 0 and d["complex"] == 1 and d["ykind"] == 2
 
