@@ -27,7 +27,10 @@
 //
 // Data movement: global -> registers (a ring of PF k-tiles in flight) -> LDS
 // (double buffer, XOR-swizzled 16-byte segments so that the ds_read_b128 of
-// consecutive rows hits distinct banks) -> MFMA.  Which tile a workgroup
+// consecutive rows hits distinct banks) -> MFMA.  Configurations with PF = 0
+// load global -> LDS directly (buffer loads that write LDS, each thread reading
+// the segment that the swizzle puts in its slot): no ring registers, and the
+// next k-tile is in flight while the current one is multiplied.  Which tile a workgroup
 // computes comes from a host-built schedule indexed by blockIdx: tiles are
 // grouped into L2-friendly blocks and the blocks are dealt to the 8 XCDs
 // (workgroup b runs on XCD b mod 8) so that each XCD's L2 serves a compact set
@@ -43,12 +46,20 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 // LDS byte offset of 16-byte segment seg of row r in a tile with KT-byte rows.
+// The XOR is its own inverse: the segment stored at physical slot s of row r is
+// swz_seg(r, s).
 template <int KT>
-__device__ __forceinline__ int swz(int r, int seg)
+__device__ __forceinline__ int swz_seg(int r, int seg)
 {
     constexpr int NSEG = KT / 16;
     constexpr int RPB = 256 / KT;  // rows per 256-byte bank row
-    return r * KT + ((seg ^ ((r / RPB) & (NSEG - 1))) << 4);
+    return seg ^ ((r / RPB) & (NSEG - 1));
+}
+
+template <int KT>
+__device__ __forceinline__ int swz(int r, int seg)
+{
+    return r * KT + (swz_seg<KT>(r, seg) << 4);
 }
 
 // Canonical residue of an int32 x (|x| < 2^31) for p < 2^8, in full-rate 32-bit
@@ -92,6 +103,16 @@ __device__ __forceinline__ void split_u16x8(v4i v, int2& hi, int2& lo)
     lo.y = (int)__builtin_amdgcn_perm(x3, x2, 0x06040200u);
 }
 
+// 16 bytes per lane from a buffer straight into LDS: lane l's bytes land at
+// dst + 16 l, dst being wave-uniform.  The completion counts as a vector memory
+// load (vmcnt).  (A separate function: the address-space cast inside a kernel
+// template keeps the host pass from instantiating it.)
+__device__ __forceinline__ void lds_load16(__amdgpu_buffer_rsrc_t rs, char* dst, int voff, int soff)
+{
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)dst, 16, voff, soff, 0,
+                                             0);
+}
+
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 // acc + the sum of the 8 uint16 values of a chunk.
@@ -114,6 +135,10 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
 {
     constexpr bool RAW = SRC == SRC_RAW_U16;
     static_assert(!RAW || (NL == 2 && !CPLX), "raw uint16 operands feed two limbs of a real field");
+    // PF = 0: operands go from global memory straight into LDS (no register ring)
+    constexpr bool DMA = PF == 0;
+    constexpr int PFR = DMA ? 1 : PF;
+    static_assert(!(DMA && RAW), "raw operands are split into limbs in registers");
     constexpr int NT = WGM * WGN * 64;
     constexpr int NROLE = CPLX ? 2 : 1;
     constexpr int NSEG = CPLX ? 2 : 1;
@@ -170,7 +195,10 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
             acol[i] = s * 8;
         } else {
             const int sub = c / (BT * SPR), r = (c / SPR) % BT, s = c % SPR;
-            aoff[i] = (int)(sub * T.x.ps + (int64_t)min(r, rows_a - 1) * T.x.ld) + s * 16;
+            // direct loads put lane l's 16 bytes at LDS slot c: that thread reads the
+            // segment which the swizzle places there
+            const int gs = DMA ? swz_seg<KT>(r, s) : s;
+            aoff[i] = (int)(sub * T.x.ps + (int64_t)min(r, rows_a - 1) * T.x.ld) + gs * 16;
             alds[i] = sub * TILE + swz<KT>(r, s);
         }
     }
@@ -184,7 +212,8 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
             bcol[i] = s * 8;
         } else {
             const int sub = c / (BT * SPR), r = (c / SPR) % BT, s = c % SPR;
-            boff[i] = (int)(sub * T.z.ps + (int64_t)min(r, rows_b - 1) * T.z.ld) + s * 16;
+            const int gs = DMA ? swz_seg<KT>(r, s) : s;
+            boff[i] = (int)(sub * T.z.ps + (int64_t)min(r, rows_b - 1) * T.z.ld) + gs * 16;
             blds[i] = (NA + sub) * TILE + swz<KT>(r, s);
         }
     }
@@ -194,7 +223,7 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     const int nst = NSEG * nkc;
     const int seg_a = (int)(NL * T.x.ps), seg_b = (int)(NL * T.z.ps);
 
-    v4i ra[PF][ACH], rb[PF][BCH];
+    v4i ra[PFR][ACH], rb[PFR][BCH];
     const int kvalid = T.kvalid;
     auto gload = [&](int st, v4i* a, v4i* b) {
         if (RAW) {
@@ -222,6 +251,16 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
         const int seg = st >= nkc ? 1 : 0;
         const int kc = st - seg * nkc;
         const int oa = seg * seg_a + kc * KT, ob = seg * seg_b + kc * KT;
+        if (DMA) {
+            // chunk c = tid + i * NT lands at LDS byte 16 c of the stage: the wave's 64
+            // lanes fill 1 KiB from the wave-uniform base given here
+            char* base = lds + (st & 1) * STAGE + wave * 1024;
+#pragma unroll
+            for (int i = 0; i < ACH; ++i) lds_load16(rsa, base + i * NT * 16, aoff[i], oa);
+#pragma unroll
+            for (int i = 0; i < BCH; ++i) lds_load16(rsb, base + NA * TILE + i * NT * 16, boff[i], ob);
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < ACH; ++i) a[i] = __builtin_amdgcn_raw_buffer_load_b128(rsa, aoff[i], oa, 0);
 #pragma unroll
@@ -319,11 +358,13 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     // after compute(st): 1.86 vs 1.93 ms (one limb, 256-tiles, PF = 2) and 7.11 vs
     // 7.26 ms (two limbs, PF = 1) for the products at n = k = 16384.
     constexpr int SPOS = PF >= 2 ? 2 : 1;
-    constexpr int HK = SPOS == 1 ? NKS / 2 - 1 : -1;
+    constexpr int HK = SPOS == 1 && !DMA ? NKS / 2 - 1 : -1;
     // The compiler's MFMA / LDS-read interleaving strategy 0 for the two-limb products
-    // read from carrier planes (6.40 vs 6.82 ms of products at n = k = 16384).  One
-    // limb (its 128 accumulator registers) and raw operands would spill with it.
-    constexpr bool IGLP = NL == 2 && !RAW;
+    // read from carrier planes through registers (6.40 vs 6.82 ms of products at
+    // n = k = 16384).  One limb (its 128 accumulator registers) and raw operands
+    // would spill with it; with direct loads it made the one-limb kernel slower
+    // (1.82 vs 1.75 ms) and changed nothing with two limbs.
+    constexpr bool IGLP = NL == 2 && !RAW && !DMA;
     auto compute = [&](int buf, auto hook) {
         const char* base = lds + buf * STAGE;
         v4i af[2][NA][FM], bf[2][NB][FN];
@@ -340,22 +381,34 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     // ---- pipeline: PF k-tiles in flight in registers, two LDS buffers.  Stage
     // st + 1 goes to the buffer that compute(st - 1) read, which the barrier ending
     // iteration st - 1 released, so it may be written while compute(st) runs.
+    // Direct loads: stage st + 1 is loaded into that buffer while compute(st) runs;
+    // the barrier ending iteration st waits for the loads (vmcnt) before any wave
+    // reads the stage.
+    if (DMA) {
+        if (nst > 0) gload(0, ra[0], rb[0]);
+        __syncthreads();
+        for (int st = 0; st < nst; ++st) {
+            if (st + 1 < nst) gload(st + 1, ra[0], rb[0]);
+            compute(st & 1, [] {});
+            __syncthreads();
+        }
+    }
 #pragma unroll
-    for (int u = 0; u < PF; ++u)
+    for (int u = 0; u < (DMA ? 0 : PF); ++u)
         if (u < nst) gload(u, ra[u], rb[u]);
-    if (nst > 0) sstore(0, ra[0], rb[0]);
-    __syncthreads();
-    for (int st0 = 0; st0 < nst; st0 += PF) {
+    if (!DMA && nst > 0) sstore(0, ra[0], rb[0]);
+    if (!DMA) __syncthreads();
+    for (int st0 = 0; st0 < (DMA ? 0 : nst); st0 += PFR) {
 #pragma unroll
-        for (int u = 0; u < PF; ++u) {
+        for (int u = 0; u < PFR; ++u) {
             const int st = st0 + u;
             if (st < nst) {
                 auto next = [&] {
-                    if (st + 1 < nst) sstore((st + 1) & 1, ra[(u + 1) % PF], rb[(u + 1) % PF]);
+                    if (st + 1 < nst) sstore((st + 1) & 1, ra[(u + 1) % PFR], rb[(u + 1) % PFR]);
                 };
                 // register slot u held stage st (already in LDS): refill it with stage st + PF
                 if (SPOS == 2) next();
-                if (st + PF < nst) gload(st + PF, ra[u], rb[u]);
+                if (st + PFR < nst) gload(st + PFR, ra[u], rb[u]);
                 compute(st & 1, next);
                 __syncthreads();
             }
@@ -510,10 +563,11 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
 }
 
 // ---- configurations ---------------------------------------------------------
-// id -> (limbs, complex, tile edge, wave grid, k-tile bytes, prefetch depth).
+// id -> (limbs, complex, tile edge, wave grid, k-tile bytes, prefetch depth;
+// depth 0 = direct global-to-LDS loads).
 // Accumulator registers per lane: NROLE * NACC * (BT/WGM/32) * (BT/WGN/32) * 16.
 struct CfgInfo {
-    int nl, cplx, bt, kt, nthreads, lds;
+    int nl, cplx, bt, kt, nthreads, lds, raw;
 };
 
 // (Configurations whose accumulators do not fit the register file without
@@ -533,19 +587,25 @@ struct CfgInfo {
     X(16, 2, 0, 128, 2, 4, 128, 2)        \
     X(17, 2, 0, 64, 2, 2, 64, 2)          \
     X(18, 2, 0, 128, 2, 4, 64, 4)         \
-    X(21, 2, 0, 64, 2, 2, 64, 4)
+    X(21, 2, 0, 64, 2, 2, 64, 4)          \
+    X(24, 1, 0, 256, 2, 4, 128, 0)        \
+    X(25, 2, 0, 128, 2, 2, 128, 0)        \
+    X(26, 2, 0, 128, 2, 4, 128, 0)
 
 static CfgInfo cfg_info(int id)
 {
 #define FFA_INFO(ID, NL, CP, BT, WM, WN, KT, PF) \
-    if (id == ID) return CfgInfo{NL, CP, BT, KT, WM * WN * 64, 2 * ((CP ? 2 : 1) * NL + NL) * BT * KT};
+    if (id == ID)                                                                              \
+        return CfgInfo{NL, CP, BT, KT, WM * WN * 64, 2 * ((CP ? 2 : 1) * NL + NL) * BT * KT, \
+                       NL == 2 && !CP && PF > 0};
     FFA_I8_CONFIGS(FFA_INFO)
 #undef FFA_INFO
-    return CfgInfo{0, 0, 0, 0, 0, 0};
+    return CfgInfo{0, 0, 0, 0, 0, 0, 0};
 }
 
 int gemm_i8_config_tile(int cfg) { return cfg_info(cfg).bt; }
 int gemm_i8_config_ktile(int cfg) { return cfg_info(cfg).kt; }
+int gemm_i8_config_raw(int cfg) { return cfg_info(cfg).raw; }
 
 int gemm_i8_config_valid(int cfg, int nl, int cplx)
 {
@@ -559,7 +619,10 @@ int gemm_i8_default_config(int nl, int cplx, int64_t max_dim)
     // 8 waves, two k-tiles in flight: 6.85 ms against 7.11 ms for configuration 15 (one
     // k-tile in flight) for the products at n = k = 16384
     if (nl == 2) return 16;
-    return max_dim >= 2048 ? 10 : 2;
+    // 8 waves of 128x64, operands loaded straight into LDS: 1.75 ms against 1.85 ms for
+    // configuration 10 (the same tiles through a register ring) for the products at
+    // n = k = 16384, p = 251
+    return max_dim >= 2048 ? 24 : 2;
 }
 
 template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC>
@@ -585,14 +648,15 @@ static int launch_cfg(const GemmTask* d_tasks, const TileEnt* d_sched, int nbloc
     return (int)hipGetLastError();
 }
 
-// Raw uint16 operands exist only for the two-limb real configurations.
+// Raw uint16 operands exist only for the two-limb real configurations that load
+// through registers.
 template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF>
 static int launch_src(int src, const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks,
                       const Bases& b, const FieldParams& fp, hipStream_t s)
 {
     if (src == SRC_CARRIER)
         return launch_cfg<NL, CPLX, BT, WGM, WGN, KT, PF, SRC_CARRIER>(d_tasks, d_sched, nblocks, b, fp, s);
-    if constexpr (NL == 2 && CPLX == 0) {
+    if constexpr (NL == 2 && CPLX == 0 && PF > 0) {
         if (src == SRC_RAW_U16)
             return launch_cfg<NL, CPLX, BT, WGM, WGN, KT, PF, SRC_RAW_U16>(d_tasks, d_sched, nblocks, b, fp, s);
     }

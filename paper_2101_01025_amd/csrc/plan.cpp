@@ -624,10 +624,11 @@ void choose_kernel(Plan& pl, int64_t max_dim)
 
 // Whether a problem's products can read the caller's uint16 rows directly: two
 // limbs of a real field, no recursion (nothing else reads A), no input check,
-// and 16-byte aligned rows.
+// 16-byte aligned rows, and a product kernel that loads through registers.
 bool raw_u16_ok(const Plan& pl, const Problem& pr, int levels)
 {
-    return pl.carrier == CAR_I8 && pl.nl == 2 && !pl.cplx && pr.dA == FFA_U16 && levels == 0 && !pr.trans &&
+    return pl.carrier == CAR_I8 && pl.nl == 2 && !pl.cplx && gemm_i8_config_raw(pl.gemm_cfg) && pr.dA == FFA_U16 &&
+           levels == 0 && !pr.trans &&
            !pl.check_inputs && pr.k > 0 && pr.aligned && (pr.lda * 2) % 16 == 0 &&
            (pr.a_off * 2) % 16 == 0 && pr.lda * 2 < (1ll << 31) / 256;
 }
