@@ -97,6 +97,27 @@ def test_plan_operand_source():
         st, d = ffa.plan_describe(args["n"], args["k"], args["p"], hermitian=herm, dA=args["dA"],
                                   dC=args["dC"], opts=o)
         assert st == 0 and d["src"] == "carrier", (kw, d)
+    # raw operands are split into limbs between registers and LDS: a product kernel that
+    # loads straight into LDS (two-limb configurations 25 and 26) reads carrier planes
+    for cfg, src in ((16, "raw_u16"), (25, "carrier"), (26, "carrier")):
+        st, d = ffa.plan_describe(300, 200, 65521, dA=ffa.U16, dC=ffa.U16,
+                                  opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL, operands=ffa.OPERANDS_RAW,
+                                                     kernel=cfg + 1))
+        assert st == 0 and d["cfg"] == cfg and d["src"] == src, (cfg, d)
+
+
+def test_default_product_configurations():
+    # one limb: 128-tiles below 2048 rows per leaf, else 8 waves of 128x64 on 256-tiles with
+    # direct loads; two limbs: 128-tiles with a register ring
+    for n, cfg in ((1024, 2), (2048, 24), (16384, 24)):
+        st, d = ffa.plan_describe(n, n, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
+                                  opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
+        assert st == 0 and d["cfg"] == cfg and d["tile"] == (128 if cfg == 2 else 256), (n, d)
+    st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8)
+    # centred int8 input is read in place by the pre-additions and products
+    assert st == 0 and d["levels"] == 1 and d["cfg"] == 24 and d["direct"] == 1 and d["conditioning"] == 0
+    st, d = ffa.plan_describe(16384, 16384, 65521, dA=ffa.U16, dC=ffa.U16)
+    assert st == 0 and d["cfg"] == 16
 
 
 def test_plan_product_groups_and_streams():
