@@ -282,6 +282,20 @@ int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws)
         if (he != hipSuccess) return dev_fail(c, he);
     }
     if ((e = products(ms, pl.off_sched, pl.sched.size()))) return dev_fail(c, e);
+    if (!pl.tail.empty()) {
+        // the K-pieces of the launch's split last-round tiles, added into their places;
+        // one launch per output format (the planner groups the tasks by it)
+        hipEvent_t pev = phase_begin(c, ms);
+        for (size_t i0 = 0; i0 < pl.tail.size();) {
+            size_t i1 = i0 + 1;
+            while (i1 < pl.tail.size() && pl.tail[i1].out.dt == pl.tail[i0].out.dt) ++i1;
+            e = launch_tail_sum((const TailTask*)(blob + pl.off_tail) + i0, (int)(i1 - i0), pl.tile,
+                                pl.tail[i0].out.dt, b, pl.fp, s);
+            if (e) return dev_fail(c, e);
+            i0 = i1;
+        }
+        phase_end(c, ms, pev, 2);
+    }
     if (!pl.gemm_r.empty()) {
         // the real products of the 2M base case, then their combination into the leaves
         hipEvent_t pev = phase_begin(c, ms);

@@ -1146,6 +1146,44 @@ int launch_herk2m(const Herk2mTask* d_tasks, int ntasks, int max_n, int res_dt, 
     }
 }
 
+// Sum of the K-pieces of split product tiles: one workgroup per (row, task), its
+// threads across the row (consecutive columns, so every piece is read and the
+// output written in contiguous runs).  Pieces and output share the element
+// format T (canonical residues, exact in every format).
+template <typename T>
+__global__ void __launch_bounds__(256) tail_sum(const TailTask* tasks, Bases b, FieldParams fp)
+{
+    const TailTask& t = tasks[blockIdx.y];
+    const int r = blockIdx.x;
+    if (r >= t.rows) return;
+    const char* pb = b.p[t.part.buf] + t.part.off;
+    T* out = reinterpret_cast<T*>(b.p[t.out.buf] + t.out.off) + (int64_t)r * t.out.ld;
+    for (int c = threadIdx.x; c < t.cols; c += blockDim.x) {
+        int32_t v = 0;
+        for (int q = 0; q < t.nparts; ++q)
+            v = add_mod(v, (int32_t)reinterpret_cast<const T*>(pb + q * t.pstride)[(int64_t)r * t.part.ld + c], fp.p);
+        out[c] = (T)v;
+    }
+}
+
+// max_rows: the most rows of any task (the tile edge)
+int launch_tail_sum(const TailTask* d_tasks, int ntasks, int max_rows, int dt, const Bases& b,
+                    const FieldParams& fp, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if (ntasks <= 0 || max_rows <= 0) return 0;
+    const dim3 g((unsigned)max_rows, ntasks);
+    switch (dt) {
+    case DT_U8: hipLaunchKernelGGL((tail_sum<uint8_t>), g, dim3(256), 0, s, d_tasks, b, fp); break;
+    case DT_U16: hipLaunchKernelGGL((tail_sum<uint16_t>), g, dim3(256), 0, s, d_tasks, b, fp); break;
+    case DT_I32: hipLaunchKernelGGL((tail_sum<int32_t>), g, dim3(256), 0, s, d_tasks, b, fp); break;
+    case DT_I64: hipLaunchKernelGGL((tail_sum<int64_t>), g, dim3(256), 0, s, d_tasks, b, fp); break;
+    case DT_F64: hipLaunchKernelGGL((tail_sum<double>), g, dim3(256), 0, s, d_tasks, b, fp); break;
+    default: return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
+}
+
 template <typename RT>
 static int launch_update_rt(dim3 g, hipStream_t s, const UpdateTask* d, int c_dt, const Bases& b,
                             const FieldParams& fp)

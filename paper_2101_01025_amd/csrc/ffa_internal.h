@@ -150,6 +150,16 @@ struct TileEnt {
     int32_t x, y;
 };
 
+// One product tile computed as nparts K-pieces (the last partial round of a
+// launch, spread over more workgroups): out (rows x cols residues) = the sum of
+// the pieces mod p.  Piece q is a tile of residues at part + q * pstride bytes
+// (row stride part.ld elements) in the format of out.
+struct TailTask {
+    ResRef part, out;
+    int64_t pstride;
+    int32_t rows, cols, nparts, pad_;
+};
+
 // Conditioning: caller's A (n x k, format dt_in) into a carrier matrix of
 // npad x kpad (zero padded), planes re (and im, -re for F_p[i]).
 // trans: the caller's A is k x n and the carrier receives its transpose.
@@ -216,6 +226,8 @@ int launch_wino_post(const WinoPostTask* d_tasks, int ntasks, int max_h, const B
                      const FieldParams& fp, void* stream);
 int launch_herk2m(const Herk2mTask* d_tasks, int ntasks, int max_n, int res_dt, int out_dt,
                   const Bases& b, const FieldParams& fp, void* stream);
+int launch_tail_sum(const TailTask* d_tasks, int ntasks, int max_rows, int dt, const Bases& b,
+                    const FieldParams& fp, void* stream);
 int launch_update(const UpdateTask* d_tasks, int ntasks, int max_n, int x_dt, int c_dt, const Bases& b,
                   const FieldParams& fp, void* stream);
 int launch_preadd(const PreaddTask* d_tasks, int ntasks, int h, int w, const Bases& b,

@@ -398,6 +398,92 @@ int build_schedule(const std::vector<GemmTask>& tasks, bool cplx, size_t first, 
     return tiles;
 }
 
+// The last partial round of the launch: on each XCD (32 CUs, entries x, x + 8, ...
+// of the schedule) the tiles past its last full round of 32.  When they fill at
+// most a quarter of the XCD, each is replaced by four single-tile tasks over a
+// quarter of K each, writing residue tiles in the workspace, and a TailTask adds
+// them into the tile's place mod p before anything reads it.  The launch then
+// ends a quarter round after its last full round instead of a whole round.
+// Tiles on the diagonal of a base case (written in part) are not split.
+void split_tail(Plan& pl)
+{
+    constexpr int NX = 8, CPX = 32, NQ = 4;
+    if (pl.carrier != CAR_I8 || pl.cplx || pl.gemm_src != SRC_CARRIER || pl.sched.empty()) return;
+    const int bt = pl.tile;
+    const size_t len = pl.sched.size() / NX;
+    std::vector<std::vector<TileEnt>> bins(NX);
+    for (size_t i = 0; i < len; ++i)
+        for (int x = 0; x < NX; ++x)
+            if (pl.sched[i * NX + x].x >= 0) bins[x].push_back(pl.sched[i * NX + x]);
+    auto splittable = [&](const TileEnt& e) {
+        const GemmTask& g = pl.gemm[e.x];
+        const int ti = e.y & 0xffff, tj = e.y >> 16;
+        return !(g.syrk && ti == tj) && g.K % (NQ * pl.ktile) == 0 && g.kvalid == g.K;
+    };
+    int64_t ws = round_up(pl.ws_bytes, 256);
+    std::vector<TailTask> tail;
+    for (auto& v : bins) {
+        const int nt = (int)(v.size() % CPX);
+        if (nt == 0 || nt * NQ > CPX) continue;
+        std::vector<char> taken(v.size(), 0);
+        int got = 0;
+        for (size_t i = v.size(); i-- > 0 && got < nt;)
+            if (splittable(v[i])) taken[i] = 1, ++got;
+        if (got < nt) continue;
+        std::vector<TileEnt> keep, pieces;
+        for (size_t i = 0; i < v.size(); ++i) {
+            if (!taken[i]) {
+                keep.push_back(v[i]);
+                continue;
+            }
+            const GemmTask g0 = pl.gemm[v[i].x];
+            const int r0 = (v[i].y & 0xffff) * bt, c0 = (v[i].y >> 16) * bt;
+            const int64_t es = dtype_size(g0.c.dt);
+            TailTask tt{};
+            tt.part = g0.c;
+            tt.part.buf = tt.part.buf2 = BUF_WS;
+            tt.part.off = tt.part.off2 = ws;
+            tt.part.ld = bt;
+            tt.out = g0.c;
+            tt.out.off += ((int64_t)r0 * g0.c.ld + c0) * es;
+            tt.pstride = (int64_t)bt * bt * es;
+            tt.rows = std::min(bt, g0.M - r0);
+            tt.cols = std::min(bt, g0.N - c0);
+            tt.nparts = NQ;
+            const int kq = g0.K / NQ;
+            for (int q = 0; q < NQ; ++q) {
+                GemmTask g = g0;
+                g.x.off += (int64_t)r0 * g0.x.ld + (int64_t)q * kq;
+                g.z.off += (int64_t)c0 * g0.z.ld + (int64_t)q * kq;
+                g.M = tt.rows;
+                g.N = tt.cols;
+                g.K = g.kvalid = kq;
+                g.syrk = 0;
+                g.tiles_m = g.tiles_n = 1;
+                g.c = tt.part;
+                g.c.off = g.c.off2 = ws + q * tt.pstride;
+                pieces.push_back({(int32_t)pl.gemm.size(), 0});
+                pl.gemm.push_back(g);
+            }
+            ws += round_up(NQ * tt.pstride, 256);
+            tail.push_back(tt);
+        }
+        keep.insert(keep.end(), pieces.begin(), pieces.end());
+        v = std::move(keep);
+    }
+    if (tail.empty()) return;
+    size_t nlen = 0;
+    for (const auto& v : bins) nlen = std::max(nlen, v.size());
+    pl.sched.assign(nlen * NX, TileEnt{-1, 0});
+    for (int x = 0; x < NX; ++x)
+        for (size_t i = 0; i < bins[x].size(); ++i) pl.sched[i * NX + x] = bins[x][i];
+    pl.gemm_aonly.resize(pl.gemm.size(), 0);
+    pl.total_tiles += (NQ - 1) * (int)tail.size();
+    std::stable_sort(tail.begin(), tail.end(), [](const TailTask& a, const TailTask& b) { return a.out.dt < b.out.dt; });
+    pl.tail = std::move(tail);
+    pl.ws_bytes = ws;
+}
+
 // Orders the products as [reads only A | reads pre-addition outputs] and builds
 // one schedule per group when they run on two streams (the second group exists
 // only with recursion), else one schedule for all.
@@ -406,6 +492,7 @@ void schedule_products(Plan& pl)
     if (!pl.fork) {
         pl.gemm_split = (int)pl.gemm.size();
         pl.total_tiles = build_schedule(pl.gemm, pl.cplx, 0, pl.gemm.size(), pl.sched);
+        if (pl.split_tail) split_tail(pl);
         pl.total_tiles += build_schedule(pl.gemm_r, false, 0, pl.gemm_r.size(), pl.sched_r);
         pl.sched2.clear();
         return;
@@ -463,6 +550,12 @@ bool extents_ok(const Plan& pl)
         if (!res_ok(t.g, t.n, t.n, false) || !res_ok(t.h, t.n, t.n, false) || !res_ok(t.out, t.n, t.n, true) ||
             (t.split && !res_ok(t.h2, t.n, t.n, false)))
             return false;
+    for (const auto& t : pl.tail) {
+        if (!res_ok(t.out, t.rows, t.cols, false)) return false;
+        ResRef last = t.part;
+        last.off += (t.nparts - 1) * t.pstride;
+        if (!res_ok(t.part, t.rows, t.cols, false) || !res_ok(last, t.rows, t.cols, false)) return false;
+    }
     for (const auto& lv : pl.post)
         for (const auto& t : lv) {
             for (int j = 0; j < 5; ++j)
@@ -713,6 +806,7 @@ Plan make_plan(const Problem& pr)
     if (pl.status == FFA_OK) pl.status = check_bound(pl);
     pl.zero_fill = pr.k == 0;
     pl.fork = o.streams == FFA_STREAMS_TWO && pl.levels > 0 && !pl.herk2m && !pl.wino;
+    pl.split_tail = !pl.fork;
     size_grids(pl);
     return pl;
 }
@@ -829,13 +923,14 @@ std::vector<char> pack_tables(Plan& pl)
     pl.off_h2m = put(pl.h2m.data(), pl.h2m.size() * sizeof(Herk2mTask));
     pl.off_wpre = put(pl.wpre.data(), pl.wpre.size() * sizeof(WinoPreTask));
     pl.off_wpost = put(pl.wpost.data(), pl.wpost.size() * sizeof(WinoPostTask));
+    pl.off_tail = put(pl.tail.data(), pl.tail.size() * sizeof(TailTask));
     pl.blob_bytes = (int64_t)blob.size();
     return blob;
 }
 
 std::string describe(const Plan& pl)
 {
-    char buf[1024];
+    char buf[2048];
     std::string pre = "[", post = "[";
     for (int l = 0; l < pl.levels; ++l) {
         pre += std::to_string(pl.pre[l].size()) + (l + 1 < pl.levels ? "," : "");
@@ -850,7 +945,7 @@ std::string describe(const Plan& pl)
              "\"gemm_tasks\":%zu,\"tiles\":%d,\"blocks\":%zu,\"cfg\":%d,\"tile\":%d,"
              "\"macs\":%lld,\"ykind\":%d,\"ya\":%d,\"yb\":%d,\"src\":\"%s\",\"streams\":%d,"
              "\"blocks_a_only\":%zu,\"herk_base\":\"%s\",\"real_tasks\":%zu,\"general\":\"%s\","
-             "\"wino_tasks\":%zu,\"wino_min\":%lld,\"cfg_real\":%d,\"st32\":%d}",
+             "\"wino_tasks\":%zu,\"wino_min\":%lld,\"cfg_real\":%d,\"st32\":%d,\"tail_tiles\":%zu}",
              pl.status, pl.levels, pl.carrier == CAR_F64 ? "f64" : "int8", pl.nl, pl.cplx,
              (long long)pl.npad, (long long)pl.kpad, pl.direct ? 1 : 0, pl.max_abs,
              (long long)pl.max_k, (long long)pl.ws_bytes, pl.cond.size(), pre.c_str(), post.c_str(),
@@ -859,7 +954,7 @@ std::string describe(const Plan& pl)
              pl.fp.yb, pl.gemm_src == SRC_RAW_U16 ? "raw_u16" : "carrier", pl.fork ? 2 : 1,
              pl.sched.size(), pl.herk2m ? "2m" : (pl.cplx ? "4m" : "none"), pl.gemm_r.size(),
              pl.wpre.empty() ? "classical" : "winograd", pl.wpre.size(), (long long)pl.wino_min,
-             pl.herk2m ? pl.gemm_cfg_r : -1, pl.fp.st32);
+             pl.herk2m ? pl.gemm_cfg_r : -1, pl.fp.st32, pl.tail.size());
     return buf;
 }
 

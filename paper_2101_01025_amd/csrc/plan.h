@@ -74,6 +74,8 @@ struct Plan {
     int ktile = 0;                     // product k-tile (carrier elements); K is padded to it
     std::vector<TileEnt> sched;         // XCD-balanced tile schedule of group 1, one entry per workgroup
     std::vector<TileEnt> sched2;        // same for group 2
+    bool split_tail = false;            // may split the launch's last partial round over K
+    std::vector<TailTask> tail;         // tiles so split: sums of their pieces
     bool fork = false;                  // run pre-additions + group 2 on a second stream
     int64_t ws_bytes = 0;
     int64_t products_macs = 0;         // multiply-accumulates of the products (per limb product)
@@ -84,7 +86,7 @@ struct Plan {
     void* d_blob = nullptr;
     int64_t blob_bytes = 0;
     int64_t off_cond = 0, off_gemm = 0, off_sched = 0, off_sched2 = 0, off_upd = 0;
-    int64_t off_gemm_r = 0, off_sched_r = 0, off_h2m = 0, off_wpre = 0, off_wpost = 0;
+    int64_t off_gemm_r = 0, off_sched_r = 0, off_h2m = 0, off_wpre = 0, off_wpost = 0, off_tail = 0;
     std::vector<int64_t> off_pre, off_post;
 };
 

@@ -127,6 +127,30 @@ def test_winograd_threshold_mixed_plans(p, dt, wino_min):
     check_syrk(A, p, dt, out, **kw)
 
 
+# (n, k, p, input, output, options): shapes whose launch leaves a partial last round of
+# at most a quarter of each XCD, so that those tiles are computed as four K-pieces and
+# summed (one limb on 256-tiles, recursive and classical; two limbs on 128-tiles)
+TAIL_CASES = [
+    (2304, 2560, 251, "i8", "u8", dict(algo=1)),
+    (4352, 1024, 251, "i8", "u8", dict(levels=1)),
+    (2944, 1024, 65521, "u16", "u16", dict(algo=1)),
+    (2944, 1024, 65521, "u16", "i64", dict(algo=1)),
+]
+
+
+@pytest.mark.parametrize("n,k,p,di,do,kw", TAIL_CASES)
+def test_split_last_round_tiles(n, k, p, di, do, kw):
+    ffa = _ffa()
+    dA = ffa.I8_CENTRED if di == "i8" else ffa.U16
+    dC = {"u8": ffa.U8, "u16": ffa.U16, "i64": ffa.I64}[do]
+    st, d = ffa.plan_describe(n, k, p, dA=dA, dC=dC, opts=ffa.make_opts(**kw))
+    assert st == 0 and d["tail_tiles"] > 0, d
+    A = si.uniform_residues(n, k, p, 1500 + n + k)
+    tdA = torch.int8 if di == "i8" else torch.uint16
+    tdC = {"u8": torch.uint8, "u16": torch.uint16, "i64": torch.int64}[do]
+    check_syrk(A, p, tdA, tdC, **kw)
+
+
 @pytest.mark.parametrize("p", [3, 5, 13, 241])
 def test_int8_small_primes(p):
     # p = 3 and 251 use Y = [[a,b],[-b,a]] (x) I; p = 5, 13, 241 use Y = sqrt(-1) I

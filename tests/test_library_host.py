@@ -59,7 +59,8 @@ def test_plan_levels_padding_and_carriers():
     assert d["ykind"] == 1 and (d["ya"], d["yb"]) == (80, 80)
     st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
                               opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
-    assert d["levels"] == 0 and d["gemm_tasks"] == 1 and d["tiles"] == 64 * 65 // 2
+    # one task of 64 * 65 / 2 tiles; the 32 of its last partial round run as K-quarters
+    assert d["levels"] == 0 and d["gemm_tasks"] == 1 + 4 * 32 and d["tiles"] == 64 * 65 // 2 + 3 * 32
     st, d = ffa.plan_describe(1000, 333, 65521, dA=ffa.U16, dC=ffa.U16, opts=ffa.make_opts(levels=3))
     assert st == 0 and d["limbs"] == 2 and d["levels"] == 3 and d["direct"] == 0
     assert d["npad"] % 8 == 0 and d["kpad"] % (64 * 8) == 0 and d["kpad"] >= 333
@@ -297,3 +298,25 @@ def test_plans_keep_every_task_inside_the_workspace():
         st, d = ffa.plan_describe(n, k, p, hermitian=herm, dA=dA, dC=dC,
                                   opts=ffa.make_opts(levels=levels, **kw))
         assert st == 0, (p, herm, kw, n, k, levels, st)
+
+
+def test_last_round_split():
+    # one level at 16384^2, p = 251: 3632 tiles of 256 on 8 XCDs of 32 CUs leave 6 tiles
+    # past 14 full rounds on each XCD; they run as four K-quarters each
+    st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8)
+    assert st == 0 and d["tail_tiles"] == 48 and d["tiles"] == 3632 + 3 * 48, d
+    # the classical product: 2080 tiles, 4 past 8 full rounds per XCD
+    st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
+                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
+    assert st == 0 and d["tail_tiles"] == 32 and d["tiles"] == 2080 + 3 * 32, d
+    # not split: a last round fuller than a quarter, K not a multiple of four k-tiles,
+    # two streams, the fp64 carrier, F_p[i]
+    for args, kw in (((4096, 4096, 251), dict(algo=ffa.ALGO_CLASSICAL)),
+                     ((2304, 2560 - 128, 251), dict(algo=ffa.ALGO_CLASSICAL)),
+                     ((16384, 16384, 251), dict(streams=ffa.STREAMS_TWO))):
+        st, d = ffa.plan_describe(*args, dA=ffa.I8_CENTRED, dC=ffa.U8, opts=ffa.make_opts(**kw))
+        assert st == 0 and d["tail_tiles"] == 0, (args, kw, d)
+    st, d = ffa.plan_describe(8192, 8192, 65521, dA=ffa.F64, dC=ffa.U16)
+    assert st == 0 and d["tail_tiles"] == 0
+    st, d = ffa.plan_describe(4096, 8192, 65519, hermitian=True, dA=ffa.U16, dC=ffa.U16)
+    assert st == 0 and d["tail_tiles"] == 0
