@@ -1146,23 +1146,50 @@ int launch_herk2m(const Herk2mTask* d_tasks, int ntasks, int max_n, int res_dt, 
     }
 }
 
-// Sum of the K-pieces of split product tiles: one workgroup per (row, task), its
-// threads across the row (consecutive columns, so every piece is read and the
-// output written in contiguous runs).  Pieces and output share the element
-// format T (canonical residues, exact in every format).
+// Sum of the K-pieces of split product tiles: blockIdx.y picks the task, and the
+// workgroups of its row stride over the tile in 16-byte chunks of consecutive
+// columns (element by element where the output rows are not 16-byte aligned or
+// the width is not a multiple of a chunk).  Pieces and output share the element
+// format T (canonical residues, exact in every format); piece rows are 16-byte
+// aligned by construction.
 template <typename T>
 __global__ void __launch_bounds__(256) tail_sum(const TailTask* tasks, Bases b, FieldParams fp)
 {
+    constexpr int E = 16 / (int)sizeof(T);
     const TailTask& t = tasks[blockIdx.y];
-    const int r = blockIdx.x;
-    if (r >= t.rows) return;
     const char* pb = b.p[t.part.buf] + t.part.off;
-    T* out = reinterpret_cast<T*>(b.p[t.out.buf] + t.out.off) + (int64_t)r * t.out.ld;
-    for (int c = threadIdx.x; c < t.cols; c += blockDim.x) {
+    T* out = reinterpret_cast<T*>(b.p[t.out.buf] + t.out.off);
+    const int stride = gridDim.x * blockDim.x;
+    const int first = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool vec = ((((uintptr_t)out) | (uintptr_t)(t.out.ld * (int64_t)sizeof(T))) & 15) == 0 &&
+                     t.cols % E == 0 && (t.part.ld * (int)sizeof(T)) % 16 == 0 && ((t.part.off | t.pstride) & 15) == 0;
+    if (vec) {
+        const int cpr = t.cols / E;
+        for (int i = first; i < t.rows * cpr; i += stride) {
+            const int r = i / cpr, c0 = (i - r * cpr) * E;
+            int32_t v[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = 0;
+            for (int q = 0; q < t.nparts; ++q) {
+                alignas(16) T x[E];
+                *reinterpret_cast<int4*>(x) = *reinterpret_cast<const int4*>(
+                    pb + q * t.pstride + ((int64_t)r * t.part.ld + c0) * (int64_t)sizeof(T));
+#pragma unroll
+                for (int e = 0; e < E; ++e) v[e] = add_mod(v[e], (int32_t)x[e], fp.p);
+            }
+            alignas(16) T y[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) y[e] = (T)v[e];
+            *reinterpret_cast<int4*>(out + (int64_t)r * t.out.ld + c0) = *reinterpret_cast<const int4*>(y);
+        }
+        return;
+    }
+    for (int i = first; i < t.rows * t.cols; i += stride) {
+        const int r = i / t.cols, c = i - r * t.cols;
         int32_t v = 0;
         for (int q = 0; q < t.nparts; ++q)
             v = add_mod(v, (int32_t)reinterpret_cast<const T*>(pb + q * t.pstride)[(int64_t)r * t.part.ld + c], fp.p);
-        out[c] = (T)v;
+        out[(int64_t)r * t.out.ld + c] = (T)v;
     }
 }
 
@@ -1172,7 +1199,8 @@ int launch_tail_sum(const TailTask* d_tasks, int ntasks, int max_rows, int dt, c
 {
     hipStream_t s = (hipStream_t)stream;
     if (ntasks <= 0 || max_rows <= 0) return 0;
-    const dim3 g((unsigned)max_rows, ntasks);
+    // one 16-byte chunk per thread for 8-bit tiles; wider formats loop
+    const dim3 g((unsigned)(((int64_t)max_rows * max_rows / 16 + 255) / 256), ntasks);
     switch (dt) {
     case DT_U8: hipLaunchKernelGGL((tail_sum<uint8_t>), g, dim3(256), 0, s, d_tasks, b, fp); break;
     case DT_U16: hipLaunchKernelGGL((tail_sum<uint16_t>), g, dim3(256), 0, s, d_tasks, b, fp); break;
