@@ -400,14 +400,15 @@ int build_schedule(const std::vector<GemmTask>& tasks, bool cplx, size_t first, 
 
 // The last partial round of the launch: on each XCD (32 CUs, entries x, x + 8, ...
 // of the schedule) the tiles past its last full round of 32.  When they fill at
-// most a quarter of the XCD, each is replaced by four single-tile tasks over a
-// quarter of K each, writing residue tiles in the workspace, and a TailTask adds
-// them into the tile's place mod p before anything reads it.  The launch then
-// ends a quarter round after its last full round instead of a whole round.
-// Tiles on the diagonal of a base case (written in part) are not split.
+// most a quarter (a half) of the XCD, each is replaced by four (two) single-tile
+// tasks over a quarter (a half) of K each, writing residue tiles in the
+// workspace, and a TailTask adds them into the tile's place mod p before
+// anything reads it.  The launch then ends a quarter (half) round after its last
+// full round instead of a whole round.  Tiles on the diagonal of a base case
+// (written in part) are not split.
 void split_tail(Plan& pl)
 {
-    constexpr int NX = 8, CPX = 32, NQ = 4;
+    constexpr int NX = 8, CPX = 32;
     if (pl.carrier != CAR_I8 || pl.cplx || pl.gemm_src != SRC_CARRIER || pl.sched.empty()) return;
     const int bt = pl.tile;
     const size_t len = pl.sched.size() / NX;
@@ -415,6 +416,7 @@ void split_tail(Plan& pl)
     for (size_t i = 0; i < len; ++i)
         for (int x = 0; x < NX; ++x)
             if (pl.sched[i * NX + x].x >= 0) bins[x].push_back(pl.sched[i * NX + x]);
+    int NQ = 4;
     auto splittable = [&](const TileEnt& e) {
         const GemmTask& g = pl.gemm[e.x];
         const int ti = e.y & 0xffff, tj = e.y >> 16;
@@ -424,6 +426,7 @@ void split_tail(Plan& pl)
     std::vector<TailTask> tail;
     for (auto& v : bins) {
         const int nt = (int)(v.size() % CPX);
+        NQ = nt * 4 <= CPX ? 4 : 2;
         if (nt == 0 || nt * NQ > CPX) continue;
         std::vector<char> taken(v.size(), 0);
         int got = 0;
@@ -478,7 +481,7 @@ void split_tail(Plan& pl)
     for (int x = 0; x < NX; ++x)
         for (size_t i = 0; i < bins[x].size(); ++i) pl.sched[i * NX + x] = bins[x][i];
     pl.gemm_aonly.resize(pl.gemm.size(), 0);
-    pl.total_tiles += (NQ - 1) * (int)tail.size();
+    for (const auto& t : tail) pl.total_tiles += t.nparts - 1;
     std::stable_sort(tail.begin(), tail.end(), [](const TailTask& a, const TailTask& b) { return a.out.dt < b.out.dt; });
     pl.tail = std::move(tail);
     pl.ws_bytes = ws;

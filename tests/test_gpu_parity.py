@@ -128,13 +128,15 @@ def test_winograd_threshold_mixed_plans(p, dt, wino_min):
 
 
 # (n, k, p, input, output, options): shapes whose launch leaves a partial last round of
-# at most a quarter of each XCD, so that those tiles are computed as four K-pieces and
-# summed (one limb on 256-tiles, recursive and classical; two limbs on 128-tiles)
+# at most a quarter (a half) of each XCD, so that those tiles are computed as four (two)
+# K-pieces and summed (one limb on 256-tiles, recursive and classical; two limbs on
+# 128-tiles)
 TAIL_CASES = [
     (2304, 2560, 251, "i8", "u8", dict(algo=1)),
     (4352, 1024, 251, "i8", "u8", dict(levels=1)),
     (2944, 1024, 65521, "u16", "u16", dict(algo=1)),
     (2944, 1024, 65521, "u16", "i64", dict(algo=1)),
+    (3712, 1024, 65521, "u16", "u16", dict(algo=1)),  # halves only
 ]
 
 

@@ -65,7 +65,9 @@ def test_plan_levels_padding_and_carriers():
     assert st == 0 and d["limbs"] == 2 and d["levels"] == 3 and d["direct"] == 0
     assert d["npad"] % 8 == 0 and d["kpad"] % (64 * 8) == 0 and d["kpad"] >= 333
     assert d["preadd_tasks"] == [1, 3, 9] and d["postadd_tasks"] == [1, 3, 9]
-    assert d["gemm_tasks"] == 27 + 2 * (1 + 3 + 9)
+    # 27 leaves and two general products per node, plus two or four K-pieces per split tile
+    extra = d["gemm_tasks"] - (27 + 2 * (1 + 3 + 9))
+    assert 2 * d["tail_tiles"] <= extra <= 4 * d["tail_tiles"], d
     # fp64 carrier: with recursion the blocks are conditioned into fp32 storage (exact
     # below 2^24; half the additions' traffic), without it the products read the doubles
     st, d = ffa.plan_describe(8192, 8192, 65521, dA=ffa.F64, dC=ffa.F64)
@@ -176,7 +178,10 @@ def test_plan_winograd_general_products():
     n = k = 4096
     st, d = ffa.plan_describe(n, k, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
                               opts=ffa.make_opts(levels=1, general=ffa.GENERAL_WINOGRAD))
-    assert st == 0 and d["general"] == "winograd" and d["wino_tasks"] == 2 and d["gemm_tasks"] == 17
+    # (plus two or four K-pieces per tile of the launch's split last round)
+    extra = d["gemm_tasks"] - 17
+    assert st == 0 and d["general"] == "winograd" and d["wino_tasks"] == 2
+    assert 2 * d["tail_tiles"] <= extra <= 4 * d["tail_tiles"], d
     h, w = n // 2, k // 2
     assert d["macs"] == 3 * (h * (h + 1) // 2) * w + 2 * 7 * (h // 2) ** 2 * (w // 2)
     # rows and columns are padded one halving deeper
@@ -309,7 +314,13 @@ def test_last_round_split():
     st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
                               opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
     assert st == 0 and d["tail_tiles"] == 32 and d["tiles"] == 2080 + 3 * 32, d
-    # not split: a last round fuller than a quarter, K not a multiple of four k-tiles,
+    # two limbs, one level: 14432 tiles of 128 leave 12 per XCD, too many for quarters: halves
+    st, d = ffa.plan_describe(16384, 16384, 65521, dA=ffa.U16, dC=ffa.U16)
+    assert st == 0 and d["tail_tiles"] == 96 and d["tiles"] == 14432 + 96, d
+    st, d = ffa.plan_describe(3712, 1024, 65521, dA=ffa.U16, dC=ffa.U16,
+                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
+    assert st == 0 and d["tail_tiles"] == 15 and d["gemm_tasks"] == 1 + 2 * 15, d
+    # not split: a last round fuller than a half, K not a multiple of four (two) k-tiles,
     # two streams, the fp64 carrier, F_p[i]
     for args, kw in (((4096, 4096, 251), dict(algo=ffa.ALGO_CLASSICAL)),
                      ((2304, 2560 - 128, 251), dict(algo=ffa.ALGO_CLASSICAL)),
