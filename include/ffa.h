@@ -25,7 +25,11 @@
  *     residues in [-(p-1)/2, (p-1)/2], p < 256).  Outputs are canonical.
  *   - n = 0 is valid (nothing written); k = 0 writes zeros.
  *   - Every argument is validated before anything is launched; on an error
- *     nothing is written.  No exception or abort crosses this interface.
+ *     nothing is written.  No exception or abort crosses this interface: a
+ *     failing host allocation inside the library returns FFA_ENOMEM, any
+ *     other C++ exception FFA_EINVAL.
+ *   - n is at most FFA_N_MAX (C would not fit one GPU beyond it) and k below
+ *     2^31; larger sizes give FFA_EINVAL.
  *   - A context is not thread safe; use one context per host thread.
  */
 #ifndef FFA_H
@@ -37,6 +41,8 @@
 extern "C" {
 #endif
 
+#define FFA_N_MAX 524288  /* largest n of a call, 2^19 */
+
 typedef struct ffa_ctx ffa_ctx;
 typedef struct ffa_batch ffa_batch;
 
@@ -46,7 +52,7 @@ enum {
     FFA_EINVAL = -1,       /* bad size, stride, pointer, dtype or option */
     FFA_EPRIME = -2,       /* p is not an odd prime, or too large for the carrier */
     FFA_ERANGE = -3,       /* an input entry is outside its residue range (check_inputs) */
-    FFA_ENOMEM = -4,       /* device workspace could not be allocated */
+    FFA_ENOMEM = -4,       /* device workspace or host memory could not be allocated */
     FFA_EDEVICE = -5,      /* a HIP call failed; ffa_last_device_error() has the code */
     FFA_EUNSUPPORTED = -6, /* valid request this library does not support (e.g. herk with p = 1 mod 4) */
     FFA_EBOUND = -7        /* the exact-accumulation bound of the carrier is exceeded */
@@ -181,6 +187,7 @@ int ffa_herk_modp2(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA,
  * direct launches while phase profiling is on, with check_inputs, and when the
  * context's stream is itself being captured (the kernels then join the caller's
  * graph).  One plan must not be executed from two threads at once. */
+#define FFA_BATCH_MAX 4194304  /* most problems in one batch plan (count above it: FFA_EINVAL) */
 int ffa_batch_syrk_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int64_t* k,
                         uint32_t p, int dA, int dC, const ffa_opts* opts, ffa_batch** out);
 int ffa_batch_offsets(const ffa_batch* b, int64_t* a_off, int64_t* lda, int64_t* c_off,

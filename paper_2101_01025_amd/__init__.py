@@ -13,7 +13,9 @@ import json
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libffa.so")
+# FFA_LIBRARY names another build of the same library (the host-sanitizer build of
+# the tests); by default the in-tree libffa.so
+LIB_PATH = os.environ.get("FFA_LIBRARY") or os.path.join(_HERE, "libffa.so")
 
 OK, EINVAL, EPRIME, ERANGE, ENOMEM, EDEVICE, EUNSUPPORTED, EBOUND = 0, -1, -2, -3, -4, -5, -6, -7
 I64, I32, U16, U8, F64, I8_CENTRED = 0, 1, 2, 3, 4, 5
@@ -195,9 +197,23 @@ def _out(C, n, device, dtype):
     torch = _torch()
     if C is None:
         C = torch.zeros((n, n), dtype=dtype, device=device)
+    if not C.is_cuda or C.device != device:
+        raise ValueError(f"C must be a tensor on {device}")
     if C.dim() != 2 or C.shape[0] != n or C.shape[1] != n or (n > 0 and C.stride(1) != 1):
         raise ValueError("C must be a row-major n x n tensor")
+    if n > 1 and C.stride(0) < n:
+        raise ValueError("C's rows overlap (row stride below n)")
     return C
+
+
+def _ld(T, width):
+    """Row stride in elements of a row-major 2-D tensor with `width` columns (a
+    single row or an empty tensor has no meaningful stride: width is used)."""
+    if T.shape[0] <= 1 or width == 0:
+        return max(width, 1)
+    if T.stride(0) < width:
+        raise ValueError("the tensor's rows overlap (row stride below its width)")
+    return T.stride(0)
 
 
 def default_out_dtype(p):
@@ -219,16 +235,15 @@ def syrk_modp(A, p, C=None, out_dtype=None, opts=None, alpha=1, beta=0, trans=Fa
     # no options at all: NULL, so that the library applies an autotuned record for the shape
     o = opts if opts is not None else (make_opts(**kw) if kw else None)
     ob = ctypes.byref(o) if o is not None else None
-    lda = max(A.stride(0), A.shape[1], 1)
+    lda = _ld(A, A.shape[1])
+    ldc = _ld(C, n)
     if alpha == 1 and beta == 0 and not trans:
         st = lib().ffa_syrk_modp(ctx, n, k, p, _dtype_code(A), ctypes.c_void_p(A.data_ptr()), lda,
-                                 _dtype_code(C, True), ctypes.c_void_p(C.data_ptr()),
-                                 max(C.stride(0), n, 1), ob)
+                                 _dtype_code(C, True), ctypes.c_void_p(C.data_ptr()), ldc, ob)
     else:
         st = lib().ffa_syrk_modp_ex(ctx, int(bool(trans)), n, k, p, alpha, _dtype_code(A),
                                     ctypes.c_void_p(A.data_ptr()), lda, beta, _dtype_code(C, True),
-                                    ctypes.c_void_p(C.data_ptr()), max(C.stride(0), n, 1),
-                                    ob)
+                                    ctypes.c_void_p(C.data_ptr()), ldc, ob)
     _check(st, f"(device error {lib().ffa_last_device_error(ctx)})" if st == EDEVICE else "")
     return C
 
@@ -248,10 +263,9 @@ def herk_modp2(A_re, A_im, p, C_re=None, C_im=None, out_dtype=None, opts=None, *
     o = opts if opts is not None else (make_opts(**kw) if kw else None)
     ob = ctypes.byref(o) if o is not None else None
     st = lib().ffa_herk_modp2(ctx, n, k, p, _dtype_code(A_re), ctypes.c_void_p(A_re.data_ptr()),
-                              ctypes.c_void_p(A_im.data_ptr()), max(A_re.stride(0), k, 1),
+                              ctypes.c_void_p(A_im.data_ptr()), _ld(A_re, k),
                               _dtype_code(C_re, True), ctypes.c_void_p(C_re.data_ptr()),
-                              ctypes.c_void_p(C_im.data_ptr()), max(C_re.stride(0), n, 1),
-                              ob)
+                              ctypes.c_void_p(C_im.data_ptr()), _ld(C_re, n), ob)
     _check(st, f"(device error {lib().ffa_last_device_error(ctx)})" if st == EDEVICE else "")
     return C_re, C_im
 
@@ -265,8 +279,8 @@ def autotune_syrk(A, p, C=None, out_dtype=None, reps=3):
     best = Opts()
     ms = ctypes.c_double()
     st = lib().ffa_autotune_syrk(ctx, n, k, p, _dtype_code(A), ctypes.c_void_p(A.data_ptr()),
-                                 max(A.stride(0), k, 1), _dtype_code(C, True),
-                                 ctypes.c_void_p(C.data_ptr()), max(C.stride(0), n, 1), reps,
+                                 _ld(A, k), _dtype_code(C, True),
+                                 ctypes.c_void_p(C.data_ptr()), _ld(C, n), reps,
                                  ctypes.byref(best), ctypes.byref(ms))
     _check(st, "autotune")
     return best, ms.value
@@ -302,6 +316,8 @@ class BatchSyrk:
         self.ns = np.ascontiguousarray(ns, dtype=np.int64)
         self.ks = np.ascontiguousarray(ks, dtype=np.int64)
         self.p = p
+        self.dA, self.dC = dA, dC
+        self.device_index = device_index
         self.ctx = context(device_index)
         self.opts = opts if opts is not None else make_opts(**kw)
         h = ctypes.c_void_p()
@@ -331,8 +347,24 @@ class BatchSyrk:
             view[:, :k] = M
         return out
 
+    def _packed(self, T, code, total, what, output):
+        """Checks one packed buffer against the plan: a contiguous tensor on the
+        plan's device, of the plan's format, holding at least `total` elements."""
+        if not self.handle:
+            raise ValueError("the batch plan is closed")
+        if not T.is_cuda or T.device.index != self.device_index:
+            raise ValueError(f"{what} must be a tensor on cuda:{self.device_index}")
+        if _dtype_code(T, output) != code:
+            raise ValueError(f"{what} has dtype {T.dtype}, the plan expects format {code}")
+        if not T.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+        if T.numel() < total:
+            raise ValueError(f"{what} holds {T.numel()} elements, the packed layout needs {total}")
+
     def run(self, A_packed, C_packed):
         torch = _torch()
+        self._packed(A_packed, self.dA, self.a_total, "A_packed", False)
+        self._packed(C_packed, self.dC, self.c_total, "C_packed", True)
         lib().ffa_set_stream(self.ctx, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
         _check(lib().ffa_batch_syrk_exec(self.handle, ctypes.c_void_p(A_packed.data_ptr()),
                                          ctypes.c_void_p(C_packed.data_ptr())), "batch exec")
@@ -340,6 +372,8 @@ class BatchSyrk:
     def autotune(self, A_packed, C_packed, reps=3):
         """Re-plans with each kernel configuration / cutoff, keeps the fastest."""
         torch = _torch()
+        self._packed(A_packed, self.dA, self.a_total, "A_packed", False)
+        self._packed(C_packed, self.dC, self.c_total, "C_packed", True)
         lib().ffa_set_stream(self.ctx, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
         best = Opts()
         ms = ctypes.c_double()
@@ -374,6 +408,10 @@ class BatchHerk(BatchSyrk):
 
     def run(self, A_re, A_im, C_re, C_im):
         torch = _torch()
+        self._packed(A_re, self.dA, self.a_total, "A_re", False)
+        self._packed(A_im, self.dA, self.a_total, "A_im", False)
+        self._packed(C_re, self.dC, self.c_total, "C_re", True)
+        self._packed(C_im, self.dC, self.c_total, "C_im", True)
         lib().ffa_set_stream(self.ctx, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
         _check(lib().ffa_batch_herk_exec(self.handle, ctypes.c_void_p(A_re.data_ptr()),
                                          ctypes.c_void_p(A_im.data_ptr()),

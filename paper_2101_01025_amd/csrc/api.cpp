@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -60,6 +61,22 @@ struct ffa_batch {
 };
 
 namespace {
+
+// Runs the body of an entry point.  A C++ exception thrown inside (a host
+// allocation that fails, a length error) becomes a status code here instead
+// of crossing the C interface: FFA_ENOMEM for an allocation failure,
+// FFA_EINVAL for anything else.
+template <typename F>
+auto guarded(F&& f) noexcept -> decltype(f())
+{
+    try {
+        return f();
+    } catch (const std::bad_alloc&) {
+        return FFA_ENOMEM;
+    } catch (...) {
+        return FFA_EINVAL;
+    }
+}
 
 ffa_opts default_opts()
 {
@@ -490,89 +507,101 @@ extern "C" {
 
 int ffa_create(ffa_ctx** out, int device, void* hip_stream)
 {
-    if (!out) return FFA_EINVAL;
-    *out = nullptr;
-    int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
-        (void)hipGetLastError();
-        return FFA_EINVAL;
-    }
-    ffa_ctx* c = new ffa_ctx;
-    c->device = device;
-    c->stream = (hipStream_t)hip_stream;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
-        c->arch = prop.gcnArchName;
-        const size_t colon = c->arch.find(':');
-        if (colon != std::string::npos) c->arch.resize(colon);
-    }
-    hipError_t e = hipSetDevice(device);
-    if (e == hipSuccess) e = hipMalloc((void**)&c->d_err, 256);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
-    if (e != hipSuccess) {
-        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-        if (c->aux) (void)hipStreamDestroy(c->aux);
-        if (c->d_err) (void)hipFree(c->d_err);
-        delete c;
-        return FFA_EDEVICE;
-    }
-    *out = c;
-    return FFA_OK;
+    return guarded([&]() -> int {
+        if (!out) return FFA_EINVAL;
+        *out = nullptr;
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+            (void)hipGetLastError();
+            return FFA_EINVAL;
+        }
+        std::unique_ptr<ffa_ctx> owner(new ffa_ctx);
+        ffa_ctx* c = owner.get();
+        c->device = device;
+        c->stream = (hipStream_t)hip_stream;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+            c->arch = prop.gcnArchName;
+            const size_t colon = c->arch.find(':');
+            if (colon != std::string::npos) c->arch.resize(colon);
+        }
+        hipError_t e = hipSetDevice(device);
+        if (e == hipSuccess) e = hipMalloc((void**)&c->d_err, 256);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+            if (c->aux) (void)hipStreamDestroy(c->aux);
+            if (c->d_err) (void)hipFree(c->d_err);
+            return FFA_EDEVICE;
+        }
+        *out = owner.release();
+        return FFA_OK;
+    });
 }
 
 int ffa_destroy(ffa_ctx* c)
 {
-    if (!c) return FFA_EINVAL;
-    (void)hipSetDevice(c->device);
-    (void)hipDeviceSynchronize();
-    resolve_events(c);
-    for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
-    for (auto& kv : c->cache) free_tables(*kv.second);
-    if (c->ws) (void)hipFree(c->ws);
-    if (c->d_err) (void)hipFree(c->d_err);
-    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
-    if (c->aux) (void)hipStreamDestroy(c->aux);
-    delete c;
-    return FFA_OK;
+    return guarded([&]() -> int {
+        if (!c) return FFA_EINVAL;
+        (void)hipSetDevice(c->device);
+        (void)hipDeviceSynchronize();
+        resolve_events(c);
+        for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+        for (auto& kv : c->cache) free_tables(*kv.second);
+        if (c->ws) (void)hipFree(c->ws);
+        if (c->d_err) (void)hipFree(c->d_err);
+        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+        if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+        if (c->aux) (void)hipStreamDestroy(c->aux);
+        delete c;
+        return FFA_OK;
+    });
 }
 
 int ffa_set_stream(ffa_ctx* c, void* hip_stream)
 {
-    if (!c) return FFA_EINVAL;
-    c->stream = (hipStream_t)hip_stream;
-    return FFA_OK;
+    return guarded([&]() -> int {
+        if (!c) return FFA_EINVAL;
+        c->stream = (hipStream_t)hip_stream;
+        return FFA_OK;
+    });
 }
 
 int ffa_last_device_error(const ffa_ctx* c) { return c ? c->last_err : 0; }
 
 int ffa_profile_enable(ffa_ctx* c, int on)
 {
-    if (!c) return FFA_EINVAL;
-    c->prof = on != 0;
-    return FFA_OK;
+    return guarded([&]() -> int {
+        if (!c) return FFA_EINVAL;
+        c->prof = on != 0;
+        return FFA_OK;
+    });
 }
 
 int ffa_profile_read(ffa_ctx* c, int phase, double* total_ms, int64_t* calls)
 {
-    if (!c || phase < 0 || phase > 3) return FFA_EINVAL;
-    resolve_events(c);
-    if (total_ms) *total_ms = c->total_ms[phase];
-    if (calls) *calls = c->calls[phase];
-    return FFA_OK;
+    return guarded([&]() -> int {
+        if (!c || phase < 0 || phase > 3) return FFA_EINVAL;
+        resolve_events(c);
+        if (total_ms) *total_ms = c->total_ms[phase];
+        if (calls) *calls = c->calls[phase];
+        return FFA_OK;
+    });
 }
 
 int ffa_profile_reset(ffa_ctx* c)
 {
-    if (!c) return FFA_EINVAL;
-    resolve_events(c);
-    for (int i = 0; i < 4; ++i) {
-        c->total_ms[i] = 0;
-        c->calls[i] = 0;
-    }
-    return FFA_OK;
+    return guarded([&]() -> int {
+        if (!c) return FFA_EINVAL;
+        resolve_events(c);
+        for (int i = 0; i < 4; ++i) {
+            c->total_ms[i] = 0;
+            c->calls[i] = 0;
+        }
+        return FFA_OK;
+    });
 }
 
 const char* ffa_status_string(int s)
@@ -592,85 +621,97 @@ const char* ffa_status_string(int s)
 
 int ffa_skew_unitary(uint32_t p, int hermitian, uint32_t* a, uint32_t* b, int* kind)
 {
-    if (!a || !b || !kind) return FFA_EINVAL;
-    if (!is_odd_prime(p)) return FFA_EPRIME;
-    if (hermitian && p % 4 != 3) return FFA_EUNSUPPORTED;
-    uint64_t x, y;
-    int k;
-    if (skew_unitary_params(p, hermitian != 0, &k, &x, &y)) return FFA_EPRIME;
-    *a = (uint32_t)x;
-    *b = (uint32_t)y;
-    *kind = k;
-    return FFA_OK;
+    return guarded([&]() -> int {
+        if (!a || !b || !kind) return FFA_EINVAL;
+        if (!is_odd_prime(p)) return FFA_EPRIME;
+        if (hermitian && p % 4 != 3) return FFA_EUNSUPPORTED;
+        uint64_t x, y;
+        int k;
+        if (skew_unitary_params(p, hermitian != 0, &k, &x, &y)) return FFA_EPRIME;
+        *a = (uint32_t)x;
+        *b = (uint32_t)y;
+        *kind = k;
+        return FFA_OK;
+    });
 }
 
 int ffa_syrk_modp(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA, const void* A,
                   int64_t lda, int dC, void* C, int64_t ldc, const ffa_opts* opts)
 {
-    Problem pr;
-    pr.n = n;
-    pr.k = k;
-    pr.lda = lda;
-    pr.ldc = ldc;
-    pr.p = p;
-    pr.dA = dA;
-    pr.dC = dC;
-    pr.opts = opts ? *opts : default_opts();
-    if (!opts && ctx) (void)tuned_opts(ctx, n, k, p, 0, dA, dC, &pr.opts);
-    pr.aligned = ((uintptr_t)A % 16) == 0;
-    return run_call(ctx, pr, A, nullptr, C, nullptr);
+    return guarded([&]() -> int {
+        Problem pr;
+        pr.n = n;
+        pr.k = k;
+        pr.lda = lda;
+        pr.ldc = ldc;
+        pr.p = p;
+        pr.dA = dA;
+        pr.dC = dC;
+        pr.opts = opts ? *opts : default_opts();
+        if (!opts && ctx) (void)tuned_opts(ctx, n, k, p, 0, dA, dC, &pr.opts);
+        pr.aligned = ((uintptr_t)A % 16) == 0;
+        return run_call(ctx, pr, A, nullptr, C, nullptr);
+    });
 }
 
 int ffa_syrk_modp_ex(ffa_ctx* ctx, int trans, int64_t n, int64_t k, uint32_t p, uint32_t alpha, int dA,
                      const void* A, int64_t lda, uint32_t beta, int dC, void* C, int64_t ldc,
                      const ffa_opts* opts)
 {
-    Problem pr;
-    pr.n = n;
-    pr.k = k;
-    pr.lda = lda;
-    pr.ldc = ldc;
-    pr.p = p;
-    pr.dA = dA;
-    pr.dC = dC;
-    pr.trans = trans;
-    pr.alpha = alpha;
-    pr.beta = beta;
-    pr.opts = opts ? *opts : default_opts();
-    if (!opts && ctx) (void)tuned_opts(ctx, n, k, p, 0, dA, dC, &pr.opts);
-    pr.aligned = ((uintptr_t)A % 16) == 0;
-    return run_call(ctx, pr, A, nullptr, C, nullptr);
+    return guarded([&]() -> int {
+        Problem pr;
+        pr.n = n;
+        pr.k = k;
+        pr.lda = lda;
+        pr.ldc = ldc;
+        pr.p = p;
+        pr.dA = dA;
+        pr.dC = dC;
+        pr.trans = trans;
+        pr.alpha = alpha;
+        pr.beta = beta;
+        pr.opts = opts ? *opts : default_opts();
+        if (!opts && ctx) (void)tuned_opts(ctx, n, k, p, 0, dA, dC, &pr.opts);
+        pr.aligned = ((uintptr_t)A % 16) == 0;
+        return run_call(ctx, pr, A, nullptr, C, nullptr);
+    });
 }
 
 int ffa_herk_modp2(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA, const void* A_re,
                    const void* A_im, int64_t lda, int dC, void* C_re, void* C_im, int64_t ldc,
                    const ffa_opts* opts)
 {
-    Problem pr;
-    pr.n = n;
-    pr.k = k;
-    pr.lda = lda;
-    pr.ldc = ldc;
-    pr.p = p;
-    pr.herm = 1;
-    pr.dA = dA;
-    pr.dC = dC;
-    pr.opts = opts ? *opts : default_opts();
-    if (!opts && ctx) (void)tuned_opts(ctx, n, k, p, 1, dA, dC, &pr.opts);
-    pr.aligned = false;  // the conditioning always builds the complex planes
-    return run_call(ctx, pr, A_re, A_im, C_re, C_im);
+    return guarded([&]() -> int {
+        Problem pr;
+        pr.n = n;
+        pr.k = k;
+        pr.lda = lda;
+        pr.ldc = ldc;
+        pr.p = p;
+        pr.herm = 1;
+        pr.dA = dA;
+        pr.dC = dC;
+        pr.opts = opts ? *opts : default_opts();
+        if (!opts && ctx) (void)tuned_opts(ctx, n, k, p, 1, dA, dC, &pr.opts);
+        pr.aligned = false;  // the conditioning always builds the complex planes
+        return run_call(ctx, pr, A_re, A_im, C_re, C_im);
+    });
 }
 
 int ffa_batch_syrk_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int64_t* k,
                         uint32_t p, int dA, int dC, const ffa_opts* opts, ffa_batch** out)
 {
-    return batch_plan(ctx, count, n, k, p, 0, dA, dC, opts, out);
+    return guarded([&]() -> int {
+        return batch_plan(ctx, count, n, k, p, 0, dA, dC, opts, out);
+    });
 }
 
 int ffa_batch_herk_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int64_t* k,
                         uint32_t p, int dA, int dC, const ffa_opts* opts, ffa_batch** out)
 {
-    return batch_plan(ctx, count, n, k, p, 1, dA, dC, opts, out);
+    return guarded([&]() -> int {
+        return batch_plan(ctx, count, n, k, p, 1, dA, dC, opts, out);
+    });
 }
 
 }  // extern "C"
@@ -680,7 +721,7 @@ namespace {
 int batch_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int64_t* k, uint32_t p, int herm,
                int dA, int dC, const ffa_opts* opts, ffa_batch** out)
 {
-    if (!ctx || !out || count <= 0 || !n || !k) return FFA_EINVAL;
+    if (!ctx || !out || count <= 0 || count > FFA_BATCH_MAX || !n || !k) return FFA_EINVAL;
     *out = nullptr;
     std::vector<Problem> prs(count);
     const ffa_opts o = opts ? *opts : default_opts();
@@ -694,25 +735,28 @@ int batch_plan(ffa_ctx* ctx, int64_t count, const int64_t* n, const int64_t* k, 
         prs[i].dC = dC;
         prs[i].opts = o;
     }
-    ffa_batch* b = new ffa_batch;
+    std::unique_ptr<ffa_batch> owner(new ffa_batch);
+    ffa_batch* b = owner.get();
     b->ctx = ctx;
-    b->prs = prs;
-    b->plan = make_batch_plan(prs);
-    if (b->plan.status) {
-        const int st = b->plan.status;
-        delete b;
-        return st;
-    }
+    b->prs = std::move(prs);
+    b->plan = make_batch_plan(b->prs);
+    if (b->plan.status) return b->plan.status;
     (void)hipSetDevice(ctx->device);
-    int st = batch_workspace(b);
-    if (!st) st = upload_tables(ctx, b->plan);
+    int st = FFA_OK;
+    try {
+        st = batch_workspace(b);
+        if (!st) st = upload_tables(ctx, b->plan);
+    } catch (...) {
+        free_tables(b->plan);
+        if (b->ws) (void)hipFree(b->ws);
+        throw;
+    }
     if (st) {
         free_tables(b->plan);
         if (b->ws) (void)hipFree(b->ws);
-        delete b;
         return st;
     }
-    *out = b;
+    *out = owner.release();
     return FFA_OK;
 }
 
@@ -723,62 +767,72 @@ extern "C" {
 int ffa_batch_offsets(const ffa_batch* b, int64_t* a_off, int64_t* lda, int64_t* c_off,
                       int64_t* a_total, int64_t* c_total)
 {
-    if (!b) return FFA_EINVAL;
-    const size_t cnt = b->plan.a_off.size();
-    if (a_off) std::memcpy(a_off, b->plan.a_off.data(), cnt * sizeof(int64_t));
-    if (lda) std::memcpy(lda, b->plan.a_ld.data(), cnt * sizeof(int64_t));
-    if (c_off) std::memcpy(c_off, b->plan.c_off.data(), cnt * sizeof(int64_t));
-    if (a_total) *a_total = b->plan.a_total;
-    if (c_total) *c_total = b->plan.c_total;
-    return FFA_OK;
+    return guarded([&]() -> int {
+        if (!b) return FFA_EINVAL;
+        const size_t cnt = b->plan.a_off.size();
+        if (a_off) std::memcpy(a_off, b->plan.a_off.data(), cnt * sizeof(int64_t));
+        if (lda) std::memcpy(lda, b->plan.a_ld.data(), cnt * sizeof(int64_t));
+        if (c_off) std::memcpy(c_off, b->plan.c_off.data(), cnt * sizeof(int64_t));
+        if (a_total) *a_total = b->plan.a_total;
+        if (c_total) *c_total = b->plan.c_total;
+        return FFA_OK;
+    });
 }
 
 int ffa_batch_syrk_exec(ffa_batch* b, const void* A_packed, void* C_packed)
 {
-    if (!b || b->plan.cplx || !C_packed || (!A_packed && b->plan.a_total > 0)) return FFA_EINVAL;
-    if (((uintptr_t)A_packed % 16) || ((uintptr_t)C_packed % 16)) return FFA_EINVAL;
-    Bases bs{};
-    bs.p[BUF_A] = (char*)A_packed;
-    bs.p[BUF_C] = (char*)C_packed;
-    return batch_exec(b, bs);
+    return guarded([&]() -> int {
+        if (!b || b->plan.cplx || !C_packed || (!A_packed && b->plan.a_total > 0)) return FFA_EINVAL;
+        if (((uintptr_t)A_packed % 16) || ((uintptr_t)C_packed % 16)) return FFA_EINVAL;
+        Bases bs{};
+        bs.p[BUF_A] = (char*)A_packed;
+        bs.p[BUF_C] = (char*)C_packed;
+        return batch_exec(b, bs);
+    });
 }
 
 int ffa_batch_herk_exec(ffa_batch* b, const void* A_re, const void* A_im, void* C_re, void* C_im)
 {
-    if (!b || !b->plan.cplx || !C_re || !C_im) return FFA_EINVAL;
-    if (b->plan.a_total > 0 && (!A_re || !A_im)) return FFA_EINVAL;
-    if (((uintptr_t)A_re | (uintptr_t)A_im | (uintptr_t)C_re | (uintptr_t)C_im) % 16) return FFA_EINVAL;
-    Bases bs{};
-    bs.p[BUF_A] = (char*)A_re;
-    bs.p[BUF_A2] = (char*)A_im;
-    bs.p[BUF_C] = (char*)C_re;
-    bs.p[BUF_C2] = (char*)C_im;
-    return batch_exec(b, bs);
+    return guarded([&]() -> int {
+        if (!b || !b->plan.cplx || !C_re || !C_im) return FFA_EINVAL;
+        if (b->plan.a_total > 0 && (!A_re || !A_im)) return FFA_EINVAL;
+        if (((uintptr_t)A_re | (uintptr_t)A_im | (uintptr_t)C_re | (uintptr_t)C_im) % 16) return FFA_EINVAL;
+        Bases bs{};
+        bs.p[BUF_A] = (char*)A_re;
+        bs.p[BUF_A2] = (char*)A_im;
+        bs.p[BUF_C] = (char*)C_re;
+        bs.p[BUF_C2] = (char*)C_im;
+        return batch_exec(b, bs);
+    });
 }
 
 int ffa_batch_describe(const ffa_batch* b, char* buf, int64_t size)
 {
-    if (!b) return FFA_EINVAL;
-    if (buf && size > 0) {
-        const std::string d = describe(b->plan);
-        const size_t m = std::min<size_t>(d.size(), (size_t)size - 1);
-        std::memcpy(buf, d.data(), m);
-        buf[m] = 0;
-    }
-    return FFA_OK;
+    return guarded([&]() -> int {
+        if (!b) return FFA_EINVAL;
+        if (buf && size > 0) {
+            const std::string d = describe(b->plan);
+            const size_t m = std::min<size_t>(d.size(), (size_t)size - 1);
+            std::memcpy(buf, d.data(), m);
+            buf[m] = 0;
+        }
+        return FFA_OK;
+    });
 }
 
 int ffa_batch_destroy(ffa_batch* b)
 {
-    if (!b) return FFA_EINVAL;
-    (void)hipSetDevice(b->ctx->device);
-    (void)hipDeviceSynchronize();
-    drop_graph(b);
-    if (b->cap) (void)hipStreamDestroy(b->cap);
-    free_tables(b->plan);
-    if (b->ws) (void)hipFree(b->ws);
-    delete b;
-    return FFA_OK;
+    return guarded([&]() -> int {
+        if (!b) return FFA_EINVAL;
+        (void)hipSetDevice(b->ctx->device);
+        (void)hipDeviceSynchronize();
+        drop_graph(b);
+        if (b->cap) (void)hipStreamDestroy(b->cap);
+        free_tables(b->plan);
+        if (b->ws) (void)hipFree(b->ws);
+        delete b;
+        return FFA_OK;
+    });
 }
 
 }  // extern "C"
@@ -851,151 +905,155 @@ int ffa_autotune_syrk(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA, co
                       int64_t lda, int dC, void* C, int64_t ldc, int reps, ffa_opts* best,
                       double* best_ms)
 {
-    if (!ctx || reps <= 0) return FFA_EINVAL;
-    Problem base;
-    base.n = n;
-    base.k = k;
-    base.lda = lda;
-    base.ldc = ldc;
-    base.p = p;
-    base.dA = dA;
-    base.dC = dC;
-    base.opts = default_opts();
-    base.aligned = ((uintptr_t)A % 16) == 0;
-    Plan probe = make_plan(base);
-    if (probe.status) return probe.status;
-    double best_t = 1e30;
-    ffa_opts best_o = default_opts();
-    bool found = false;
-    for (int car : carrier_candidates(base)) {
-        Problem cb = base;
-        cb.opts.carrier = car;
-        const Plan cprobe = make_plan(cb);
-        if (cprobe.status) continue;
-        for (int L = 0; L <= 4; ++L) {
-            if (L > 0 && ((n >> L) < 64 || k == 0)) break;
-            for (int kc : kernel_candidates(cprobe))
-            for (int opr : {FFA_OPERANDS_PLANES, FFA_OPERANDS_RAW}) {
-            // general products: single tasks, or Winograd down to 0 / 2048 / 4096 rows
-            // (each distinct plan timed once)
-            std::vector<size_t> wino_seen;
-            for (int wi = 0; wi < 4; ++wi) {
-                const int gen = wi == 0 ? FFA_GENERAL_CLASSICAL : FFA_GENERAL_WINOGRAD;
-                const int wmin = wi <= 1 ? 0 : (wi == 2 ? 2048 : 4096);
-                ffa_opts o = default_opts();
-                o.algo = L == 0 ? FFA_ALGO_CLASSICAL : FFA_ALGO_RECURSIVE;
-                o.levels = L;
-                o.kernel = kc;
-                o.carrier = car;
-                o.operands = opr;
-                o.general = gen;
-                o.wino_min = wmin;
-                Problem pr = base;
-                pr.opts = o;
-                // raw operands and Winograd only where the planner takes them
-                const Plan tp = make_plan(pr);
-                if (opr == FFA_OPERANDS_RAW && tp.gemm_src != SRC_RAW_U16) continue;
-                if (gen == FFA_GENERAL_WINOGRAD) {
-                    if (tp.wpre.empty() || std::find(wino_seen.begin(), wino_seen.end(), tp.wpre.size()) !=
-                                               wino_seen.end())
-                        continue;
-                    wino_seen.push_back(tp.wpre.size());
+    return guarded([&]() -> int {
+        if (!ctx || reps <= 0) return FFA_EINVAL;
+        Problem base;
+        base.n = n;
+        base.k = k;
+        base.lda = lda;
+        base.ldc = ldc;
+        base.p = p;
+        base.dA = dA;
+        base.dC = dC;
+        base.opts = default_opts();
+        base.aligned = ((uintptr_t)A % 16) == 0;
+        Plan probe = make_plan(base);
+        if (probe.status) return probe.status;
+        double best_t = 1e30;
+        ffa_opts best_o = default_opts();
+        bool found = false;
+        for (int car : carrier_candidates(base)) {
+            Problem cb = base;
+            cb.opts.carrier = car;
+            const Plan cprobe = make_plan(cb);
+            if (cprobe.status) continue;
+            for (int L = 0; L <= 4; ++L) {
+                if (L > 0 && ((n >> L) < 64 || k == 0)) break;
+                for (int kc : kernel_candidates(cprobe))
+                for (int opr : {FFA_OPERANDS_PLANES, FFA_OPERANDS_RAW}) {
+                // general products: single tasks, or Winograd down to 0 / 2048 / 4096 rows
+                // (each distinct plan timed once)
+                std::vector<size_t> wino_seen;
+                for (int wi = 0; wi < 4; ++wi) {
+                    const int gen = wi == 0 ? FFA_GENERAL_CLASSICAL : FFA_GENERAL_WINOGRAD;
+                    const int wmin = wi <= 1 ? 0 : (wi == 2 ? 2048 : 4096);
+                    ffa_opts o = default_opts();
+                    o.algo = L == 0 ? FFA_ALGO_CLASSICAL : FFA_ALGO_RECURSIVE;
+                    o.levels = L;
+                    o.kernel = kc;
+                    o.carrier = car;
+                    o.operands = opr;
+                    o.general = gen;
+                    o.wino_min = wmin;
+                    Problem pr = base;
+                    pr.opts = o;
+                    // raw operands and Winograd only where the planner takes them
+                    const Plan tp = make_plan(pr);
+                    if (opr == FFA_OPERANDS_RAW && tp.gemm_src != SRC_RAW_U16) continue;
+                    if (gen == FFA_GENERAL_WINOGRAD) {
+                        if (tp.wpre.empty() || std::find(wino_seen.begin(), wino_seen.end(), tp.wpre.size()) !=
+                                                   wino_seen.end())
+                            continue;
+                        wino_seen.push_back(tp.wpre.size());
+                    }
+                    double ms = 0;
+                    const int st =
+                        time_calls(ctx, reps, [&] { return run_call(ctx, pr, A, nullptr, C, nullptr); }, &ms);
+                    if (st == FFA_EBOUND || st == FFA_EUNSUPPORTED || st == FFA_EINVAL) continue;
+                    if (st) return st;
+                    if (ms < best_t) {
+                        best_t = ms;
+                        best_o = o;
+                        found = true;
+                    }
                 }
-                double ms = 0;
-                const int st =
-                    time_calls(ctx, reps, [&] { return run_call(ctx, pr, A, nullptr, C, nullptr); }, &ms);
-                if (st == FFA_EBOUND || st == FFA_EUNSUPPORTED || st == FFA_EINVAL) continue;
-                if (st) return st;
-                if (ms < best_t) {
-                    best_t = ms;
-                    best_o = o;
-                    found = true;
                 }
-            }
             }
         }
-    }
-    if (!found) return FFA_EUNSUPPORTED;
-    record_tuned(ctx, n, k, p, 0, dA, dC, best_o);
-    if (best) *best = best_o;
-    if (best_ms) *best_ms = best_t;
-    return FFA_OK;
+        if (!found) return FFA_EUNSUPPORTED;
+        record_tuned(ctx, n, k, p, 0, dA, dC, best_o);
+        if (best) *best = best_o;
+        if (best_ms) *best_ms = best_t;
+        return FFA_OK;
+    });
 }
 
 int ffa_batch_autotune(ffa_batch* b, const void* A_packed, void* C_packed, int reps, ffa_opts* best,
                        double* best_ms)
 {
-    if (!b || reps <= 0) return FFA_EINVAL;
-    if (b->plan.cplx) return FFA_EUNSUPPORTED;
-    ffa_ctx* c = b->ctx;
-    const int64_t cutoffs[] = {0, 256, 384};
-    double best_t = 1e30;
-    ffa_opts best_o = b->prs[0].opts;
-    bool found = false;
-    for (int car : carrier_candidates(b->prs[0])) {
-        std::vector<Problem> cprs = b->prs;
-        for (auto& q : cprs) q.opts.carrier = car;
-        const Plan cprobe = make_batch_plan(cprs);
-        if (cprobe.status) continue;
-        for (int kc : kernel_candidates(cprobe)) {
-            for (int64_t cut : cutoffs)
-            for (int opr : {FFA_OPERANDS_PLANES, FFA_OPERANDS_RAW}) {
-                std::vector<Problem> prs = cprs;
-                for (auto& q : prs) {
-                    q.opts.kernel = kc;
-                    q.opts.cutoff = (int32_t)cut;
-                    q.opts.levels = -1;
-                    q.opts.algo = cut == 0 ? FFA_ALGO_CLASSICAL : FFA_ALGO_AUTO;
-                    q.opts.operands = opr;
+    return guarded([&]() -> int {
+        if (!b || reps <= 0) return FFA_EINVAL;
+        if (b->plan.cplx) return FFA_EUNSUPPORTED;
+        ffa_ctx* c = b->ctx;
+        const int64_t cutoffs[] = {0, 256, 384};
+        double best_t = 1e30;
+        ffa_opts best_o = b->prs[0].opts;
+        bool found = false;
+        for (int car : carrier_candidates(b->prs[0])) {
+            std::vector<Problem> cprs = b->prs;
+            for (auto& q : cprs) q.opts.carrier = car;
+            const Plan cprobe = make_batch_plan(cprs);
+            if (cprobe.status) continue;
+            for (int kc : kernel_candidates(cprobe)) {
+                for (int64_t cut : cutoffs)
+                for (int opr : {FFA_OPERANDS_PLANES, FFA_OPERANDS_RAW}) {
+                    std::vector<Problem> prs = cprs;
+                    for (auto& q : prs) {
+                        q.opts.kernel = kc;
+                        q.opts.cutoff = (int32_t)cut;
+                        q.opts.levels = -1;
+                        q.opts.algo = cut == 0 ? FFA_ALGO_CLASSICAL : FFA_ALGO_AUTO;
+                        q.opts.operands = opr;
+                    }
+                    ffa_batch trial;
+                    trial.ctx = c;
+                    trial.prs = prs;
+                    trial.plan = make_batch_plan(prs);
+                    if (trial.plan.status) continue;
+                    if (opr == FFA_OPERANDS_RAW && trial.plan.gemm_src != SRC_RAW_U16) {
+                        free_tables(trial.plan);
+                        continue;
+                    }
+                    if (trial.plan.a_total != b->plan.a_total || trial.plan.c_total != b->plan.c_total) continue;
+                    int st = batch_workspace(&trial);
+                    if (!st) st = upload_tables(c, trial.plan);
+                    double ms = 0;
+                    if (!st)
+                        st = time_calls(c, reps, [&] { return ffa_batch_syrk_exec(&trial, A_packed, C_packed); },
+                                        &ms);
+                    (void)hipDeviceSynchronize();
+                    drop_graph(&trial);
+                    if (trial.cap) (void)hipStreamDestroy(trial.cap);
+                    trial.cap = nullptr;
+                    const bool better = !st && ms < best_t;
+                    if (better) {
+                        // the trial's plan, tables and workspace move into the batch
+                        best_t = ms;
+                        best_o = prs[0].opts;
+                        found = true;
+                        drop_graph(b);
+                        free_tables(b->plan);
+                        if (b->ws) (void)hipFree(b->ws);
+                        b->prs = prs;
+                        b->plan = std::move(trial.plan);
+                        b->ws = trial.ws;
+                        b->ws_bytes = trial.ws_bytes;
+                        trial.plan.d_blob = nullptr;
+                        trial.ws = nullptr;
+                    } else {
+                        free_tables(trial.plan);
+                        if (trial.ws) (void)hipFree(trial.ws);
+                        trial.ws = nullptr;
+                    }
+                    if (st) return st;
                 }
-                ffa_batch trial;
-                trial.ctx = c;
-                trial.prs = prs;
-                trial.plan = make_batch_plan(prs);
-                if (trial.plan.status) continue;
-                if (opr == FFA_OPERANDS_RAW && trial.plan.gemm_src != SRC_RAW_U16) {
-                    free_tables(trial.plan);
-                    continue;
-                }
-                if (trial.plan.a_total != b->plan.a_total || trial.plan.c_total != b->plan.c_total) continue;
-                int st = batch_workspace(&trial);
-                if (!st) st = upload_tables(c, trial.plan);
-                double ms = 0;
-                if (!st)
-                    st = time_calls(c, reps, [&] { return ffa_batch_syrk_exec(&trial, A_packed, C_packed); },
-                                    &ms);
-                (void)hipDeviceSynchronize();
-                drop_graph(&trial);
-                if (trial.cap) (void)hipStreamDestroy(trial.cap);
-                trial.cap = nullptr;
-                const bool better = !st && ms < best_t;
-                if (better) {
-                    // the trial's plan, tables and workspace move into the batch
-                    best_t = ms;
-                    best_o = prs[0].opts;
-                    found = true;
-                    drop_graph(b);
-                    free_tables(b->plan);
-                    if (b->ws) (void)hipFree(b->ws);
-                    b->prs = prs;
-                    b->plan = std::move(trial.plan);
-                    b->ws = trial.ws;
-                    b->ws_bytes = trial.ws_bytes;
-                    trial.plan.d_blob = nullptr;
-                    trial.ws = nullptr;
-                } else {
-                    free_tables(trial.plan);
-                    if (trial.ws) (void)hipFree(trial.ws);
-                    trial.ws = nullptr;
-                }
-                if (st) return st;
             }
         }
-    }
-    if (!found) return FFA_EUNSUPPORTED;
-    if (best) *best = best_o;
-    if (best_ms) *best_ms = best_t;
-    return FFA_OK;
+        if (!found) return FFA_EUNSUPPORTED;
+        if (best) *best = best_o;
+        if (best_ms) *best_ms = best_t;
+        return FFA_OK;
+    });
 }
 
 namespace {
@@ -1021,93 +1079,99 @@ bool json_int(const char* p, const char* e, const char* key, long long* v)
 
 int64_t ffa_tune_export(const ffa_ctx* c, char* buf, int64_t size)
 {
-    if (!c) return FFA_EINVAL;
-    std::string s = "{\"arch\":\"" + c->arch + "\",\"records\":[";
-    bool first = true;
-    for (const auto& kv : c->tuned) {
-        if (kv.first.empty() || kv.first[0] == 'c') continue;  // size-class entries follow the exact ones
-        long long n, k;
-        unsigned p;
-        int herm, dA, dC;
-        if (sscanf(kv.first.c_str(), "%lld|%lld|%u|%d|%d|%d", &n, &k, &p, &herm, &dA, &dC) != 6) continue;
-        const ffa_opts& o = kv.second;
-        char rec[320];
-        snprintf(rec, sizeof(rec),
-                 "%s{\"n\":%lld,\"k\":%lld,\"p\":%u,\"herm\":%d,\"dA\":%d,\"dC\":%d,\"algo\":%d,"
-                 "\"levels\":%d,\"cutoff\":%d,\"carrier\":%d,\"kernel\":%d,\"operands\":%d,"
-                 "\"general\":%d,\"wino_min\":%d}",
-                 first ? "" : ",", n, k, p, herm, dA, dC, o.algo, o.levels, o.cutoff, o.carrier, o.kernel,
-                 o.operands, o.general, o.wino_min);
-        s += rec;
-        first = false;
-    }
-    s += "]}";
-    if (buf && size > (int64_t)s.size()) std::memcpy(buf, s.c_str(), s.size() + 1);
-    return (int64_t)s.size();
+    return guarded([&]() -> int64_t {
+        if (!c) return FFA_EINVAL;
+        std::string s = "{\"arch\":\"" + c->arch + "\",\"records\":[";
+        bool first = true;
+        for (const auto& kv : c->tuned) {
+            if (kv.first.empty() || kv.first[0] == 'c') continue;  // size-class entries follow the exact ones
+            long long n, k;
+            unsigned p;
+            int herm, dA, dC;
+            if (sscanf(kv.first.c_str(), "%lld|%lld|%u|%d|%d|%d", &n, &k, &p, &herm, &dA, &dC) != 6) continue;
+            const ffa_opts& o = kv.second;
+            char rec[320];
+            snprintf(rec, sizeof(rec),
+                     "%s{\"n\":%lld,\"k\":%lld,\"p\":%u,\"herm\":%d,\"dA\":%d,\"dC\":%d,\"algo\":%d,"
+                     "\"levels\":%d,\"cutoff\":%d,\"carrier\":%d,\"kernel\":%d,\"operands\":%d,"
+                     "\"general\":%d,\"wino_min\":%d}",
+                     first ? "" : ",", n, k, p, herm, dA, dC, o.algo, o.levels, o.cutoff, o.carrier, o.kernel,
+                     o.operands, o.general, o.wino_min);
+            s += rec;
+            first = false;
+        }
+        s += "]}";
+        if (buf && size > (int64_t)s.size()) std::memcpy(buf, s.c_str(), s.size() + 1);
+        return (int64_t)s.size();
+    });
 }
 
 int ffa_tune_import(ffa_ctx* c, const char* json)
 {
-    if (!c || !json) return FFA_EINVAL;
-    const char* arch = strstr(json, "\"arch\"");
-    const char* recs = strstr(json, "\"records\"");
-    if (!arch || !recs) return FFA_EINVAL;
-    const char* q1 = strchr(arch + 6, '"');
-    const char* q2 = q1 ? strchr(q1 + 1, '"') : nullptr;
-    if (!q2) return FFA_EINVAL;
-    if (std::string(q1 + 1, q2) != c->arch) return 0;
-    const char* p = strchr(recs, '[');
-    if (!p) return FFA_EINVAL;
-    int taken = 0;
-    while ((p = strchr(p, '{')) != nullptr) {
-        const char* e = strchr(p, '}');
-        if (!e) return FFA_EINVAL;
-        long long n, k, pp, herm, dA, dC, algo, levels, cutoff, carrier, kernel;
-        if (!json_int(p, e, "n", &n) || !json_int(p, e, "k", &k) || !json_int(p, e, "p", &pp) ||
-            !json_int(p, e, "herm", &herm) || !json_int(p, e, "dA", &dA) || !json_int(p, e, "dC", &dC) ||
-            !json_int(p, e, "algo", &algo) || !json_int(p, e, "levels", &levels) ||
-            !json_int(p, e, "cutoff", &cutoff) || !json_int(p, e, "carrier", &carrier) ||
-            !json_int(p, e, "kernel", &kernel))
-            return FFA_EINVAL;
-        ffa_opts o = default_opts();
-        o.algo = (int32_t)algo;
-        o.levels = (int32_t)levels;
-        o.cutoff = (int32_t)cutoff;
-        o.carrier = (int32_t)carrier;
-        o.kernel = (int32_t)kernel;
-        long long v;  // fields added later: absent means the built-in choice
-        if (json_int(p, e, "operands", &v)) o.operands = (int32_t)v;
-        if (json_int(p, e, "general", &v)) o.general = (int32_t)v;
-        if (json_int(p, e, "wino_min", &v)) o.wino_min = (int32_t)v;
-        record_tuned(c, n, k, (uint32_t)pp, (int)herm, (int)dA, (int)dC, o);
-        ++taken;
-        p = e + 1;
-    }
-    return taken;
+    return guarded([&]() -> int {
+        if (!c || !json) return FFA_EINVAL;
+        const char* arch = strstr(json, "\"arch\"");
+        const char* recs = strstr(json, "\"records\"");
+        if (!arch || !recs) return FFA_EINVAL;
+        const char* q1 = strchr(arch + 6, '"');
+        const char* q2 = q1 ? strchr(q1 + 1, '"') : nullptr;
+        if (!q2) return FFA_EINVAL;
+        if (std::string(q1 + 1, q2) != c->arch) return 0;
+        const char* p = strchr(recs, '[');
+        if (!p) return FFA_EINVAL;
+        int taken = 0;
+        while ((p = strchr(p, '{')) != nullptr) {
+            const char* e = strchr(p, '}');
+            if (!e) return FFA_EINVAL;
+            long long n, k, pp, herm, dA, dC, algo, levels, cutoff, carrier, kernel;
+            if (!json_int(p, e, "n", &n) || !json_int(p, e, "k", &k) || !json_int(p, e, "p", &pp) ||
+                !json_int(p, e, "herm", &herm) || !json_int(p, e, "dA", &dA) || !json_int(p, e, "dC", &dC) ||
+                !json_int(p, e, "algo", &algo) || !json_int(p, e, "levels", &levels) ||
+                !json_int(p, e, "cutoff", &cutoff) || !json_int(p, e, "carrier", &carrier) ||
+                !json_int(p, e, "kernel", &kernel))
+                return FFA_EINVAL;
+            ffa_opts o = default_opts();
+            o.algo = (int32_t)algo;
+            o.levels = (int32_t)levels;
+            o.cutoff = (int32_t)cutoff;
+            o.carrier = (int32_t)carrier;
+            o.kernel = (int32_t)kernel;
+            long long v;  // fields added later: absent means the built-in choice
+            if (json_int(p, e, "operands", &v)) o.operands = (int32_t)v;
+            if (json_int(p, e, "general", &v)) o.general = (int32_t)v;
+            if (json_int(p, e, "wino_min", &v)) o.wino_min = (int32_t)v;
+            record_tuned(c, n, k, (uint32_t)pp, (int)herm, (int)dA, (int)dC, o);
+            ++taken;
+            p = e + 1;
+        }
+        return taken;
+    });
 }
 
 int ffa_plan_describe(int64_t n, int64_t k, uint32_t p, int hermitian, int dA, int dC,
                       int64_t lda, int64_t ldc, const ffa_opts* opts, char* buf, int64_t size)
 {
-    Problem pr;
-    pr.n = n;
-    pr.k = k;
-    pr.lda = lda;
-    pr.ldc = ldc;
-    pr.p = p;
-    pr.herm = hermitian ? 1 : 0;
-    pr.dA = dA;
-    pr.dC = dC;
-    pr.opts = opts ? *opts : default_opts();
-    pr.aligned = !hermitian;
-    Plan pl = make_plan(pr);
-    if (buf && size > 0) {
-        const std::string s = describe(pl);
-        const size_t m = std::min<size_t>(s.size(), (size_t)size - 1);
-        std::memcpy(buf, s.data(), m);
-        buf[m] = 0;
-    }
-    return pl.status;
+    return guarded([&]() -> int {
+        Problem pr;
+        pr.n = n;
+        pr.k = k;
+        pr.lda = lda;
+        pr.ldc = ldc;
+        pr.p = p;
+        pr.herm = hermitian ? 1 : 0;
+        pr.dA = dA;
+        pr.dC = dC;
+        pr.opts = opts ? *opts : default_opts();
+        pr.aligned = !hermitian;
+        Plan pl = make_plan(pr);
+        if (buf && size > 0) {
+            const std::string s = describe(pl);
+            const size_t m = std::min<size_t>(s.size(), (size_t)size - 1);
+            std::memcpy(buf, s.data(), m);
+            buf[m] = 0;
+        }
+        return pl.status;
+    });
 }
 
 }  // extern "C"

@@ -352,6 +352,8 @@ int check_bound(const Plan& pl)
 // XCD with the least work so far (workgroup b runs on XCD b mod 8), and the
 // schedule interleaves the eight per-XCD lists; shorter lists are padded with
 // idle entries.
+constexpr int64_t MAX_SCHEDULE_TILES = 1ll << 27;
+
 int build_schedule(const std::vector<GemmTask>& tasks, bool cplx, size_t first, size_t last,
                    std::vector<TileEnt>& sched)
 {
@@ -361,6 +363,10 @@ int build_schedule(const std::vector<GemmTask>& tasks, bool cplx, size_t first, 
         std::vector<TileEnt> tiles;
     };
     std::vector<Group> groups;
+    // a schedule this long would not fit host memory sensibly (and needs no GPU)
+    int64_t want = 0;
+    for (size_t t = first; t < last; ++t) want += (int64_t)tasks[t].tiles_m * tasks[t].tiles_n;
+    if (want > MAX_SCHEDULE_TILES) return -1;
     int tiles = 0;
     for (size_t t = first; t < last; ++t) {
         const GemmTask& g = tasks[t];
@@ -494,9 +500,15 @@ void schedule_products(Plan& pl)
 {
     if (!pl.fork) {
         pl.gemm_split = (int)pl.gemm.size();
-        pl.total_tiles = build_schedule(pl.gemm, pl.cplx, 0, pl.gemm.size(), pl.sched);
+        const int t1 = build_schedule(pl.gemm, pl.cplx, 0, pl.gemm.size(), pl.sched);
+        const int t2 = t1 < 0 ? 0 : build_schedule(pl.gemm_r, false, 0, pl.gemm_r.size(), pl.sched_r);
+        if (t1 < 0 || t2 < 0) {
+            pl.status = FFA_EINVAL;
+            return;
+        }
+        pl.total_tiles = t1;
         if (pl.split_tail) split_tail(pl);
-        pl.total_tiles += build_schedule(pl.gemm_r, false, 0, pl.gemm_r.size(), pl.sched_r);
+        pl.total_tiles += t2;
         pl.sched2.clear();
         return;
     }
@@ -507,8 +519,13 @@ void schedule_products(Plan& pl)
     pl.gemm.insert(pl.gemm.end(), g2.begin(), g2.end());
     pl.gemm_aonly.assign(pl.gemm_split, 1);
     pl.gemm_aonly.resize(pl.gemm.size(), 0);
-    pl.total_tiles = build_schedule(pl.gemm, pl.cplx, 0, pl.gemm_split, pl.sched);
-    pl.total_tiles += build_schedule(pl.gemm, pl.cplx, pl.gemm_split, pl.gemm.size(), pl.sched2);
+    const int t1 = build_schedule(pl.gemm, pl.cplx, 0, pl.gemm_split, pl.sched);
+    const int t2 = t1 < 0 ? 0 : build_schedule(pl.gemm, pl.cplx, pl.gemm_split, pl.gemm.size(), pl.sched2);
+    if (t1 < 0 || t2 < 0) {
+        pl.status = FFA_EINVAL;
+        return;
+    }
+    pl.total_tiles = t1 + t2;
 }
 
 // Host check of every workspace reference of the product and addition tasks:
@@ -756,7 +773,10 @@ Plan make_plan(const Problem& pr)
     if (pr.alpha >= pr.p || pr.beta >= pr.p) { pl.status = FFA_EINVAL; return pl; }
     if (pr.herm && (pr.trans || pr.alpha != 1 || pr.beta != 0)) { pl.status = FFA_EUNSUPPORTED; return pl; }
     if (pr.n > 0 && pr.ldc < pr.n) { pl.status = FFA_EINVAL; return pl; }
-    if (pr.lda >= (1ll << 31) || pr.ldc >= (1ll << 31) || pr.n >= (1ll << 30)) { pl.status = FFA_EINVAL; return pl; }
+    if (pr.lda >= (1ll << 31) || pr.ldc >= (1ll << 31) || pr.n > FFA_N_MAX || pr.k >= (1ll << 31)) {
+        pl.status = FFA_EINVAL;
+        return pl;
+    }
     pl.carrier = cm.carrier;
     pl.nl = cm.nl;
     pl.cplx = pr.herm ? 1 : 0;
@@ -837,7 +857,7 @@ Plan make_batch_plan(const std::vector<Problem>& prs)
     int maxL = 0;
     std::vector<int> L(prs.size());
     for (size_t i = 0; i < prs.size(); ++i) {
-        if (prs[i].n < 0 || prs[i].k < 0 || prs[i].n >= (1ll << 30) || prs[i].k >= (1ll << 30)) {
+        if (prs[i].n < 0 || prs[i].k < 0 || prs[i].n > FFA_N_MAX || prs[i].k >= (1ll << 30)) {
             pl.status = FFA_EINVAL;
             return pl;
         }
@@ -883,6 +903,8 @@ Plan make_batch_plan(const std::vector<Problem>& prs)
         pl.a_ld.push_back(q.lda);
         aoff += round_up(q.n * q.lda * ain, 16) / ain;
         coff += round_up(q.n * q.n * cout, 16) / cout;
+        // packed buffers beyond any device memory (and far from int64 overflow)
+        if (aoff > (1ll << 44) || coff > (1ll << 44)) { pl.status = FFA_EINVAL; return pl; }
         if (q.n == 0) continue;
         // problems of one batch share one set of levels per problem; the
         // Builder keeps per-level task lists across problems

@@ -331,3 +331,83 @@ def test_last_round_split():
     assert st == 0 and d["tail_tiles"] == 0
     st, d = ffa.plan_describe(4096, 8192, 65519, hermitian=True, dA=ffa.U16, dC=ffa.U16)
     assert st == 0 and d["tail_tiles"] == 0
+
+
+def test_sizes_beyond_the_limits_are_refused_quickly():
+    # n above FFA_N_MAX (its C would not fit one GPU) is refused before any table is built
+    # (a plan of 2^24 rows used to try to build a schedule of 2^31 tiles on the host)
+    assert ffa.plan_describe(1 << 19, 16, 251, dA=ffa.I8_CENTRED, dC=ffa.U8)[0] == ffa.OK
+    for n in ((1 << 19) + 1, 1 << 24, 1 << 40):
+        assert ffa.plan_describe(n, 16, 251, dA=ffa.I8_CENTRED, dC=ffa.U8)[0] == ffa.EINVAL
+    assert ffa.plan_describe(16, 1 << 31, 251, dA=ffa.I8_CENTRED, dC=ffa.U8)[0] == ffa.EINVAL
+
+
+_ENOMEM_PROBE = r"""
+import ctypes, resource, sys
+sys.path.insert(0, {root!r})
+import paper_2101_01025_amd as ffa
+L = ffa.lib()
+vm = [int(l.split()[1]) * 1024 for l in open('/proc/self/status') if l.startswith('VmSize')][0]
+# 256 MiB of address space beyond what is mapped now: the schedule of this plan
+# (2^19 rows in 64-row tiles, 2^25 tiles) needs more
+resource.setrlimit(resource.RLIMIT_AS, (vm + (256 << 20), resource.RLIM_INFINITY))
+o = ffa.make_opts(kernel=15)
+buf = ctypes.create_string_buffer(256)
+st = L.ffa_plan_describe(1 << 19, 4096, 251, 0, ffa.I8_CENTRED, ffa.U8, 4096, 1 << 19,
+                         ctypes.byref(o), buf, 256)
+print("status", st)
+"""
+
+
+def test_host_allocation_failure_returns_enomem():
+    # A failing host allocation inside an entry point becomes FFA_ENOMEM instead of an
+    # exception crossing the C interface (which would terminate the caller's process).
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, "-c", _ENOMEM_PROBE.format(root=ROOT)], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "status %d" % ffa.ENOMEM in r.stdout, r.stdout
+
+
+def test_binding_refuses_outputs_it_cannot_write():
+    import torch
+    dev = torch.device("cuda", 0)
+    with pytest.raises(ValueError, match="tensor on"):
+        ffa._out(torch.zeros((4, 4), dtype=torch.uint8), 4, dev, torch.uint8)
+
+
+class _FakeTensor:
+    """Stands in for a device tensor in the binding's argument checks (no GPU here)."""
+
+    def __init__(self, dtype, numel, cuda=True, index=0, contiguous=True):
+        import torch
+        self.dtype, self._numel, self.is_cuda = dtype, numel, cuda
+        self.device = torch.device("cuda", index) if cuda else torch.device("cpu")
+        self._contiguous = contiguous
+
+    def numel(self):
+        return self._numel
+
+    def is_contiguous(self):
+        return self._contiguous
+
+
+def test_batch_run_checks_its_packed_buffers():
+    import torch
+    b = ffa.BatchSyrk.__new__(ffa.BatchSyrk)
+    b.handle, b.device_index, b.dA, b.dC, b.a_total, b.c_total = 1, 0, ffa.U16, ffa.U16, 100, 50
+    ok_a, ok_c = _FakeTensor(torch.uint16, 100), _FakeTensor(torch.uint16, 50)
+    b._packed(ok_a, b.dA, b.a_total, "A_packed", False)
+    b._packed(ok_c, b.dC, b.c_total, "C_packed", True)
+    bad = [(_FakeTensor(torch.uint16, 100, cuda=False), "tensor on"),
+           (_FakeTensor(torch.uint16, 100, index=1), "tensor on"),
+           (_FakeTensor(torch.int32, 100), "dtype"),
+           (_FakeTensor(torch.uint16, 100, contiguous=False), "contiguous"),
+           (_FakeTensor(torch.uint16, 99), "elements")]
+    for t, msg in bad:
+        with pytest.raises(ValueError, match=msg):
+            b._packed(t, b.dA, b.a_total, "A_packed", False)
+    b.handle = None
+    with pytest.raises(ValueError, match="closed"):
+        b._packed(ok_a, b.dA, b.a_total, "A_packed", False)
