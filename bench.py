@@ -38,6 +38,10 @@ WORKLOADS = {
     # 4096 independent problems, n uniform in [32, 512], k uniform in [n, 2n]
     "batch4096_p65521": dict(count=4096, nmin=32, nmax=512, p=65521, dA="uint16",
                              carrier="autotuned"),
+    # the small case: one recursion level over a classical base case, int64 storage; the
+    # host figures are process CPU-seconds of the oracle and of the one-level model
+    "syrk_p65521_n256_int64": dict(n=256, k=256, p=65521, dA="int64", carrier="int8 x2 limbs",
+                                   levels=1),
 }
 
 
@@ -114,33 +118,49 @@ def measured_traffic(workload, levels):
 
 
 def make_input(w, torch):
+    """Device inputs of the workload and their host copies (for the result check)."""
     import numpy as np
 
     import seeded_inputs as si
     n, k, p = w["n"], w["k"], w["p"]
     seed = si.config_seed(2)
     if w["dA"] == "int8":
-        return torch.from_numpy(si.centred_int8(n, k, p, seed)).to("cuda"), None
+        a = si.centred_int8(n, k, p, seed)
+        return torch.from_numpy(a).to("cuda"), None, a, None
+    if w["dA"] == "int64":
+        a = si.uniform_residues(n, k, p, si.config_seed(0))
+        return torch.from_numpy(a).to("cuda"), None, a, None
     if w["dA"] == "uint16":
         if w["name"].startswith("herk"):
             ar, ai = si.complex_residues(n, k, p, si.config_seed(4), dtype=np.int32)
             return (torch.from_numpy(ar).to("cuda").to(torch.uint16),
-                    torch.from_numpy(ai).to("cuda").to(torch.uint16))
+                    torch.from_numpy(ai).to("cuda").to(torch.uint16), ar, ai)
         a = si.uniform_residues(n, k, p, seed, dtype=np.int32)
-        return torch.from_numpy(a).to("cuda").to(torch.uint16), None
+        return torch.from_numpy(a).to("cuda").to(torch.uint16), None, a, None
     a = si.uniform_residues(n, k, p, si.config_seed(1), dtype=np.float64)
-    return torch.from_numpy(a).to("cuda"), None
+    return torch.from_numpy(a).to("cuda"), None, a, None
 
 
-def timed_steps(ffa, torch, w, A, Ai, C, Ci, plans, steps, warmup, blocks=5):
-    """Times `steps` calls of each plan (recursive, then classical if given).
+def timed_steps(ffa, torch, w, A, Ai, C, Ci, plans, steps, warmup, blocks=10):
+    """Times exactly `steps` calls of each plan (recursive, then classical if given).
 
-    The plans run in alternating blocks so that clock and thermal drift during
-    the run affects both alike.  Phase durations come from HIP events the
-    library records around each phase on the same stream.
-    Returns per plan: (ms per step, {phase: summed ms of its launches per call},
-    {phase: launches per call}).
+    The steps of each plan are cut into `blocks` blocks (at least one call each)
+    and the plans run in alternating blocks, so that clock and thermal drift
+    during the run affects both alike; every block is bracketed by a device
+    synchronisation and HIP events on the current stream.  The duration of the
+    product phase (the grouped product launch and its last-round sums) comes
+    from one pair of HIP events per call that the library records around it on
+    the same stream, during these same blocks (each recorded phase costs the
+    call some microseconds, so only this one is recorded here; the other phases
+    are measured by `phase_breakdown` outside the timed region).  Nothing is
+    flushed between calls: the inputs and the workspace stay in HBM (and partly
+    in the 256 MB MALL) from one call to the next, as in a loop of calls on
+    resident data.
+    Returns per plan: (ms per step = summed block time / steps, median over the
+    blocks of the block's ms per step, ms of the product phase per call).
     """
+    import statistics
+
     def one(opts):
         if Ai is None:
             ffa.syrk_modp(A, w["p"], C=C, opts=opts)
@@ -150,18 +170,15 @@ def timed_steps(ffa, torch, w, A, Ai, C, Ci, plans, steps, warmup, blocks=5):
         for _ in range(warmup):
             one(opts)
     torch.cuda.synchronize()
+    blocks = max(1, min(blocks, steps))
     total = [0.0] * len(plans)
-    phase_ms = [dict() for _ in plans]
-    phase_calls = [dict() for _ in plans]
-    names = ((ffa.PHASE_COND, "conditioning"), (ffa.PHASE_PRE, "preadd"),
-             (ffa.PHASE_PRODUCTS, "products"), (ffa.PHASE_POST, "postadd"))
+    per_step = [[] for _ in plans]
+    prod_ms = [0.0] * len(plans)
     per_block = [steps // blocks + (1 if b < steps % blocks else 0) for b in range(blocks)]
     for nb in per_block:
-        if nb == 0:
-            continue
         for i, opts in enumerate(plans):
             ffa.profile_reset(0)
-            ffa.profile_enable(0, True)
+            ffa.profile_enable(0, True, phases=1 << ffa.PHASE_PRODUCTS)
             start = torch.cuda.Event(enable_timing=True)
             stop = torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
@@ -171,17 +188,253 @@ def timed_steps(ffa, torch, w, A, Ai, C, Ci, plans, steps, warmup, blocks=5):
             stop.record()
             torch.cuda.synchronize()
             ffa.profile_enable(0, False)
-            total[i] += start.elapsed_time(stop)
-            for ph, name in names:
-                ms, calls = ffa.profile_read(0, ph)
-                phase_ms[i][name] = phase_ms[i].get(name, 0.0) + ms
-                phase_calls[i][name] = phase_calls[i].get(name, 0) + calls
-    out = []
-    for i in range(len(plans)):
-        ph = {name: round(phase_ms[i][name] / steps, 4) for _, name in names}
-        nl = {name: phase_calls[i][name] / steps for _, name in names}
-        out.append((total[i] / steps, ph, nl))
+            t = start.elapsed_time(stop)
+            total[i] += t
+            per_step[i].append(t / nb)
+            prod_ms[i] += ffa.profile_read(0, ffa.PHASE_PRODUCTS)[0]
+    return [(total[i] / steps, statistics.median(per_step[i]), prod_ms[i] / steps)
+            for i in range(len(plans))]
+
+
+def phase_breakdown(ffa, torch, w, A, Ai, C, Ci, opts, calls=5):
+    """ms per call of each phase (HIP events around every phase), and launches per call
+    of the product phase, over `calls` calls outside the timed region."""
+    names = ((ffa.PHASE_COND, "conditioning"), (ffa.PHASE_PRE, "preadd"),
+             (ffa.PHASE_PRODUCTS, "products"), (ffa.PHASE_POST, "postadd"))
+    torch.cuda.synchronize()
+    ffa.profile_reset(0)
+    ffa.profile_enable(0, True)
+    for _ in range(calls):
+        if Ai is None:
+            ffa.syrk_modp(A, w["p"], C=C, opts=opts)
+        else:
+            ffa.herk_modp2(A, Ai, w["p"], C_re=C, C_im=Ci, opts=opts)
+    torch.cuda.synchronize()
+    ffa.profile_enable(0, False)
+    out = {}
+    for ph, name in names:
+        ms, _ = ffa.profile_read(0, ph)
+        out[name] = round(ms / calls, 4)
     return out
+
+
+def unprofiled_ms(ffa, torch, w, A, Ai, C, Ci, opts, steps):
+    """ms per call of `steps` calls in one synchronised region, without the phase events."""
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        if Ai is None:
+            ffa.syrk_modp(A, w["p"], C=C, opts=opts)
+        else:
+            ffa.herk_modp2(A, Ai, w["p"], C_re=C, C_im=Ci, opts=opts)
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+# ---------------------------------------------------------------- result checks
+# After the timed region every plan runs once more into a C filled with a value
+# that is not a residue, and the result is checked on the host from the
+# definition itself (this is not the oracle): canonical residues everywhere in the
+# lower triangle, the strict upper triangle untouched, sampled entries
+# C_ij = sum_t A_it A_jt mod p, and Freivalds' test Sym(C) X = A (A^T X) mod p
+# for four random vectors (a wrong C passes with probability at most p^-4).
+# Every sum is formed in float64 from integers whose sums stay below 2^53, so
+# the host arithmetic is exact.
+
+VECTORS = 4
+CHUNK = 2048
+
+
+class VerifyError(RuntimeError):
+    pass
+
+
+def _f64(a):
+    import numpy as np
+    return np.asarray(a, dtype=np.float64)
+
+
+def _modp(x, p):
+    import numpy as np
+    return np.mod(np.rint(x), p)
+
+
+def _pairs(n, rng, count=2000):
+    import numpy as np
+    i = rng.integers(0, n, count)
+    j = rng.integers(0, n, count)
+    i, j = np.maximum(i, j), np.minimum(i, j)
+    edges = [0, 1, n - 2, n - 1]
+    for q in (2, 4, 8):
+        b = n // q
+        edges += [b - 1, b, b + 1]
+    e = np.unique(np.clip(np.array(edges), 0, n - 1))
+    ei, ej = np.meshgrid(e, e)
+    m = ei >= ej
+    return np.concatenate([i, ei[m]]), np.concatenate([j, ej[m]])
+
+
+def _sym_times(L, X, p):
+    """Sym(L) X mod p for the lower triangle L (n x n, host) of a symmetric matrix."""
+    import numpy as np
+    n = L.shape[0]
+    Y = np.zeros((n, X.shape[1]))
+    for r0 in range(0, n, CHUNK):
+        r1 = min(n, r0 + CHUNK)
+        B = np.tril(_f64(L[r0:r1, :r1]), r0)          # rows r0..r1-1, columns j <= i
+        Y[r0:r1] += B @ X[:r1]
+        Bs = np.tril(B, r0 - 1)                        # j < i: the mirrored part
+        Y[:r1] += Bs.T @ X[r0:r1]
+    return _modp(Y, p)
+
+
+def _herm_times(Lr, Li, Xr, Xi, p):
+    """Herm(L) X mod p for the lower triangle L = Lr + i Li of a Hermitian matrix."""
+    import numpy as np
+    n = Lr.shape[0]
+    Yr, Yi = np.zeros((n, Xr.shape[1])), np.zeros((n, Xr.shape[1]))
+    for r0 in range(0, n, CHUNK):
+        r1 = min(n, r0 + CHUNK)
+        Br = np.tril(_f64(Lr[r0:r1, :r1]), r0)
+        Bi = np.tril(_f64(Li[r0:r1, :r1]), r0)
+        Yr[r0:r1] += Br @ Xr[:r1] - Bi @ Xi[:r1]
+        Yi[r0:r1] += Br @ Xi[:r1] + Bi @ Xr[:r1]
+        Sr, Si = np.tril(Br, r0 - 1), np.tril(Bi, r0 - 1)   # conj(L_ji) above the diagonal
+        Yr[:r1] += Sr.T @ Xr[r0:r1] + Si.T @ Xi[r0:r1]
+        Yi[:r1] += Sr.T @ Xi[r0:r1] - Si.T @ Xr[r0:r1]
+    return _modp(Yr, p), _modp(Yi, p)
+
+
+def _rows_times(A, X):
+    """A X (A: n x k host residues, X: k x v float64), in row chunks."""
+    import numpy as np
+    out = np.zeros((A.shape[0], X.shape[1]))
+    for r0 in range(0, A.shape[0], CHUNK):
+        out[r0:r0 + CHUNK] = _f64(A[r0:r0 + CHUNK]) @ X
+    return out
+
+
+def _cols_times(A, X):
+    """A^T X (A: n x k host residues, X: n x v float64), in row chunks."""
+    import numpy as np
+    out = np.zeros((A.shape[1], X.shape[1]))
+    for r0 in range(0, A.shape[0], CHUNK):
+        out += _f64(A[r0:r0 + CHUNK]).T @ X[r0:r0 + CHUNK]
+    return out
+
+
+def _lower_checks(Ch, p, sentinel, rng):
+    import numpy as np
+    n = Ch.shape[0]
+    for r0 in range(0, n, CHUNK):
+        blk = Ch[r0:r0 + CHUNK]
+        rows = np.arange(r0, r0 + blk.shape[0])[:, None]
+        cols = np.arange(n)[None, :]
+        low = cols <= rows
+        v = blk[low]
+        if v.size and (v.min() < 0 or v.max() >= p):
+            raise VerifyError(f"non-canonical entry in the lower triangle (rows {r0}..)")
+        if not (blk[~low] == sentinel).all():
+            raise VerifyError(f"strict upper triangle written (rows {r0}..)")
+
+
+def verify_syrk(A_host, p, C_dev, sentinel, seed):
+    """Checks the lower triangle of C = Low(A A^T) mod p computed on the device.
+    A_host: n x k residues or centred residues (congruent mod p)."""
+    import numpy as np
+    n, k = A_host.shape
+    amax = float(np.abs(A_host).max()) if A_host.size else 0.0
+    if max(n, k) * amax * (p - 1) >= 2.0 ** 53 or k * amax * amax >= 2.0 ** 53:
+        raise VerifyError("host check would not be exact in float64")
+    rng = np.random.default_rng(seed)
+    Ch = C_dev.cpu().numpy()
+    if Ch.dtype == np.uint16:
+        Ch = Ch.astype(np.int32)
+    _lower_checks(Ch, p, sentinel, rng)
+    ii, jj = _pairs(n, rng)
+    got = Ch[ii, jj].astype(np.int64)
+    exp = np.empty(len(ii), dtype=np.int64)
+    for s0 in range(0, len(ii), 256):
+        a = _f64(A_host[ii[s0:s0 + 256]])
+        b = _f64(A_host[jj[s0:s0 + 256]])
+        exp[s0:s0 + 256] = _modp((a * b).sum(1), p).astype(np.int64)
+    if not np.array_equal(got, exp):
+        bad = int(np.argmax(got != exp))
+        raise VerifyError(f"entry ({ii[bad]}, {jj[bad]}) = {got[bad]}, expected {exp[bad]}")
+    X = rng.integers(0, p, (n, VECTORS)).astype(np.float64)
+    W = _modp(_cols_times(A_host, X), p)
+    Ya = _modp(_rows_times(A_host, W), p)
+    Yc = _sym_times(Ch, X, p)
+    if not np.array_equal(Ya, Yc):
+        raise VerifyError("Freivalds check failed")
+    return {"entries": int(len(ii)), "freivalds_vectors": VECTORS}
+
+
+def verify_herk(Ar, Ai, p, Cr_dev, Ci_dev, sentinel, seed):
+    """Checks Low(A A^H) over F_p[i]/(i^2+1) (planar re/im) computed on the device."""
+    import numpy as np
+    n, k = Ar.shape
+    if 2 * max(n, k) * float(p - 1) ** 2 >= 2.0 ** 53:
+        raise VerifyError("host check would not be exact in float64")
+    rng = np.random.default_rng(seed)
+    Cr = Cr_dev.cpu().numpy().astype(np.int64)
+    Ci = Ci_dev.cpu().numpy().astype(np.int64)
+    _lower_checks(Cr, p, sentinel, rng)
+    _lower_checks(Ci, p, sentinel, rng)
+    if (np.diagonal(Ci) != 0).any():
+        raise VerifyError("nonzero imaginary part on the diagonal")
+    ii, jj = _pairs(n, rng)
+    er = np.empty(len(ii), dtype=np.int64)
+    ei = np.empty(len(ii), dtype=np.int64)
+    for s0 in range(0, len(ii), 256):
+        xr, xi = _f64(Ar[ii[s0:s0 + 256]]), _f64(Ai[ii[s0:s0 + 256]])
+        yr, yi = _f64(Ar[jj[s0:s0 + 256]]), _f64(Ai[jj[s0:s0 + 256]])
+        er[s0:s0 + 256] = _modp((xr * yr + xi * yi).sum(1), p)
+        ei[s0:s0 + 256] = _modp((xi * yr - xr * yi).sum(1), p)
+    if not (np.array_equal(Cr[ii, jj], er) and np.array_equal(Ci[ii, jj], ei)):
+        raise VerifyError("sampled entries differ")
+    Xr = rng.integers(0, p, (n, VECTORS)).astype(np.float64)
+    Xi = rng.integers(0, p, (n, VECTORS)).astype(np.float64)
+    # A (A^H X): W = A^H X = (Ar^T Xr + Ai^T Xi) + i (Ar^T Xi - Ai^T Xr)
+    Wr = _modp(_cols_times(Ar, Xr) + _cols_times(Ai, Xi), p)
+    Wi = _modp(_cols_times(Ar, Xi) - _cols_times(Ai, Xr), p)
+    Yar = _modp(_rows_times(Ar, Wr) - _rows_times(Ai, Wi), p)
+    Yai = _modp(_rows_times(Ar, Wi) + _rows_times(Ai, Wr), p)
+    Ycr, Yci = _herm_times(Cr, Ci, Xr, Xi, p)
+    if not (np.array_equal(Yar, Ycr) and np.array_equal(Yai, Yci)):
+        raise VerifyError("Freivalds check failed")
+    return {"entries": int(len(ii)), "freivalds_vectors": VECTORS}
+
+
+def verify_batch(mats, c_off, ns, p, C_dev, sentinel, seed, whole=64):
+    """Every problem of a batch: Freivalds with four vectors, canonical lower
+    triangle, untouched upper triangle; `whole` of them compared entry by entry
+    with the product formed on the host."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    Ch = C_dev.cpu().numpy().astype(np.int64)
+    full = set(rng.choice(len(ns), min(whole, len(ns)), replace=False).tolist())
+    for i, M in enumerate(mats):
+        n = int(ns[i])
+        if n == 0:
+            continue
+        G = Ch[c_off[i]:c_off[i] + n * n].reshape(n, n)
+        low = np.tril(np.ones((n, n), dtype=bool))
+        if G[low].min() < 0 or G[low].max() >= p or not (G[~low] == sentinel).all():
+            raise VerifyError(f"problem {i}: non-canonical or upper triangle written")
+        Mf = _f64(M)
+        if i in full:
+            if not np.array_equal(G[low], _modp(Mf @ Mf.T, p).astype(np.int64)[low]):
+                raise VerifyError(f"problem {i} differs")
+            continue
+        X = rng.integers(0, p, (n, VECTORS)).astype(np.float64)
+        Ya = _modp(Mf @ _modp(Mf.T @ X, p), p)
+        if not np.array_equal(Ya, _sym_times(G, X, p)):
+            raise VerifyError(f"problem {i}: Freivalds check failed")
+    return {"problems": int(len(ns)), "compared_whole": len(full), "freivalds_vectors": VECTORS}
 
 
 def run_batch(args, w, ffa, torch):
@@ -200,7 +453,6 @@ def run_batch(args, w, ffa, torch):
     eq_ops = float((ns.astype(np.float64) ** 2 * ks).sum())
     B = ffa.BatchSyrk(ns, ks, p, ffa.U16, ffa.U16)
     Ap = B.pack(mats, np.uint16)
-    del mats
     A = torch.from_numpy(Ap.astype(np.int32)).to("cuda").to(torch.uint16)
     del Ap
     C = torch.zeros(B.c_total, dtype=torch.int32, device="cuda").to(torch.uint16)
@@ -216,9 +468,10 @@ def run_batch(args, w, ffa, torch):
         for _ in range(args.warmup):
             b.run(A, C)
     torch.cuda.synchronize()
-    blocks = 5
+    blocks = max(1, min(10, args.steps))
     per_block = [args.steps // blocks + (1 if i < args.steps % blocks else 0) for i in range(blocks)]
     total = [0.0] * len(runs)
+    per_step = [[] for _ in runs]
     prof_ms, prof_calls = 0.0, 0
     phase_tot = {}
     names = ((ffa.PHASE_COND, "conditioning"), (ffa.PHASE_PRE, "preadd"),
@@ -236,6 +489,7 @@ def run_batch(args, w, ffa, torch):
             stop.record()
             torch.cuda.synchronize()
             total[i] += start.elapsed_time(stop)
+            per_step[i].append(start.elapsed_time(stop) / nb)
         # profiled block of the tuned plan (direct launches, phase events)
         ffa.profile_reset(0)
         ffa.profile_enable(0, True)
@@ -249,6 +503,16 @@ def run_batch(args, w, ffa, torch):
         prof_calls += nb
     ms = total[0] / args.steps
     phases = {name: round(phase_tot[name] / prof_calls, 4) for _, name in names}
+    # the result of each plan, checked on the host after the timed region
+    import statistics
+    checked = {}
+    for name, b in (("tuned", B), ("classical", Bc)):
+        if b is None:
+            continue
+        C.fill_(0xFFFF)
+        b.run(A, C)
+        torch.cuda.synchronize()
+        checked[name] = verify_batch(mats, B.c_off, ns, p, C, 0xFFFF, 77)
     out = {
         "metric": "equivalent n^2k ops/s for A*A^T mod p (bit-exact)",
         "value": eq_ops / (ms * 1e-3),
@@ -257,11 +521,13 @@ def run_batch(args, w, ffa, torch):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_median": statistics.median(per_step[0]),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int8" if plan["carrier"] == "int8" else "f64",
         "data": "synthetic",
+        "verified": checked,
         "config": {"workload": f"batch of {w['count']} syrk problems, n in [{w['nmin']},{w['nmax']}], "
                                f"k in [n,2n], p={p}, input=uint16, one hipGraph launch per step",
                    "count": w["count"], "p": p, "sum_n2k": eq_ops,
@@ -280,7 +546,8 @@ def run_batch(args, w, ffa, torch):
                        "frac": achieved / peak, "traffic": None, "ops_per_step": ops}
     if Bc is not None:
         cms = total[1] / args.steps
-        out["classical_gpu"] = {"value": eq_ops / (cms * 1e-3), "unit": "n^2k/s", "ms_per_step": cms}
+        out["classical_gpu"] = {"value": eq_ops / (cms * 1e-3), "unit": "n^2k/s", "ms_per_step": cms,
+                                "ms_median": statistics.median(per_step[1])}
         out["speedup_vs_classical"] = cms / ms
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_batch(ns, ks, p, seed, args.cpu_seconds, eq_ops)
@@ -343,6 +610,29 @@ def cpu_baseline(w, seconds):
                       f"{t:.2f} s, scaled by n(n+1)/(m(m+1))"}
 
 
+def cpu_seconds_small(w, reps=5):
+    """Process CPU-seconds (CLOCK_PROCESS_CPUTIME_ID, all threads) of the oracle and of
+    the plain model of Algorithm 1 with one recursion level, on the workload itself
+    (median of `reps` runs each)."""
+    import statistics
+
+    import oracle
+    from oracle import alg1_model
+    import seeded_inputs as si
+    a = si.uniform_residues(w["n"], w["k"], w["p"], si.config_seed(0))
+
+    def cpu(f):
+        ts = []
+        for _ in range(reps):
+            t0 = time.process_time()
+            f()
+            ts.append(time.process_time() - t0)
+        return statistics.median(ts)
+    return {"oracle_cpu_s": cpu(lambda: oracle.syrk_modp(a, w["p"])),
+            "alg1_one_level_model_cpu_s": cpu(lambda: alg1_model.syrk(a, w["p"], 1)),
+            "oracle_threads": oracle.num_threads(), "reps": reps, "clock": "process CPU time"}
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -352,18 +642,29 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only (use --gpus 1); "
                                    "the multi-GPU design is described, not built"}))
         sys.exit(2)
+    import statistics
+
     import torch
 
     import paper_2101_01025_amd as ffa
     w = dict(WORKLOADS[args.workload])
     w["name"] = args.workload
-    if args.workload.startswith("batch"):
-        print(json.dumps(run_batch(args, w, ffa, torch)))
-        return
+    try:
+        if args.workload.startswith("batch"):
+            print(json.dumps(run_batch(args, w, ffa, torch)))
+            return
+        run_single(args, w, ffa, torch)
+    except VerifyError as e:
+        print(json.dumps({"error": f"result check failed: {e}", "workload": args.workload}))
+        sys.exit(1)
+
+
+def run_single(args, w, ffa, torch):
     n, k, p = w["n"], w["k"], w["p"]
     herm = w["name"].startswith("herk")
-    A, Ai = make_input(w, torch)
-    od = ffa.default_out_dtype(p) if w["dA"] != "float64" else torch.float64
+    A, Ai, A_host, Ai_host = make_input(w, torch)
+    od = ffa.default_out_dtype(p) if w["dA"] not in ("float64", "int64") else \
+        (torch.float64 if w["dA"] == "float64" else torch.int64)
     C = torch.zeros((n, n), dtype=od, device="cuda")
     Ci = torch.zeros((n, n), dtype=od, device="cuda") if herm else None
     torch.cuda.synchronize()
@@ -372,7 +673,8 @@ def main():
     hb = {"auto": ffa.HERK_AUTO, "2m": ffa.HERK_2M, "4m": ffa.HERK_4M}[args.herk_base]
     gen = {"auto": ffa.GENERAL_AUTO, "classical": ffa.GENERAL_CLASSICAL,
            "winograd": ffa.GENERAL_WINOGRAD}[args.general]
-    opts = ffa.make_opts(levels=args.levels, streams=streams, herk_base=hb, kernel=args.kernel,
+    levels = args.levels if args.levels >= 0 else w.get("levels", -1)
+    opts = ffa.make_opts(levels=levels, streams=streams, herk_base=hb, kernel=args.kernel,
                          general=gen, wino_min=args.wino_min)
     dA_code = ffa._dtype_code(A)
     _, plan = ffa.plan_describe(n, k, p, hermitian=herm, dA=dA_code, dC=ffa._dtype_code(C, True),
@@ -383,8 +685,25 @@ def main():
                               kernel=args.kernel)
     plans = [opts] if args.no_classical else [opts, classical]
     res = timed_steps(ffa, torch, w, A, Ai, C, Ci, plans, args.steps, args.warmup)
-    ms, phases, launches = res[0]
+    ms, ms_med, prod_ms = res[0]
     value = n * n * k / (ms * 1e-3)
+    bare = [unprofiled_ms(ffa, torch, w, A, Ai, C, Ci, o, args.steps) for o in plans]
+    phases = phase_breakdown(ffa, torch, w, A, Ai, C, Ci, opts)
+
+    # the result of every timed plan, checked on the host after the timed region
+    sentinel = {torch.uint8: 255, torch.int64: -7, torch.float64: -7.0}.get(od, 0xFFFF)
+    checked = {}
+    for name, o in zip(("recursive", "classical"), plans):
+        C.fill_(sentinel)
+        if herm:
+            Ci.fill_(sentinel)
+            ffa.herk_modp2(A, Ai, p, C_re=C, C_im=Ci, opts=o)
+            torch.cuda.synchronize()
+            checked[name] = verify_herk(A_host, Ai_host, p, C, Ci, sentinel, 91)
+        else:
+            ffa.syrk_modp(A, p, C=C, opts=o)
+            torch.cuda.synchronize()
+            checked[name] = verify_syrk(A_host, p, C, sentinel, 91)
 
     out = {
         "metric": "equivalent n^2k ops/s for A*A^T mod p (bit-exact)",
@@ -394,47 +713,52 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_median": ms_med,
+        "ms_per_step_unprofiled": bare[0],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int8" if plan["carrier"] == "int8" else "f64",
         "data": "synthetic",
+        "verified": checked,
         "config": {"workload": f"{'herk' if herm else 'syrk'} n={n} k={k} p={p} input={w['dA']} "
                                f"carrier={w['carrier']}",
                    "n": n, "k": k, "p": p, "levels": plan["levels"], "limbs": plan["limbs"],
                    "parallelism": "single GPU"},
         "phases_ms": phases,
-        "product_launches_per_step": launches["products"],
     }
     if herm:
         # value counts n^2 k operations of F_{p^2}; each is four products of F_p
         out["units"] = {"value": "n^2k/s of F_p^2 operations",
                         "fp_equivalent": 4.0 * n * n * k / (ms * 1e-3)}
     # roofline of the dominant kernel, the grouped product kernel: algorithmic ops of
-    # its launches in one step over their summed durations (HIP events per launch)
+    # one step's product phase over its duration in the timed region (HIP events)
     limb2 = plan["limbs"] ** 2  # macs counts real products (a complex one is four)
     ops = 2.0 * plan["macs"] * limb2
-    prod_ms = phases["products"]
     if plan["carrier"] == "int8":
         achieved = ops / (prod_ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "mfma", "kernel": "gemm_i8 (grouped products)",
                            "achieved": achieved, "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
                            "frac": achieved / PEAK_INT8_TOPS,
                            "traffic": measured_traffic(args.workload, plan["levels"]),
-                           "ops_per_step": ops}
+                           "ops_per_step": ops, "product_phase_ms": prod_ms}
     else:
         achieved = ops / (prod_ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "mfma", "kernel": "gemm_f64 (grouped products)",
                            "achieved": achieved, "peak": PEAK_F64_TFLOPS, "unit": "TFLOP/s",
                            "frac": achieved / PEAK_F64_TFLOPS, "traffic": None,
-                           "ops_per_step": ops}
+                           "ops_per_step": ops, "product_phase_ms": prod_ms}
     if not args.no_classical:
-        cms, cph, _ = res[1]
+        cms, cmed, cprod = res[1]
         out["classical_gpu"] = {"value": n * n * k / (cms * 1e-3), "unit": "n^2k/s",
-                                "ms_per_step": cms, "products_ms": cph["products"]}
+                                "ms_per_step": cms, "ms_median": cmed, "products_ms": cprod,
+                                "ms_per_step_unprofiled": bare[1]}
         out["speedup_vs_classical"] = cms / ms
+        out["speedup_vs_classical_unprofiled"] = bare[1] / bare[0]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        if "levels" in w:
+            out["cpu_seconds"] = cpu_seconds_small(w)
     print(json.dumps(out))
 
 

@@ -208,10 +208,12 @@ int ffa_batch_describe(const ffa_batch* b, char* buf, int64_t size);
 
 /* Phase timing with HIP events recorded on the context's stream around each
  * phase of every later call: 0 = conditioning, 1 = pre-additions (all levels),
- * 2 = products (one grouped launch), 3 = post-additions (all levels).
+ * 2 = products (the grouped launch and its last-round sums), 3 = post-additions
+ * (all levels).  phases is a bit mask (bit q: phase q; 15 = every phase, 0 = off);
+ * each recorded phase adds two events per call to the stream.
  * ffa_profile_read synchronises on the recorded events and returns the summed
- * milliseconds and the number of calls measured for the phase. */
-int ffa_profile_enable(ffa_ctx* ctx, int on);
+ * milliseconds and the number of event pairs measured for the phase. */
+int ffa_profile_enable(ffa_ctx* ctx, int phases);
 int ffa_profile_read(ffa_ctx* ctx, int phase, double* total_ms, int64_t* calls);
 int ffa_profile_reset(ffa_ctx* ctx);
 

@@ -135,8 +135,12 @@ def plan_describe(n, k, p, hermitian=False, dA=I64, dC=I64, lda=None, ldc=None, 
     return st, json.loads(buf.value.decode())
 
 
-def profile_enable(device_index, on=True):
-    _check(lib().ffa_profile_enable(context(device_index), int(on)))
+PROFILE_ALL = 15
+
+
+def profile_enable(device_index, on=True, phases=PROFILE_ALL):
+    """Phase timing on (for the phases of the bit mask `phases`) or off."""
+    _check(lib().ffa_profile_enable(context(device_index), phases if on else 0))
 
 
 def profile_reset(device_index):

@@ -33,8 +33,8 @@ struct ffa_ctx {
     int last_err = 0;
     std::map<std::string, std::unique_ptr<Plan>> cache;
     std::map<std::string, ffa_opts> tuned;  // autotuner's choice per shape and per size class
-    // phase timing
-    bool prof = false;
+    // phase timing: bit q set = phase q is recorded
+    int prof = 0;
     struct Pending {
         hipEvent_t a, b;
         int phase;
@@ -154,10 +154,10 @@ hipEvent_t take_event(ffa_ctx* c)
     return e;
 }
 
-// Records the start event of a phase (no-op when profiling is off).
-hipEvent_t phase_begin(ffa_ctx* c, hipStream_t s)
+// Records the start event of a phase (no-op when that phase is not profiled).
+hipEvent_t phase_begin(ffa_ctx* c, hipStream_t s, int phase)
 {
-    if (!c->prof) return nullptr;
+    if (!((c->prof >> phase) & 1)) return nullptr;
     hipEvent_t e = take_event(c);
     if (e) (void)hipEventRecord(e, s);
     return e;
@@ -165,7 +165,7 @@ hipEvent_t phase_begin(ffa_ctx* c, hipStream_t s)
 
 void phase_end(ffa_ctx* c, hipStream_t s, hipEvent_t start, int phase)
 {
-    if (!c->prof || !start) return;
+    if (!start) return;
     hipEvent_t e = take_event(c);
     if (!e) return;
     (void)hipEventRecord(e, s);
@@ -244,7 +244,7 @@ int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws)
     int e;
     if (!pl.cond.empty()) {
         if (pl.check_inputs && (e = launch_zero_flag(c->d_err, s))) return dev_fail(c, e);
-        hipEvent_t ev = phase_begin(c, ms);
+        hipEvent_t ev = phase_begin(c, ms, 0);
         const CondTask* ct = (const CondTask*)(blob + pl.off_cond);
         e = pl.cond_trans ? launch_condition_trans(ct, (int)pl.cond.size(), pl.cond_max_blocks,
                                                    pl.cond[0].dt_in, b, pl.fp, pl.carrier, c->d_err, s)
@@ -271,15 +271,12 @@ int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws)
     const GemmTask* g = (const GemmTask*)(blob + pl.off_gemm);
     auto products = [&](hipStream_t st, int64_t off, size_t nsched) -> int {
         if (nsched == 0) return 0;
-        hipEvent_t pev = phase_begin(c, st);
         const TileEnt* sc = (const TileEnt*)(blob + off);
-        const int r = pl.carrier == CAR_F64
-                          ? launch_gemm_f64(g, sc, (int)nsched, b, pl.fp, (void*)st)
-                          : launch_gemm_i8(pl.gemm_cfg, pl.gemm_src, g, sc, (int)nsched, b, pl.fp, (void*)st);
-        phase_end(c, st, pev, 2);
-        return r;
+        return pl.carrier == CAR_F64
+                   ? launch_gemm_f64(g, sc, (int)nsched, b, pl.fp, (void*)st)
+                   : launch_gemm_i8(pl.gemm_cfg, pl.gemm_src, g, sc, (int)nsched, b, pl.fp, (void*)st);
     };
-    hipEvent_t ev = pl.levels > 0 ? phase_begin(c, ps) : nullptr;
+    hipEvent_t ev = pl.levels > 0 ? phase_begin(c, ps, 1) : nullptr;
     for (int l = 0; l < pl.levels; ++l) {
         if (pl.pre[l].empty()) continue;
         e = launch_preadd((const PreaddTask*)(blob + pl.off_pre[l]), (int)pl.pre[l].size(),
@@ -294,15 +291,18 @@ int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws)
     }
     phase_end(c, ps, ev, 1);
     if (fork) {
+        hipEvent_t pev = phase_begin(c, ps, 2);
         if ((e = products(ps, pl.off_sched2, pl.sched2.size()))) return dev_fail(c, e);
+        phase_end(c, ps, pev, 2);
         hipError_t he = hipEventRecord(c->ev_join, ps);
         if (he != hipSuccess) return dev_fail(c, he);
     }
+    // one event pair around the grouped product launch and its last-round sums
+    hipEvent_t pev = pl.sched.empty() ? nullptr : phase_begin(c, ms, 2);
     if ((e = products(ms, pl.off_sched, pl.sched.size()))) return dev_fail(c, e);
     if (!pl.tail.empty()) {
         // the K-pieces of the launch's split last-round tiles, added into their places;
         // one launch per output format (the planner groups the tasks by it)
-        hipEvent_t pev = phase_begin(c, ms);
         for (size_t i0 = 0; i0 < pl.tail.size();) {
             size_t i1 = i0 + 1;
             while (i1 < pl.tail.size() && pl.tail[i1].out.dt == pl.tail[i0].out.dt) ++i1;
@@ -311,11 +311,11 @@ int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws)
             if (e) return dev_fail(c, e);
             i0 = i1;
         }
-        phase_end(c, ms, pev, 2);
     }
+    phase_end(c, ms, pev, 2);
     if (!pl.gemm_r.empty()) {
         // the real products of the 2M base case, then their combination into the leaves
-        hipEvent_t pev = phase_begin(c, ms);
+        hipEvent_t pev = phase_begin(c, ms, 2);
         e = launch_gemm_i8(pl.gemm_cfg_r, SRC_CARRIER, (const GemmTask*)(blob + pl.off_gemm_r),
                            (const TileEnt*)(blob + pl.off_sched_r), (int)pl.sched_r.size(), b, pl.fp, s);
         if (e) return dev_fail(c, e);
@@ -334,7 +334,7 @@ int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws)
         hipError_t he = hipStreamWaitEvent(ms, c->ev_join, 0);
         if (he != hipSuccess) return dev_fail(c, he);
     }
-    ev = pl.levels > 0 ? phase_begin(c, ms) : nullptr;
+    ev = pl.levels > 0 ? phase_begin(c, ms, 3) : nullptr;
     if (!pl.wpost.empty()) {
         // Strassen-Winograd combinations (before the post-additions that read P3, P4)
         e = launch_wino_post((const WinoPostTask*)(blob + pl.off_wpost), (int)pl.wpost.size(),
@@ -351,7 +351,7 @@ int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws)
     }
     if (!pl.upd.empty()) {
         // C <- alpha X + beta C (counted with the post-additions)
-        if (!ev) ev = phase_begin(c, ms);
+        if (!ev) ev = phase_begin(c, ms, 3);
         e = launch_update((const UpdateTask*)(blob + pl.off_upd), (int)pl.upd.size(), pl.upd_max_n,
                           pl.upd[0].x.dt, pl.upd[0].c.dt, b, pl.fp, s);
         if (e) return dev_fail(c, e);
@@ -575,7 +575,7 @@ int ffa_profile_enable(ffa_ctx* c, int on)
 {
     return guarded([&]() -> int {
         if (!c) return FFA_EINVAL;
-        c->prof = on != 0;
+        c->prof = on & 15;
         return FFA_OK;
     });
 }

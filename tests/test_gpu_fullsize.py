@@ -66,7 +66,7 @@ def _check_syrk_large(Ares, C, p, rng):
     ii, jj = _pairs(n, rng)
     assert np.array_equal(Ch[ii, jj], oracle.syrk_entries(Ares, p, ii, jj))
     Cl = np.tril(Ch)
-    for _ in range(2):
+    for _ in range(4):  # false-pass probability p^-4 at most
         x = rng.integers(0, p, n)
         yc, ya = oracle.freivalds_syrk(Ares, Cl, p, x)
         assert np.array_equal(yc, ya)
@@ -132,15 +132,25 @@ def test_int8x2_16384_p65521(algo):
     _check_syrk_large(Ares, C, p, np.random.default_rng(12))
 
 
-def test_herk_4096x8192_p65519():
-    """A 4096 x 8192 over F_p[i]/(i^2+1), p = 65519, planar uint16."""
+@pytest.mark.parametrize("plan", ["default", "levels1-2m", "levels1-4m", "classical-4m"])
+def test_herk_4096x8192_p65519(plan):
+    """A 4096 x 8192 over F_p[i]/(i^2+1), p = 65519, planar uint16: the default plan (2M base
+    case, no recursion), one level of Algorithm 1 over the 2M or the 4M base case, and the
+    plain complex product (four real products)."""
     ffa = _ffa()
     n, k, p = 4096, 8192, 65519
-    _say("herk", n, k, p)
+    kw = {"default": {}, "levels1-2m": dict(levels=1, herk_base=ffa.HERK_2M),
+          "levels1-4m": dict(levels=1, herk_base=ffa.HERK_4M),
+          "classical-4m": dict(algo=ffa.ALGO_CLASSICAL, herk_base=ffa.HERK_4M)}[plan]
+    if kw:
+        st, d = ffa.plan_describe(n, k, p, hermitian=True, dA=ffa.U16, dC=ffa.U16,
+                                  opts=ffa.make_opts(**kw))
+        assert st == 0 and d["levels"] == kw.get("levels", 0), d
+    _say("herk", n, k, p, plan)
     Ar, Ai = si.complex_residues(n, k, p, si.config_seed(4))
     Cr = torch.full((n, n), 0xBEEF, dtype=torch.int32, device="cuda").to(torch.uint16)
     Ci = torch.full((n, n), 0xBEEF, dtype=torch.int32, device="cuda").to(torch.uint16)
-    ffa.herk_modp2(_u16(Ar), _u16(Ai), p, C_re=Cr, C_im=Ci)
+    ffa.herk_modp2(_u16(Ar), _u16(Ai), p, C_re=Cr, C_im=Ci, **kw)
     torch.cuda.synchronize()
     _upper_untouched(Cr, 0xBEEF, n)
     _upper_untouched(Ci, 0xBEEF, n)
@@ -153,7 +163,7 @@ def test_herk_4096x8192_p65519():
     er, ei = oracle.herk_entries(Ar, Ai, p, ii, jj)
     assert np.array_equal(gr[ii, jj], er) and np.array_equal(gi[ii, jj], ei)
     Lr, Li = np.tril(gr), np.tril(gi)
-    for _ in range(2):
+    for _ in range(4):  # false-pass probability p^-8 at most (two coordinates each)
         xr, xi = rng.integers(0, p, n), rng.integers(0, p, n)
         yc, ya = oracle.freivalds_herk(Ar, Ai, Lr, Li, p, xr, xi)
         assert np.array_equal(yc[0], ya[0]) and np.array_equal(yc[1], ya[1])

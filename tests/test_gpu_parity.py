@@ -190,6 +190,98 @@ def test_int8x2_extreme_limbs():
         check_syrk(A, p, torch.int32, torch.int64, levels=1)
 
 
+# ------------------------------------------------------------------ at the exact-accumulation bound
+# The planner admits a product while K * max|x| * max|y| stays below the carrier's exact
+# range (int32 for INT8 MFMA, 2^53 for fp64).  These cases run at the largest K it admits,
+# with the operand magnitudes that reach the bound, and compare the whole lower triangle.
+
+def _pattern(n, k, hi, lo, kind):
+    """Residues: all `hi`, all `lo`, or `hi` / `lo` alternating with the parity of
+    row + column (so that rows of equal parity meet hi*hi + ... and rows of different
+    parity hi*lo terms in every position)."""
+    if kind == "hi":
+        return np.full((n, k), hi, dtype=np.int64)
+    if kind == "lo":
+        return np.full((n, k), lo, dtype=np.int64)
+    par = (np.arange(n)[:, None] + np.arange(k)[None, :]) & 1
+    return np.where(par == 0, hi, lo).astype(np.int64)
+
+
+def _check_planned(n, k, p, dA, dC, **kw):
+    ffa = _ffa()
+    st, d = ffa.plan_describe(n, k, p, dA=dA, dC=dC, opts=ffa.make_opts(**kw))
+    assert st == 0, d
+    return d
+
+
+@pytest.mark.parametrize("kind", ["hi", "lo", "alt"])
+@pytest.mark.parametrize("cfg", ["default", "cfg24"])
+def test_int8_p251_at_bound(kind, cfg):
+    """One limb, p = 251: K = 137344 (137344 * 125^2 = 2146000000, the last k-tile
+    multiple below 2^31 - 2^17) with entries +125, -125, or both alternating."""
+    ffa = _ffa()
+    p, n, k = 251, 256, 137344
+    kw = dict(algo=ffa.ALGO_CLASSICAL)
+    if cfg == "cfg24":
+        kw["kernel"] = 25
+    d = _check_planned(n, k, p, ffa.I8_CENTRED, ffa.U8, **kw)
+    assert d["max_k"] == k and d["max_abs"] == 125
+    assert ffa.plan_describe(n, k + 128, p, dA=ffa.I8_CENTRED, dC=ffa.U8,
+                             opts=ffa.make_opts(**kw))[0] == ffa.EBOUND
+    A = _pattern(n, k, 125, p - 125, kind)
+    check_syrk(A, p, torch.int8, torch.uint8, **kw)
+    if kind == "alt":
+        check_syrk(A, p, torch.int8, torch.uint8, levels=1)
+
+
+@pytest.mark.parametrize("vals", [(65521 - 32881, 65521 - 32881), (32639, 32639), (65520, 65520),
+                                  (65521 - 32881, 32639)])
+@pytest.mark.parametrize("operands", ["planes", "raw"])
+def test_int8x2_p65521_at_bound(vals, operands):
+    """Two limbs, p = 65521: K = 65408 (2 K 128^2 < 2^31 for the middle accumulator), with
+    the representatives of largest limbs -32881 (hi = -128) and 32639 (hi = 127), p - 1
+    (-1), and -32881 / 32639 alternating."""
+    ffa = _ffa()
+    p, n, k = 65521, 256, 65408
+    kw = dict(algo=ffa.ALGO_CLASSICAL,
+              operands=ffa.OPERANDS_RAW if operands == "raw" else ffa.OPERANDS_PLANES)
+    d = _check_planned(n, k, p, ffa.U16, ffa.U16, **kw)
+    assert d["max_k"] == k and d["src"] == ("raw_u16" if operands == "raw" else "carrier")
+    assert ffa.plan_describe(n, k + 128, p, dA=ffa.U16, dC=ffa.U16,
+                             opts=ffa.make_opts(**kw))[0] == ffa.EBOUND
+    A = _pattern(n, k, vals[0], vals[1], "alt")
+    check_syrk(A, p, torch.uint16, torch.uint16, **kw)
+
+
+def test_f64_direct_at_bound():
+    """fp64 carrier reading canonical doubles: K (p - 1)^2 < 2^53.  p = 131071 at the largest
+    K the planner admits, K = 524304, every entry p - 1 in most rows: such a dot product is
+    524304 * 131070^2 = 9007199248449600, 6291392 below 2^53."""
+    ffa = _ffa()
+    p, n, k = 131071, 64, 524304
+    d = _check_planned(n, k, p, ffa.F64, ffa.F64, algo=ffa.ALGO_CLASSICAL)
+    assert d["direct"] == 1 and d["max_k"] == k and d["max_abs"] == p - 1
+    assert k * (p - 1) ** 2 < 2 ** 53 <= (k + 16) * (p - 1) ** 2
+    assert ffa.plan_describe(n, k + 16, p, dA=ffa.F64, dC=ffa.F64,
+                             opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))[0] == ffa.EBOUND
+    A = np.full((n, k), p - 1, dtype=np.int64)
+    A[::3, 1::2] = 1  # some rows with other values, so that not every entry is equal
+    check_syrk(A.astype(np.float64), p, torch.float64, torch.float64, algo=ffa.ALGO_CLASSICAL)
+
+
+def test_f64_recursive_near_bound():
+    """fp64 carrier with recursion (centred values |x| <= 65535 held in fp32): one level,
+    leaf and general products of K = kpad / 2 >= 1048608, so that K 65535^2 lies between
+    2^52 and 2^53; entries +65535 / -65535 alternating."""
+    ffa = _ffa()
+    p, n, k = 131071, 64, 2097664
+    d = _check_planned(n, k, p, ffa.F64, ffa.F64, levels=1)
+    assert d["levels"] == 1 and d["st32"] == 1 and d["max_abs"] == 65535
+    assert 2 ** 52 <= d["max_k"] * 65535 ** 2 < 2 ** 53, d
+    A = _pattern(n, k, 65535, p - 65535, "alt")
+    check_syrk(A.astype(np.float64), p, torch.float64, torch.float64, levels=1)
+
+
 # ------------------------------------------------------------------ FP64 carrier
 
 @pytest.mark.parametrize("levels", [0, 1, 2, 4])
@@ -445,7 +537,7 @@ def test_full_size_p251_sampled_and_freivalds(algo):
     exp = oracle.syrk_entries(Ares, p, ii, jj)
     assert np.array_equal(Ch[ii, jj], exp)
     Cl = np.tril(Ch)
-    for _ in range(2):
+    for _ in range(4):  # false-pass probability p^-4 at most
         x = rng.integers(0, p, n)
         yc, ya = oracle.freivalds_syrk(Ares, Cl, p, x)
         assert np.array_equal(yc, ya)
