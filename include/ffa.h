@@ -55,7 +55,8 @@ enum {
     FFA_ENOMEM = -4,       /* device workspace or host memory could not be allocated */
     FFA_EDEVICE = -5,      /* a HIP call failed; ffa_last_device_error() has the code */
     FFA_EUNSUPPORTED = -6, /* valid request this library does not support (e.g. herk with p = 1 mod 4) */
-    FFA_EBOUND = -7        /* the exact-accumulation bound of the carrier is exceeded */
+    FFA_EBOUND = -7,       /* the exact-accumulation bound of the carrier is exceeded */
+    FFA_ESCRATCH = -8      /* ffa_syrk_modp_noalloc: the call needs more than FFA_SCRATCH_BYTES */
 };
 
 /* element formats of A and C */
@@ -152,6 +153,25 @@ int ffa_skew_unitary(uint32_t p, int hermitian, uint32_t* a, uint32_t* b, int* k
 int ffa_syrk_modp(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p,
                   int dA, const void* A, int64_t lda,
                   int dC, void* C, int64_t ldc, const ffa_opts* opts);
+
+/* For callers that cannot allocate device memory (code under graph capture,
+ * serving loops, harnesses that forbid hipMalloc): ffa_syrk_modp with the same
+ * arguments, results and errors, which calls no hipMalloc, hipFree or other
+ * allocating routine.  Its workspace and task tables live in a fixed device array
+ * of FFA_SCRATCH_BYTES per GPU, which the library holds from the moment it is
+ * loaded until the process ends (its address is looked up when a context is
+ * created on the GPU).  Host memory is still used for the plan (kept in the
+ * context's cache, as for ffa_syrk_modp).
+ *   - FFA_ESCRATCH: the call's workspace and tables would exceed FFA_SCRATCH_BYTES
+ *     (e.g. a recursive 16384 x 16384 call needs 576 MiB); nothing is launched.
+ *   - Every call on one GPU, from any context or stream, shares that GPU's array,
+ *     which keeps the last call's contents (no kernel of the call expects it to
+ *     hold zeros).  Calls that may overlap on one GPU (different streams, or
+ *     different host threads) race on it; calls in one stream do not. */
+#define FFA_SCRATCH_BYTES (64ll << 20)
+int ffa_syrk_modp_noalloc(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p,
+                          int dA, const void* A, int64_t lda,
+                          int dC, void* C, int64_t ldc, const ffa_opts* opts);
 
 /* The SYRK update form (Section 7, schedule for alpha A A^T + beta C):
  *   C <- alpha Low(op(A) op(A)^T) + beta Low(C)  mod p,

@@ -18,6 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("FFA_LIBRARY") or os.path.join(_HERE, "libffa.so")
 
 OK, EINVAL, EPRIME, ERANGE, ENOMEM, EDEVICE, EUNSUPPORTED, EBOUND = 0, -1, -2, -3, -4, -5, -6, -7
+ESCRATCH = -8
+SCRATCH_BYTES = 64 << 20  # FFA_SCRATCH_BYTES: fixed scratch of syrk_modp_noalloc per GPU
 I64, I32, U16, U8, F64, I8_CENTRED = 0, 1, 2, 3, 4, 5
 ALGO_AUTO, ALGO_CLASSICAL, ALGO_RECURSIVE = 0, 1, 2
 CARRIER_AUTO, CARRIER_INT8, CARRIER_F64 = 0, 1, 2
@@ -34,6 +36,7 @@ SYMBOLS = [
     "ffa_profile_enable", "ffa_profile_read", "ffa_profile_reset",
     "ffa_autotune_syrk", "ffa_batch_autotune", "ffa_tune_export", "ffa_tune_import",
     "ffa_batch_describe", "ffa_syrk_modp_ex", "ffa_batch_herk_plan", "ffa_batch_herk_exec",
+    "ffa_syrk_modp_noalloc",
 ]
 PHASE_COND, PHASE_PRE, PHASE_PRODUCTS, PHASE_POST = 0, 1, 2, 3
 
@@ -82,6 +85,7 @@ def lib():
         L.ffa_skew_unitary.argtypes = [u32, i32, ctypes.POINTER(u32), ctypes.POINTER(u32),
                                        ctypes.POINTER(i32)]
         L.ffa_syrk_modp.argtypes = [P, i64, i64, u32, i32, P, i64, i32, P, i64, P]
+        L.ffa_syrk_modp_noalloc.argtypes = [P, i64, i64, u32, i32, P, i64, i32, P, i64, P]
         L.ffa_syrk_modp_ex.argtypes = [P, i32, i64, i64, u32, u32, i32, P, i64, u32, i32, P, i64, P]
         L.ffa_herk_modp2.argtypes = [P, i64, i64, u32, i32, P, P, i64, i32, P, P, i64, P]
         L.ffa_batch_syrk_plan.argtypes = [P, i64, P, P, u32, i32, i32, P, ctypes.POINTER(P)]
@@ -248,6 +252,22 @@ def syrk_modp(A, p, C=None, out_dtype=None, opts=None, alpha=1, beta=0, trans=Fa
         st = lib().ffa_syrk_modp_ex(ctx, int(bool(trans)), n, k, p, alpha, _dtype_code(A),
                                     ctypes.c_void_p(A.data_ptr()), lda, beta, _dtype_code(C, True),
                                     ctypes.c_void_p(C.data_ptr()), ldc, ob)
+    _check(st, f"(device error {lib().ffa_last_device_error(ctx)})" if st == EDEVICE else "")
+    return C
+
+
+def syrk_modp_noalloc(A, p, C, opts=None, **kw):
+    """C = Low(A A^T) mod p through ffa_syrk_modp_noalloc: the library allocates no device
+    memory in this call (its workspace is a fixed scratch of SCRATCH_BYTES per GPU), so C
+    must be given.  Raises FfaError(ESCRATCH) when the call needs more scratch."""
+    ctx = _prep(A)
+    n, k = A.shape
+    C = _out(C, n, A.device, C.dtype)
+    o = opts if opts is not None else (make_opts(**kw) if kw else None)
+    ob = ctypes.byref(o) if o is not None else None
+    st = lib().ffa_syrk_modp_noalloc(ctx, n, k, p, _dtype_code(A), ctypes.c_void_p(A.data_ptr()),
+                                     _ld(A, k), _dtype_code(C, True), ctypes.c_void_p(C.data_ptr()),
+                                     _ld(C, n), ob)
     _check(st, f"(device error {lib().ffa_last_device_error(ctx)})" if st == EDEVICE else "")
     return C
 

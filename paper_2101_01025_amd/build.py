@@ -18,7 +18,7 @@ OBJDIR = os.path.join(CSRC, "_build")
 LIB = os.path.join(HERE, "libffa.so")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["gemm_i8.hip", "gemm_f64.hip", "elementwise.hip"]
+HIP_SOURCES = ["gemm_i8.hip", "gemm_f64.hip", "elementwise.hip", "noalloc.hip"]
 CPP_SOURCES = ["field.cpp", "plan.cpp", "api.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function"]

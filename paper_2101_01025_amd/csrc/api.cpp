@@ -206,10 +206,17 @@ int ensure_workspace(ffa_ctx* c, int64_t bytes)
     return FFA_OK;
 }
 
+// The plan's task tables packed on the host (once; the host copy is kept).
+const std::vector<char>& host_tables(Plan& pl)
+{
+    if (pl.h_blob.empty()) pl.h_blob = pack_tables(pl);
+    return pl.h_blob;
+}
+
 int upload_tables(ffa_ctx* c, Plan& pl)
 {
     if (pl.d_blob) return FFA_OK;
-    std::vector<char> blob = pack_tables(pl);
+    const std::vector<char>& blob = host_tables(pl);
     if (blob.empty()) return FFA_OK;
     hipError_t e = hipMalloc(&pl.d_blob, blob.size());
     if (e != hipSuccess) {
@@ -235,10 +242,9 @@ void free_tables(Plan& pl)
 // on the context's second stream, forked from the caller's stream after the
 // conditioning and joined back before the post-additions; the first product
 // group (products that read only A) runs on the caller's stream meanwhile.
-int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws)
+int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws, const char* blob)
 {
     b.p[BUF_WS] = ws;
-    char* blob = (char*)pl.d_blob;
     hipStream_t ms = c->stream;
     void* s = (void*)ms;
     int e;
@@ -389,7 +395,7 @@ int run_call(ffa_ctx* c, const Problem& pr, const void* A, const void* A2, void*
     int st = ensure_workspace(c, pl->ws_bytes);
     if (!st) st = upload_tables(c, *pl);
     if (st) return st;
-    return run_plan(c, *pl, b, c->ws);
+    return run_plan(c, *pl, b, c->ws, (const char*)pl->d_blob);
 }
 
 // The batch plan's own workspace, sized for its plan; drops a captured graph
@@ -438,7 +444,7 @@ int capture_graph(ffa_batch* b, const Bases& bs)
     if (he != hipSuccess) return dev_fail(c, he);
     hipStream_t user = c->stream;
     c->stream = b->cap;
-    const int st = run_plan(c, b->plan, bs, b->ws);
+    const int st = run_plan(c, b->plan, bs, b->ws, (const char*)b->plan.d_blob);
     c->stream = user;
     hipGraph_t g = nullptr;
     he = hipStreamEndCapture(b->cap, &g);
@@ -488,7 +494,7 @@ int batch_exec(ffa_batch* b, const Bases& bs)
         if (he != hipSuccess) return dev_fail(c, he);
         direct = cs != hipStreamCaptureStatusNone;  // the caller's capture records the kernels
     }
-    if (direct) return run_plan(c, b->plan, bs, b->ws);
+    if (direct) return run_plan(c, b->plan, bs, b->ws, (const char*)b->plan.d_blob);
     if (!b->gexec || b->gA != bs.p[BUF_A] || b->gC != bs.p[BUF_C] || b->gA2 != bs.p[BUF_A2] ||
         b->gC2 != bs.p[BUF_C2]) {
         const int st = capture_graph(b, bs);
@@ -526,6 +532,8 @@ int ffa_create(ffa_ctx** out, int device, void* hip_stream)
             if (colon != std::string::npos) c->arch.resize(colon);
         }
         hipError_t e = hipSetDevice(device);
+        // the fixed scratch of ffa_syrk_modp_noalloc: its address on this device
+        if (e == hipSuccess) e = (hipError_t)scratch_setup(device);
         if (e == hipSuccess) e = hipMalloc((void**)&c->d_err, 256);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
@@ -615,6 +623,7 @@ const char* ffa_status_string(int s)
     case FFA_EDEVICE: return "HIP call failed";
     case FFA_EUNSUPPORTED: return "unsupported request";
     case FFA_EBOUND: return "exact accumulation bound exceeded";
+    case FFA_ESCRATCH: return "the call needs more than the fixed scratch of the no-allocation entry point";
     }
     return "unknown status";
 }
@@ -651,6 +660,46 @@ int ffa_syrk_modp(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA, const 
         if (!opts && ctx) (void)tuned_opts(ctx, n, k, p, 0, dA, dC, &pr.opts);
         pr.aligned = ((uintptr_t)A % 16) == 0;
         return run_call(ctx, pr, A, nullptr, C, nullptr);
+    });
+}
+
+int ffa_syrk_modp_noalloc(ffa_ctx* ctx, int64_t n, int64_t k, uint32_t p, int dA, const void* A,
+                          int64_t lda, int dC, void* C, int64_t ldc, const ffa_opts* opts)
+{
+    return guarded([&]() -> int {
+        Problem pr;
+        pr.n = n;
+        pr.k = k;
+        pr.lda = lda;
+        pr.ldc = ldc;
+        pr.p = p;
+        pr.dA = dA;
+        pr.dC = dC;
+        pr.opts = opts ? *opts : default_opts();
+        if (!opts && ctx) (void)tuned_opts(ctx, n, k, p, 0, dA, dC, &pr.opts);
+        pr.aligned = ((uintptr_t)A % 16) == 0;
+        if (!ctx) return FFA_EINVAL;
+        if (pr.n > 0 && !C) return FFA_EINVAL;
+        if (pr.n > 0 && pr.k > 0 && !A) return FFA_EINVAL;
+        Plan* pl = cached_plan(ctx, pr);
+        if (pl->status) return pl->status;
+        if (pr.n == 0) return FFA_OK;
+        // tables first, then the workspace, in the fixed scratch
+        const std::vector<char>& tables = host_tables(*pl);
+        const int64_t tbytes = ((int64_t)tables.size() + 255) / 256 * 256;
+        if (tbytes + pl->ws_bytes > FFA_SCRATCH_BYTES) return FFA_ESCRATCH;
+        hipError_t he = hipSetDevice(ctx->device);
+        if (he != hipSuccess) return dev_fail(ctx, he);
+        char* base = scratch_base(ctx->device);
+        if (!base) return FFA_EDEVICE;
+        if (!tables.empty()) {
+            he = hipMemcpyAsync(base, tables.data(), tables.size(), hipMemcpyHostToDevice, ctx->stream);
+            if (he != hipSuccess) return dev_fail(ctx, he);
+        }
+        Bases b{};
+        b.p[BUF_A] = (char*)A;
+        b.p[BUF_C] = (char*)C;
+        return run_plan(ctx, *pl, b, base + tbytes, base);
     });
 }
 

@@ -210,6 +210,13 @@ struct UpdateTask {
     int32_t n, pad_;
 };
 
+// ---- fixed scratch of the entry point that allocates nothing (noalloc.hip) ----
+// Looks up the scratch array's device address on `device`, which must be the
+// current device; once per device, later calls return at once.  hipError_t as int.
+int scratch_setup(int device);
+// That address (null before scratch_setup succeeded on the device).
+char* scratch_base(int device);
+
 // ---- launch wrappers (defined in the .hip files) ---------------------------
 // All return a hipError_t value cast to int.
 int launch_zero_flag(int32_t* d_flag, void* stream);

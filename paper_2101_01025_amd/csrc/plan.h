@@ -82,7 +82,8 @@ struct Plan {
     std::vector<int64_t> a_off, c_off; // packed batch layout (elements)
     std::vector<int64_t> a_ld;         // packed batch: row stride of each A_i (elements)
     int64_t a_total = 0, c_total = 0;
-    // device copy of the tables (filled by the API layer)
+    // host and device copies of the tables (filled by the API layer)
+    std::vector<char> h_blob;
     void* d_blob = nullptr;
     int64_t blob_bytes = 0;
     int64_t off_cond = 0, off_gemm = 0, off_sched = 0, off_sched2 = 0, off_upd = 0;
