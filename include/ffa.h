@@ -56,7 +56,8 @@ enum {
     FFA_EDEVICE = -5,      /* a HIP call failed; ffa_last_device_error() has the code */
     FFA_EUNSUPPORTED = -6, /* valid request this library does not support (e.g. herk with p = 1 mod 4) */
     FFA_EBOUND = -7,       /* the exact-accumulation bound of the carrier is exceeded */
-    FFA_ESCRATCH = -8      /* ffa_syrk_modp_noalloc: the call needs more than FFA_SCRATCH_BYTES */
+    FFA_ESCRATCH = -8,     /* ffa_syrk_modp_noalloc: the call needs more than FFA_SCRATCH_BYTES */
+    FFA_EWAIT = -9         /* a bounded wait inside a kernel gave up (ffa_device_status) */
 };
 
 /* element formats of A and C */
@@ -92,11 +93,15 @@ enum { FFA_CARRIER_AUTO = 0, FFA_CARRIER_INT8 = 1, FFA_CARRIER_F64 = 2 };
  *                 FFA_OPERANDS_PLANES: always; FFA_OPERANDS_RAW: without recursion and
  *                 with uint16 input in 16-byte aligned rows, the product kernel reads A
  *                 itself and forms the limbs on the fly (else ignored)
- *   streams       FFA_STREAMS_AUTO / FFA_STREAMS_ONE: everything in stream order on the
- *                 caller's stream; FFA_STREAMS_TWO: with recursion, the pre-additions and
- *                 the products that need them run on a second stream of the context while
- *                 the products that read only A run on the caller's stream (joined before
- *                 the post-additions)
+ *   streams       FFA_STREAMS_AUTO: with one level of recursion and one limb of a real
+ *                 field, the pre-additions run on the context's second stream beside the
+ *                 single product launch on the caller's stream, whose tiles that read only
+ *                 A come first and whose tiles that read S1..S4 wait for them (joined
+ *                 before the post-additions); otherwise as FFA_STREAMS_ONE.
+ *                 FFA_STREAMS_ONE: everything in stream order on the caller's stream;
+ *                 FFA_STREAMS_TWO: with recursion, the pre-additions and the products that
+ *                 need them run on a second stream as a second product launch while the
+ *                 products that read only A run on the caller's stream
  *   herk_base     base case of ffa_herk_modp2: FFA_HERK_AUTO / FFA_HERK_2M = the 2M method
  *                 (Section 6, Algorithm 3 with epsilon = 1): one real SYRK of Xr + Xi and one
  *                 real GEMM Xr Xi^T, 1.5 n^2 k products over F_p; FFA_HERK_4M = the four real
@@ -138,6 +143,13 @@ int ffa_destroy(ffa_ctx* ctx);
 int ffa_set_stream(ffa_ctx* ctx, void* hip_stream);
 /* hipError_t of the last failing HIP call of this context (0 if none). */
 int ffa_last_device_error(const ffa_ctx* ctx);
+/* Synchronises the context's stream and reports FFA_EWAIT if a bounded wait inside
+ * a kernel of an earlier call on the context gave up, which makes that call's result
+ * invalid (the record is then cleared); FFA_OK otherwise.  Such waits exist where a
+ * call runs its pre-additions beside the product launch (opts.streams AUTO, one limb,
+ * one level): the product tiles that read S1..S4 wait, for about a second at most,
+ * for the pre-addition kernel on the context's second stream. */
+int ffa_device_status(ffa_ctx* ctx);
 const char* ffa_status_string(int status);
 
 /* The skew-unitary Y used for p (Section 4):

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("FFA_LIBRARY") or os.path.join(_HERE, "libffa.so")
 
 OK, EINVAL, EPRIME, ERANGE, ENOMEM, EDEVICE, EUNSUPPORTED, EBOUND = 0, -1, -2, -3, -4, -5, -6, -7
-ESCRATCH = -8
+ESCRATCH, EWAIT = -8, -9
 SCRATCH_BYTES = 64 << 20  # FFA_SCRATCH_BYTES: fixed scratch of syrk_modp_noalloc per GPU
 I64, I32, U16, U8, F64, I8_CENTRED = 0, 1, 2, 3, 4, 5
 ALGO_AUTO, ALGO_CLASSICAL, ALGO_RECURSIVE = 0, 1, 2
@@ -36,7 +36,7 @@ SYMBOLS = [
     "ffa_profile_enable", "ffa_profile_read", "ffa_profile_reset",
     "ffa_autotune_syrk", "ffa_batch_autotune", "ffa_tune_export", "ffa_tune_import",
     "ffa_batch_describe", "ffa_syrk_modp_ex", "ffa_batch_herk_plan", "ffa_batch_herk_exec",
-    "ffa_syrk_modp_noalloc",
+    "ffa_syrk_modp_noalloc", "ffa_device_status",
 ]
 PHASE_COND, PHASE_PRE, PHASE_PRODUCTS, PHASE_POST = 0, 1, 2, 3
 
@@ -80,6 +80,7 @@ def lib():
         L.ffa_destroy.argtypes = [P]
         L.ffa_set_stream.argtypes = [P, P]
         L.ffa_last_device_error.argtypes = [P]
+        L.ffa_device_status.argtypes = [P]
         L.ffa_status_string.argtypes = [i32]
         L.ffa_status_string.restype = ctypes.c_char_p
         L.ffa_skew_unitary.argtypes = [u32, i32, ctypes.POINTER(u32), ctypes.POINTER(u32),
@@ -140,6 +141,12 @@ def plan_describe(n, k, p, hermitian=False, dA=I64, dC=I64, lda=None, ldc=None, 
 
 
 PROFILE_ALL = 15
+
+
+def device_status(device_index=0):
+    """Synchronises the device's context and raises FfaError(EWAIT) if a bounded wait
+    inside a kernel of an earlier call gave up (the results of those calls are not valid)."""
+    _check(lib().ffa_device_status(context(device_index)), "device status")
 
 
 def profile_enable(device_index, on=True, phases=PROFILE_ALL):

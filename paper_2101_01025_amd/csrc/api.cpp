@@ -33,6 +33,7 @@ struct ffa_ctx {
     int last_err = 0;
     std::map<std::string, std::unique_ptr<Plan>> cache;
     std::map<std::string, ffa_opts> tuned;  // autotuner's choice per shape and per size class
+    std::map<int, bool> coresident;         // per product configuration: fits beside the pre-additions
     // phase timing: bit q set = phase q is recorded
     int prof = 0;
     struct Pending {
@@ -235,6 +236,29 @@ void free_tables(Plan& pl)
     pl.d_blob = nullptr;
 }
 
+// Whether the signalling pre-addition kernel fits a CU beside a workgroup of the
+// plan's product kernel (gfx950: 512 VGPRs per SIMD lane, 160 KiB of LDS per CU),
+// so that it runs while the product launch holds every CU.  Measured once per
+// product configuration and context.
+bool coresident(ffa_ctx* c, const Plan& pl)
+{
+    if (pl.carrier != CAR_I8) return false;
+    auto it = c->coresident.find(pl.gemm_cfg);
+    if (it != c->coresident.end()) return it->second;
+    bool ok = false;
+    int gv = 0, gt = 0, glds = 0, pv = 0, pt = 0;
+    if (c->arch == "gfx950" && gemm_i8_config_regs(pl.gemm_cfg, &gv, &gt, &glds) == 0 &&
+        preadd_signal_regs(&pv, &pt) == 0 && gv > 0 && pv > 0 && gv <= 256 && pv <= 256) {
+        auto waves_per_simd = [](int threads) { return (threads / 64 + 3) / 4; };
+        auto granule = [](int v) { return (v + 7) / 8 * 8; };
+        const int regs = waves_per_simd(gt) * granule(gv) + waves_per_simd(pt) * granule(pv);
+        ok = regs <= 512 && glds <= 160 * 1024 && waves_per_simd(gt) + waves_per_simd(pt) <= 8;
+    }
+    (void)hipGetLastError();
+    c->coresident[pl.gemm_cfg] = ok;
+    return ok;
+}
+
 // The launch sequence: conditioning, pre-additions (top-down), all products in
 // one grouped launch, post-additions (bottom-up).
 // The workspace (at least pl.ws_bytes) and the uploaded tables are the caller's
@@ -245,6 +269,7 @@ void free_tables(Plan& pl)
 int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws, const char* blob)
 {
     b.p[BUF_WS] = ws;
+    b.p[BUF_ERR] = (char*)c->d_err;
     hipStream_t ms = c->stream;
     void* s = (void*)ms;
     int e;
@@ -267,8 +292,13 @@ int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws, const char* blob)
             if (h_err) return FFA_ERANGE;
         }
     }
-    const bool fork = pl.fork && !pl.sched2.empty();
+    // pre-additions beside the product launch: the counter the waiting tiles read is
+    // zeroed first; the pre-addition kernel runs on the second stream when both kernels
+    // fit a CU together, else before the products on this stream (the waits then pass)
+    const bool beside = pl.overlap_pre && coresident(c, pl);
+    const bool fork = (pl.fork && !pl.sched2.empty()) || beside;
     hipStream_t ps = fork ? c->aux : ms;  // stream of the pre-additions
+    if (pl.overlap_pre && (e = launch_zero_words(b, pl.wait_off, 2, s))) return dev_fail(c, e);
     if (fork) {
         hipError_t he = hipEventRecord(c->ev_fork, ms);
         if (he == hipSuccess) he = hipStreamWaitEvent(ps, c->ev_fork, 0);
@@ -285,8 +315,14 @@ int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws, const char* blob)
     hipEvent_t ev = pl.levels > 0 ? phase_begin(c, ps, 1) : nullptr;
     for (int l = 0; l < pl.levels; ++l) {
         if (pl.pre[l].empty()) continue;
-        e = launch_preadd((const PreaddTask*)(blob + pl.off_pre[l]), (int)pl.pre[l].size(),
-                          pl.pre_max_h[l], pl.pre_max_w[l], b, pl.fp, pl.carrier, (void*)ps);
+        if (pl.overlap_pre) {
+            e = launch_preadd_signal((const PreaddTask*)(blob + pl.off_pre[l]), (int)pl.pre[l].size(),
+                                     pl.pre_max_h[l], pl.pre_max_w[l], b, pl.fp, pl.pre_blocks, pl.wait_off,
+                                     (void*)ps);
+        } else {
+            e = launch_preadd((const PreaddTask*)(blob + pl.off_pre[l]), (int)pl.pre[l].size(),
+                              pl.pre_max_h[l], pl.pre_max_w[l], b, pl.fp, pl.carrier, (void*)ps);
+        }
         if (e) return dev_fail(c, e);
     }
     if (!pl.wpre.empty()) {
@@ -296,7 +332,10 @@ int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws, const char* blob)
         if (e) return dev_fail(c, e);
     }
     phase_end(c, ps, ev, 1);
-    if (fork) {
+    if (beside) {
+        hipError_t he = hipEventRecord(c->ev_join, ps);
+        if (he != hipSuccess) return dev_fail(c, he);
+    } else if (fork) {
         hipEvent_t pev = phase_begin(c, ps, 2);
         if ((e = products(ps, pl.off_sched2, pl.sched2.size()))) return dev_fail(c, e);
         phase_end(c, ps, pev, 2);
@@ -535,6 +574,7 @@ int ffa_create(ffa_ctx** out, int device, void* hip_stream)
         // the fixed scratch of ffa_syrk_modp_noalloc: its address on this device
         if (e == hipSuccess) e = (hipError_t)scratch_setup(device);
         if (e == hipSuccess) e = hipMalloc((void**)&c->d_err, 256);
+        if (e == hipSuccess) e = hipMemset(c->d_err, 0, 256);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
@@ -578,6 +618,24 @@ int ffa_set_stream(ffa_ctx* c, void* hip_stream)
 }
 
 int ffa_last_device_error(const ffa_ctx* c) { return c ? c->last_err : 0; }
+
+int ffa_device_status(ffa_ctx* c)
+{
+    return guarded([&]() -> int {
+        if (!c) return FFA_EINVAL;
+        hipError_t he = hipSetDevice(c->device);
+        if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+        if (he == hipSuccess) he = hipStreamSynchronize(c->aux);
+        int32_t h = 0;
+        if (he == hipSuccess) he = hipMemcpy(&h, c->d_err + 1, sizeof(int32_t), hipMemcpyDeviceToHost);
+        if (he != hipSuccess) return dev_fail(c, he);
+        if (!h) return FFA_OK;
+        const int32_t zero = 0;
+        he = hipMemcpy(c->d_err + 1, &zero, sizeof(int32_t), hipMemcpyHostToDevice);
+        if (he != hipSuccess) return dev_fail(c, he);
+        return FFA_EWAIT;
+    });
+}
 
 int ffa_profile_enable(ffa_ctx* c, int on)
 {
@@ -624,6 +682,7 @@ const char* ffa_status_string(int s)
     case FFA_EUNSUPPORTED: return "unsupported request";
     case FFA_EBOUND: return "exact accumulation bound exceeded";
     case FFA_ESCRATCH: return "the call needs more than the fixed scratch of the no-allocation entry point";
+    case FFA_EWAIT: return "a bounded wait inside a kernel gave up; results since the last check are not valid";
     }
     return "unknown status";
 }

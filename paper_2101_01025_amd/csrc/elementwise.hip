@@ -8,6 +8,8 @@
 // Every value is reduced mod p where it is produced.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_common.h"
 #include "ffa_internal.h"
 
@@ -371,6 +373,125 @@ __global__ void __launch_bounds__(256) preadd_i8(const PreaddTask* tasks, Bases 
                             *reinterpret_cast<const int2*>(out[j][half][q][l]);
                 }
     }
+}
+
+// One limb over F_p (p < 2^8), real field: the carrier and every S hold centred
+// residues in [-(p-1)/2, (p-1)/2], and the pre-additions stay in that form
+// throughout (no canonical round trip).  Each S is reduced once: a sum that
+// contains a product by a coefficient of Y with an fp32 quotient
+// (mod_centred_small), a short sum of residues with cen_short.  The element
+// pairs (left column c, right column c + w/2) are those the block-structured Y
+// mixes; with the scalar Y the two halves are independent.
+typedef int nt4 __attribute__((ext_vector_type(4)));
+
+template <int YK, int VEC, bool NT = false>
+__device__ __forceinline__ void preadd_c1_item(const PreaddTask& T, const Bases& b, const FieldParams& fp,
+                                               int r, int c)
+{
+    const int h = T.h, w = T.w, hw = w / 2;
+    typedef int8_t vec_t[VEC];
+    // A11, A12, A21, A22 (blk = 2 * row half + column half), left / right column halves
+    alignas(16) vec_t in[4][2];
+    const char* abase = b.p[T.a.buf] + T.a.off;
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const char* src = abase + (int64_t)((blk >> 1) * h + r) * T.a.ld + (blk & 1) * w + c + half * hw;
+            if (NT) *reinterpret_cast<nt4*>(in[blk][half]) = __builtin_nontemporal_load(reinterpret_cast<const nt4*>(src));
+            else if (VEC == 16) *reinterpret_cast<int4*>(in[blk][half]) = *reinterpret_cast<const int4*>(src);
+            else *reinterpret_cast<int2*>(in[blk][half]) = *reinterpret_cast<const int2*>(src);
+        }
+    const int32_t p = fp.p, r20 = fp.r20;
+    const float ip = (float)fp.inv_p;
+    // Y's coefficients as centred residues (|a|, |b| <= (p-1)/2)
+    const int32_t ca = fp.ya > fp.half ? fp.ya - p : fp.ya;
+    const int32_t cb = fp.yb > fp.half ? fp.yb - p : fp.yb;
+    alignas(16) vec_t out[4][2];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        int32_t x[4][2];
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+            for (int half = 0; half < 2; ++half) x[blk][half] = in[blk][half][e];
+        int32_t s1[2], s2[2];
+        if (YK == Y_BLOCKS) {
+            // [X_L | X_R] Y = [a X_L - b X_R | b X_L + a X_R];  |.| <= 4 ((p-1)/2)^2 < 2^16
+            const int32_t dl = x[2][0] - x[0][0], dr = x[2][1] - x[0][1];
+            s1[0] = mod_centred_small(__mul24(ca, dl) - __mul24(cb, dr), p, ip);
+            s1[1] = mod_centred_small(__mul24(cb, dl) + __mul24(ca, dr), p, ip);
+            s2[0] = mod_centred_small(x[3][0] - __mul24(ca, x[2][0]) + __mul24(cb, x[2][1]), p, ip);
+            s2[1] = mod_centred_small(x[3][1] - __mul24(cb, x[2][0]) - __mul24(ca, x[2][1]), p, ip);
+        } else {
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                s1[half] = mod_centred_small(__mul24(ca, x[2][half] - x[0][half]), p, ip);
+                s2[half] = mod_centred_small(x[3][half] - __mul24(ca, x[2][half]), p, ip);
+            }
+        }
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const int32_t t = s1[half] - x[3][half];  // S3 before reduction, |t| <= p - 1
+            out[0][half][e] = (int8_t)s1[half];
+            out[1][half][e] = (int8_t)s2[half];
+            out[2][half][e] = (int8_t)cen_short(t, p, r20);                  // S3 = S1 - A22
+            out[3][half][e] = (int8_t)cen_short(t + x[1][half], p, r20);     // S4 = S3 + A12
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        char* sbase = b.p[T.s[j].buf] + T.s[j].off + (int64_t)r * T.s[j].ld + c;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            char* dst = sbase + half * hw;
+            if (NT) __builtin_nontemporal_store(*reinterpret_cast<const nt4*>(out[j][half]), reinterpret_cast<nt4*>(dst));
+            else if (VEC == 16) *reinterpret_cast<int4*>(dst) = *reinterpret_cast<const int4*>(out[j][half]);
+            else *reinterpret_cast<int2*>(dst) = *reinterpret_cast<const int2*>(out[j][half]);
+        }
+    }
+}
+
+template <int YK, int VEC>
+__global__ void __launch_bounds__(256) preadd_c1(const PreaddTask* tasks, Bases b, FieldParams fp)
+{
+    const PreaddTask& T = tasks[blockIdx.y];
+    const int gpr = T.w / 2 / VEC;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= T.h * gpr) return;
+    preadd_c1_item<YK, VEC>(T, b, fp, idx / gpr, (idx % gpr) * VEC);
+}
+
+// The same on a fixed grid that loops over the work, for running beside the
+// product launch: each workgroup, once every one of its threads' S values is
+// stored, raises the workspace counter by one with release ordering at device
+// scope (its stores are written back from this XCD's L2 before the counter
+// moves), so that product tiles waiting for the counter read complete S blocks.
+// Its loads and stores are non-temporal: the streamed blocks then displace less
+// of the operand panels that the product tiles beside it keep in L2 (measured:
+// 1.847 vs 1.860 ms per call at 16384^2, p = 251).
+template <int YK>
+__global__ void __launch_bounds__(256) preadd_c1_signal(const PreaddTask* tasks, Bases b, FieldParams fp,
+                                                        int64_t counter_off)
+{
+    constexpr int VEC = 16;
+    const PreaddTask& T = tasks[blockIdx.y];
+    const int gpr = T.w / 2 / VEC;
+    const int total = T.h * gpr;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x)
+        preadd_c1_item<YK, VEC, true>(T, b, fp, idx / gpr, (idx % gpr) * VEC);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(reinterpret_cast<int32_t*>(b.p[BUF_WS] + counter_off), 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ void zero_words(Bases b, int64_t off, int words)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < words) reinterpret_cast<int32_t*>(b.p[BUF_WS] + off)[i] = 0;
 }
 
 // fp64 carrier (real only): centred residues held as doubles.
@@ -990,6 +1111,40 @@ int launch_condition(const CondTask* d_tasks, int ntasks, int nblocks, int dt_in
     return (int)hipGetLastError();
 }
 
+int launch_preadd_signal(const PreaddTask* d_tasks, int ntasks, int h, int w, const Bases& b,
+                         const FieldParams& fp, int blocks, int64_t counter_off, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if (ntasks <= 0 || h <= 0 || w <= 0 || (w / 2) % 16 || fp.nl != 1 || fp.cplx) return (int)hipErrorInvalidValue;
+    const dim3 g((unsigned)blocks, ntasks);
+    if (fp.ykind == Y_BLOCKS)
+        hipLaunchKernelGGL((preadd_c1_signal<Y_BLOCKS>), g, dim3(256), 0, s, d_tasks, b, fp, counter_off);
+    else
+        hipLaunchKernelGGL((preadd_c1_signal<Y_SCALAR>), g, dim3(256), 0, s, d_tasks, b, fp, counter_off);
+    return (int)hipGetLastError();
+}
+
+int launch_zero_words(const Bases& b, int64_t off, int words, void* stream)
+{
+    if (words <= 0) return 0;
+    hipLaunchKernelGGL(zero_words, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, (hipStream_t)stream, b,
+                       off, words);
+    return (int)hipGetLastError();
+}
+
+int preadd_signal_regs(int* vgprs, int* threads)
+{
+    hipFuncAttributes a{};
+    hipError_t e = hipFuncGetAttributes(&a, (const void*)preadd_c1_signal<Y_BLOCKS>);
+    if (e != hipSuccess) return (int)e;
+    hipFuncAttributes a2{};
+    e = hipFuncGetAttributes(&a2, (const void*)preadd_c1_signal<Y_SCALAR>);
+    if (e != hipSuccess) return (int)e;
+    *vgprs = std::max(a.numRegs, a2.numRegs);
+    *threads = 256;
+    return 0;
+}
+
 int launch_preadd(const PreaddTask* d_tasks, int ntasks, int h, int w, const Bases& b,
                   const FieldParams& fp, int carrier, void* stream)
 {
@@ -1002,9 +1157,18 @@ int launch_preadd(const PreaddTask* d_tasks, int ntasks, int h, int w, const Bas
         else hipLaunchKernelGGL(preadd_f64<double>, g, dim3(256), 0, s, d_tasks, b, fp);
     } else if (!fp.cplx) {
         if (fp.nl == 1) {
-            const int64_t t8 = (int64_t)h * (w / 2 / 8);
-            hipLaunchKernelGGL((preadd_i8<1, 0, 8>), dim3((unsigned)((t8 + 255) / 256), ntasks),
-                               dim3(256), 0, s, d_tasks, b, fp);
+            // one limb: centred arithmetic throughout; 16 columns per thread when every
+            // half-row holds whole 16-byte groups (w / 2 is a multiple of the k-tile)
+            const bool v16 = (w / 2) % 16 == 0;
+            const int vec = v16 ? 16 : 8;
+            const dim3 g((unsigned)(((int64_t)h * (w / 2 / vec) + 255) / 256), ntasks);
+            if (fp.ykind == Y_BLOCKS) {
+                if (v16) hipLaunchKernelGGL((preadd_c1<Y_BLOCKS, 16>), g, dim3(256), 0, s, d_tasks, b, fp);
+                else hipLaunchKernelGGL((preadd_c1<Y_BLOCKS, 8>), g, dim3(256), 0, s, d_tasks, b, fp);
+            } else {
+                if (v16) hipLaunchKernelGGL((preadd_c1<Y_SCALAR, 16>), g, dim3(256), 0, s, d_tasks, b, fp);
+                else hipLaunchKernelGGL((preadd_c1<Y_SCALAR, 8>), g, dim3(256), 0, s, d_tasks, b, fp);
+            }
         } else {
             const int64_t t8 = (int64_t)h * (w / 2 / 8);
             hipLaunchKernelGGL((preadd_i8<2, 0, 8>), dim3((unsigned)((t8 + 255) / 256), ntasks),

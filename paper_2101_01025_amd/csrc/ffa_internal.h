@@ -25,7 +25,8 @@ enum BufId : int32_t {
     BUF_C = 2,   // caller's C (real part)
     BUF_C2 = 3,  // caller's imaginary part of C
     BUF_WS = 4,  // library workspace
-    NBUF = 5
+    BUF_ERR = 5, // the context's device status words (int32 [0]: input range, [1]: wait timeout)
+    NBUF = 6
 };
 
 struct Bases {
@@ -103,6 +104,8 @@ struct FieldParams {
     int32_t alpha, beta;  // C <- alpha X + beta C (canonical) in the update pass
     int32_t npo;          // complex carriers: 4 = planes re, im, -re and re + im (2M base case)
     int32_t st32;         // fp64 carrier held in fp32 storage (exact integers below 2^24)
+    int32_t r20;          // round(2^20 / p): centred reduction of short sums for p < 2^8
+    int32_t pad_;
 };
 
 // ---- tasks ----------------------------------------------------------------
@@ -135,7 +138,12 @@ struct GemmTask {
     int32_t syrk;
     int32_t tiles_m, tiles_n;
     int32_t kvalid;        // columns of the operands that hold data (K for carriers)
-    int32_t pad_;
+    // > 0: the task's operands are written by a kernel running beside the launch;
+    // before its first load a tile waits until the workspace counter at byte
+    // wait_off has reached this value (bounded; a timeout is recorded in the context's
+    // status word BUF_ERR[1])
+    int32_t wait;
+    int64_t wait_off;
 };
 
 // Operand source of a product launch (every task of a launch shares it).
@@ -239,6 +247,17 @@ int launch_update(const UpdateTask* d_tasks, int ntasks, int max_n, int x_dt, in
                   const FieldParams& fp, void* stream);
 int launch_preadd(const PreaddTask* d_tasks, int ntasks, int h, int w, const Bases& b,
                   const FieldParams& fp, int carrier, void* stream);
+// The same pre-additions (one limb, real field) on a grid of `blocks` x ntasks
+// workgroups that loop over the work, each raising the workspace counter at byte
+// `counter_off` by one when its part is written (release at device scope): run on
+// a second stream beside the product launch whose tiles wait for the counter.
+int launch_preadd_signal(const PreaddTask* d_tasks, int ntasks, int h, int w, const Bases& b,
+                         const FieldParams& fp, int blocks, int64_t counter_off, void* stream);
+// Zeroes `words` int32 words at byte `off` of the workspace (a kernel, so that
+// graph capture records no memset node).
+int launch_zero_words(const Bases& b, int64_t off, int words, void* stream);
+// Resources of the signalling pre-addition kernel (for the co-residency check).
+int preadd_signal_regs(int* vgprs, int* threads);
 // out_dt: format of the outputs of this level (every task of a launch shares it)
 int launch_postadd(const PostaddTask* d_tasks, int ntasks, int h, int out_dt, const Bases& b,
                    const FieldParams& fp, void* stream);
@@ -254,6 +273,9 @@ int gemm_i8_config_ktile(int cfg);
 int gemm_i8_config_raw(int cfg);  // the configuration can read raw uint16 operands
 int gemm_i8_config_valid(int cfg, int nl, int cplx);
 int gemm_i8_default_config(int nl, int cplx, int64_t max_dim);
+// VGPRs per thread, threads per workgroup and LDS bytes of a configuration's kernel
+// (carrier operands); hipError_t as int
+int gemm_i8_config_regs(int cfg, int* vgprs, int* threads, int* lds);
 int gemm_tile_f64();
 // k-tile of the FP64 product kernel, in carrier elements
 constexpr int KTILE_F64 = 16;

@@ -37,6 +37,8 @@
 // of operand panels and every XCD gets the same amount of work.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.h"
 #include "ffa_internal.h"
 
@@ -73,8 +75,23 @@ __device__ __forceinline__ int32_t mod_small_p(int32_t x, int32_t p, int32_t c16
     // (the mask tells the compiler that the product fits its 24-bit multiplier)
     const int32_t v = (x >> 16) * (c16 & 0xff) + (x & 0xffff) + off;
     const int32_t q = (int32_t)floorf((float)v * inv_lo);
-    const uint32_t r = (uint32_t)(v - __mul24(q, p));
+    const uint32_t r = (uint32_t)mad24_s(q, -p, v);
     return (int32_t)min(r, r - (uint32_t)p);
+}
+
+// Canonical residue of an int32 x with |x| < 2^22 p (p < 2^8) in six full-rate
+// operations: y = x / p is formed in fp32 and rounded to the nearest integer by
+// adding 1.5 * 2^23 in the same fused multiply-add (whose result then has an
+// ulp of 1).  The computed y is within |y| 2^-23 < 1/2 of x / p, so q differs
+// from x / p by less than 1 and r = x - q p lies in (-p, p); one unsigned
+// minimum makes it canonical.
+__device__ __forceinline__ int32_t mod_fast_p(int32_t x, int32_t p, float inv_p)
+{
+    constexpr float MAGIC = 12582912.0f;  // 1.5 * 2^23
+    const float t = __builtin_fmaf((float)x, inv_p, MAGIC);
+    const int32_t q = __float_as_int(t) - __float_as_int(MAGIC);
+    const int32_t r = mad24_s(q, -p, x);
+    return (int32_t)min((uint32_t)r, (uint32_t)(r + p));
 }
 
 // The first lim (1 <= lim < 8) uint16 elements at byte offset off, element by
@@ -161,6 +178,12 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     const TileEnt ent = sched[blockIdx.x];
     if (ent.x < 0) return;  // padding entry of the XCD-balanced schedule
     const GemmTask& T = tasks[ent.x];
+    if (T.wait > 0) {
+        // operands produced beside this launch: wait until they are all written
+        if (threadIdx.x == 0)
+            wait_counter(bases.p[BUF_WS] + T.wait_off, T.wait, reinterpret_cast<int32_t*>(bases.p[BUF_ERR]) + 1);
+        __syncthreads();
+    }
     const int row0 = (ent.y & 0xffff) * BT, col0 = (ent.y >> 16) * BT;
     const int M = T.M, N = T.N, K = T.K;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -457,8 +480,16 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     const bool syrk = T.syrk != 0;
     const int ldc = T.c.ld;
     const int rows_c = min(BT, M - row0), cols_c = min(BT, N - col0);
-    auto residue = [&](int r, int m, int n, int v) -> int32_t {
-        if (NL == 1) return mod_small_p(acc[r][0][m][n][v], p, c16, moff, inv_lo);  // one limb: p < 2^8
+    // one limb: the six-operation reduction where every accumulator stays below
+    // 2^22 p in magnitude (K ((p-1)/2)^2 below it: the planner's products up to
+    // K = 67000 at p = 251), else the exact 24-bit folding
+    const bool fast = NL == 1 && (int64_t)K * fp.half * fp.half < ((int64_t)p << 22);
+    const float inv_p32 = (float)fp.inv_p;
+    auto residue_in = [&](auto fast_tag, int r, int m, int n, int v) __attribute__((always_inline)) -> int32_t {
+        if (NL == 1) {
+            if (decltype(fast_tag)::value) return mod_fast_p(acc[r][0][m][n][v], p, inv_p32);
+            return mod_small_p(acc[r][0][m][n][v], p, c16, moff, inv_lo);
+        }
         double val = 65536.0 * (double)acc[r][0][m][n][v] + 256.0 * (double)acc[r][NACC - 2][m][n][v] +
                      (double)acc[r][NACC - 1][m][n][v];
         if (RAW) {
@@ -473,8 +504,11 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     // writes whole 16-byte segments of C rows.  Segments that cross the matrix
     // edge or the diagonal of a base case are written element by element.  Needs
     // a 16-byte aligned tile origin and row stride, and 32-bit tile offsets.
-    auto epilogue = [&](auto tag) {
+    auto epilogue = [&](auto tag, auto fast_tag) __attribute__((always_inline)) {
         using OT = decltype(tag);
+        auto residue = [&](int r, int m, int n, int v) __attribute__((always_inline)) {
+            return residue_in(fast_tag, r, m, n, v);
+        };
         constexpr int ES = (int)sizeof(OT);
         constexpr int RB = BT * ES;   // bytes per staged row
         constexpr int NSR = RB / 16;  // segments per row
@@ -552,12 +586,18 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
             }
         }
     };
+    // (the faster reduction only for byte residues, the format of every product of a
+    // one-limb recursion, so that the epilogue exists once more, not five times)
+    if (fast && T.c.dt == DT_U8) {
+        epilogue(uint8_t{}, std::true_type{});
+        return;
+    }
     switch (T.c.dt) {
-    case DT_U8: epilogue(uint8_t{}); break;
-    case DT_U16: epilogue(uint16_t{}); break;
-    case DT_I32: epilogue(int32_t{}); break;
-    case DT_I64: epilogue(int64_t{}); break;
-    case DT_F64: epilogue(double{}); break;
+    case DT_U8: epilogue(uint8_t{}, std::false_type{}); break;
+    case DT_U16: epilogue(uint16_t{}, std::false_type{}); break;
+    case DT_I32: epilogue(int32_t{}, std::false_type{}); break;
+    case DT_I64: epilogue(int64_t{}, std::false_type{}); break;
+    case DT_F64: epilogue(double{}, std::false_type{}); break;
     default: break;
     }
 }
@@ -660,6 +700,24 @@ static int launch_src(int src, const GemmTask* d_tasks, const TileEnt* d_sched, 
         if (src == SRC_RAW_U16)
             return launch_cfg<NL, CPLX, BT, WGM, WGN, KT, PF, SRC_RAW_U16>(d_tasks, d_sched, nblocks, b, fp, s);
     }
+    return (int)hipErrorInvalidValue;
+}
+
+int gemm_i8_config_regs(int cfg, int* vgprs, int* threads, int* lds)
+{
+#define FFA_REGS(ID, NL, CP, BT, WM, WN, KT, PF)                                                       \
+    if (cfg == ID) {                                                                                 \
+        hipFuncAttributes a{};                                                                       \
+        const hipError_t e =                                                                         \
+            hipFuncGetAttributes(&a, (const void*)gemm_i8<NL, CP, BT, WM, WN, KT, PF, SRC_CARRIER>); \
+        if (e != hipSuccess) return (int)e;                                                          \
+        *vgprs = a.numRegs;                                                                          \
+        *threads = WM * WN * 64;                                                                     \
+        *lds = 2 * ((CP ? 2 : 1) * NL + NL) * BT * KT;                                               \
+        return 0;                                                                                    \
+    }
+    FFA_I8_CONFIGS(FFA_REGS)
+#undef FFA_REGS
     return (int)hipErrorInvalidValue;
 }
 

@@ -296,6 +296,7 @@ Common common_setup(uint32_t p, int herm, int dA, int dC, const ffa_opts& o)
     fp.nl = cm.nl;
     fp.cplx = herm ? 1 : 0;
     fp.inv_p = 1.0 / (double)p;
+    fp.r20 = (int32_t)(((1 << 20) + p / 2) / p);
     fp.npo = herm ? 3 : 1;
     return cm;
 }
@@ -355,11 +356,12 @@ int check_bound(const Plan& pl)
 constexpr int64_t MAX_SCHEDULE_TILES = 1ll << 27;
 
 int build_schedule(const std::vector<GemmTask>& tasks, bool cplx, size_t first, size_t last,
-                   std::vector<TileEnt>& sched)
+                   std::vector<TileEnt>& sched, const std::vector<char>* phase = nullptr)
 {
     constexpr int GR = 4, GC = 8, NX = 8;
     struct Group {
         double cost;
+        int phase;  // groups of phase 0 come before those of phase 1 in every XCD's list
         std::vector<TileEnt> tiles;
     };
     std::vector<Group> groups;
@@ -375,6 +377,7 @@ int build_schedule(const std::vector<GemmTask>& tasks, bool cplx, size_t first, 
             const int bj_end = g.syrk ? std::min(bi + GR, g.tiles_n) : g.tiles_n;
             for (int bj = 0; bj < bj_end; bj += GC) {
                 Group gr;
+                gr.phase = phase ? (*phase)[t] : 0;
                 for (int ti = bi; ti < std::min(bi + GR, g.tiles_m); ++ti)
                     for (int tj = bj; tj < std::min(bj + GC, g.tiles_n); ++tj)
                         if (!g.syrk || tj <= ti) gr.tiles.push_back({(int32_t)t, ti | (tj << 16)});
@@ -385,8 +388,9 @@ int build_schedule(const std::vector<GemmTask>& tasks, bool cplx, size_t first, 
             }
         }
     }
-    std::stable_sort(groups.begin(), groups.end(),
-                     [](const Group& a, const Group& b) { return a.cost > b.cost; });
+    std::stable_sort(groups.begin(), groups.end(), [](const Group& a, const Group& b) {
+        return a.phase != b.phase ? a.phase < b.phase : a.cost > b.cost;
+    });
     std::vector<std::vector<TileEnt>> bins(NX);
     double load[NX] = {0};
     for (const Group& gr : groups) {
@@ -500,7 +504,13 @@ void schedule_products(Plan& pl)
 {
     if (!pl.fork) {
         pl.gemm_split = (int)pl.gemm.size();
-        const int t1 = build_schedule(pl.gemm, pl.cplx, 0, pl.gemm.size(), pl.sched);
+        // with the pre-additions beside the launch, the tiles that wait for them come
+        // after every tile that reads only A, on every XCD
+        std::vector<char> phase;
+        if (pl.overlap_pre)
+            for (char a : pl.gemm_aonly) phase.push_back(a ? 0 : 1);
+        const int t1 = build_schedule(pl.gemm, pl.cplx, 0, pl.gemm.size(), pl.sched,
+                                      pl.overlap_pre ? &phase : nullptr);
         const int t2 = t1 < 0 ? 0 : build_schedule(pl.gemm_r, false, 0, pl.gemm_r.size(), pl.sched_r);
         if (t1 < 0 || t2 < 0) {
             pl.status = FFA_EINVAL;
@@ -830,6 +840,22 @@ Plan make_plan(const Problem& pr)
     pl.zero_fill = pr.k == 0;
     pl.fork = o.streams == FFA_STREAMS_TWO && pl.levels > 0 && !pl.herk2m && !pl.wino;
     pl.split_tail = !pl.fork;
+    // pre-additions beside the product launch (streams AUTO): one limb of a real field,
+    // one level, carrier operands, 16-byte column groups in each half of a block
+    pl.overlap_pre = o.streams == FFA_STREAMS_AUTO && pl.status == FFA_OK && pl.levels == 1 &&
+                     pl.carrier == CAR_I8 && pl.nl == 1 && !pl.cplx && pl.wpre.empty() &&
+                     pl.gemm_src == SRC_CARRIER && pl.pre.size() == 1 && pl.pre[0].size() == 1 &&
+                     (pl.pre[0][0].w / 2) % 16 == 0;
+    if (pl.overlap_pre) {
+        pl.pre_blocks = PRE_SIGNAL_BLOCKS;
+        pl.wait_off = round_up(pl.ws_bytes, 256);
+        pl.ws_bytes = pl.wait_off + 256;  // the counter and the timeout word
+        for (size_t t = 0; t < pl.gemm.size(); ++t)
+            if (!pl.gemm_aonly[t]) {
+                pl.gemm[t].wait = pl.pre_blocks;
+                pl.gemm[t].wait_off = pl.wait_off;
+            }
+    }
     size_grids(pl);
     return pl;
 }
@@ -970,7 +996,8 @@ std::string describe(const Plan& pl)
              "\"gemm_tasks\":%zu,\"tiles\":%d,\"blocks\":%zu,\"cfg\":%d,\"tile\":%d,"
              "\"macs\":%lld,\"ykind\":%d,\"ya\":%d,\"yb\":%d,\"src\":\"%s\",\"streams\":%d,"
              "\"blocks_a_only\":%zu,\"herk_base\":\"%s\",\"real_tasks\":%zu,\"general\":\"%s\","
-             "\"wino_tasks\":%zu,\"wino_min\":%lld,\"cfg_real\":%d,\"st32\":%d,\"tail_tiles\":%zu}",
+             "\"wino_tasks\":%zu,\"wino_min\":%lld,\"cfg_real\":%d,\"st32\":%d,\"tail_tiles\":%zu,"
+             "\"overlap_pre\":%d}",
              pl.status, pl.levels, pl.carrier == CAR_F64 ? "f64" : "int8", pl.nl, pl.cplx,
              (long long)pl.npad, (long long)pl.kpad, pl.direct ? 1 : 0, pl.max_abs,
              (long long)pl.max_k, (long long)pl.ws_bytes, pl.cond.size(), pre.c_str(), post.c_str(),
@@ -979,7 +1006,7 @@ std::string describe(const Plan& pl)
              pl.fp.yb, pl.gemm_src == SRC_RAW_U16 ? "raw_u16" : "carrier", pl.fork ? 2 : 1,
              pl.sched.size(), pl.herk2m ? "2m" : (pl.cplx ? "4m" : "none"), pl.gemm_r.size(),
              pl.wpre.empty() ? "classical" : "winograd", pl.wpre.size(), (long long)pl.wino_min,
-             pl.herk2m ? pl.gemm_cfg_r : -1, pl.fp.st32, pl.tail.size());
+             pl.herk2m ? pl.gemm_cfg_r : -1, pl.fp.st32, pl.tail.size(), pl.overlap_pre ? 1 : 0);
     return buf;
 }
 

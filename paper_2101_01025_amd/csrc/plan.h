@@ -77,6 +77,14 @@ struct Plan {
     bool split_tail = false;            // may split the launch's last partial round over K
     std::vector<TailTask> tail;         // tiles so split: sums of their pieces
     bool fork = false;                  // run pre-additions + group 2 on a second stream
+    // Pre-additions beside the product launch: one limb, one level.  The
+    // pre-addition kernel runs on a second stream (PRE_SIGNAL_BLOCKS workgroups,
+    // each raising the counter at workspace byte wait_off when done) while the
+    // single product launch runs the tiles that read only A first; its tiles
+    // that read S1..S4 wait for the counter.
+    bool overlap_pre = false;
+    int pre_blocks = 0;                 // workgroups of the pre-addition kernel (the counter's target)
+    int64_t wait_off = 0;
     int64_t ws_bytes = 0;
     int64_t products_macs = 0;         // multiply-accumulates of the products (per limb product)
     std::vector<int64_t> a_off, c_off; // packed batch layout (elements)
@@ -90,6 +98,8 @@ struct Plan {
     int64_t off_gemm_r = 0, off_sched_r = 0, off_h2m = 0, off_wpre = 0, off_wpost = 0, off_tail = 0;
     std::vector<int64_t> off_pre, off_post;
 };
+
+constexpr int PRE_SIGNAL_BLOCKS = 256;
 
 // Validates and plans one call.  status != FFA_OK means the call must fail
 // with that status before launching anything.

@@ -530,6 +530,7 @@ def test_full_size_p251_sampled_and_freivalds(algo):
     kw = dict(algo=1) if algo == "classical" else dict()
     C = ffa.syrk_modp(dA, p, **kw)
     torch.cuda.synchronize()
+    ffa.device_status(0)
     Ch = C.cpu().numpy().astype(np.int64)
     Ares = np.mod(A8.astype(np.int64), p)
     rng = np.random.default_rng(5)
@@ -596,3 +597,26 @@ def test_strided_a_and_c(case):
     low = np.tril(np.ones((n, n), dtype=bool))
     assert np.array_equal(g[:, :n][low], exp[low])
     assert (g[:, :n][~low] == sent).all() and (g[:, n:] == sent).all()
+
+
+# ------------------------------------------------------------------ pre-additions beside the products
+
+@pytest.mark.parametrize("shape", [(1000, 900), (257, 300), (2048, 1536)])
+@pytest.mark.parametrize("p", [251, 241])
+def test_preadditions_beside_the_product_launch(shape, p):
+    """One limb, one level, streams AUTO: the pre-addition kernel runs on the context's
+    second stream beside the single product launch, whose tiles that read S1..S4 wait for
+    it.  Same bits as the serial plan and as the oracle; no wait gave up."""
+    ffa = _ffa()
+    n, k = shape
+    d = ffa.plan_describe(n, k, p, dA=ffa.I8_CENTRED, dC=ffa.U8, opts=ffa.make_opts(levels=1))[1]
+    assert d["overlap_pre"] == 1 and d["levels"] == 1
+    d1 = ffa.plan_describe(n, k, p, dA=ffa.I8_CENTRED, dC=ffa.U8,
+                           opts=ffa.make_opts(levels=1, streams=ffa.STREAMS_ONE))[1]
+    assert d1["overlap_pre"] == 0
+    A = si.uniform_residues(n, k, p, 900 + n + p)
+    for _ in range(3):  # repeated calls reuse the counter and the workspace
+        got = check_syrk(A, p, torch.int8, torch.uint8, levels=1)
+    serial = check_syrk(A, p, torch.int8, torch.uint8, levels=1, streams=ffa.STREAMS_ONE)
+    assert np.array_equal(np.tril(got), np.tril(serial))
+    ffa.device_status(0)

@@ -411,3 +411,51 @@ def test_batch_run_checks_its_packed_buffers():
     b.handle = None
     with pytest.raises(ValueError, match="closed"):
         b._packed(ok_a, b.dA, b.a_total, "A_packed", False)
+
+
+def test_short_centred_reduction_is_exact_for_every_small_prime():
+    # The kernels' reduction of short sums (|v| <= 3 (p-1)/2) for p < 2^8:
+    # q = (v * round(2^20 / p) + 2^19) >> 20 (arithmetic shift), v - q p, must give the
+    # centred residue for every odd prime p < 256 and every v in range.
+    import numpy as np
+    for p in range(3, 256, 2):
+        if not oracle.is_prime(p):
+            continue
+        half = (p - 1) // 2
+        r20 = ((1 << 20) + p // 2) // p
+        v = np.arange(-3 * half, 3 * half + 1, dtype=np.int64)
+        q = (v * r20 + (1 << 19)) >> 20
+        got = v - q * p
+        want = np.mod(v + half, p) - half
+        assert np.array_equal(got, want), p
+        assert (np.abs(v * r20) < 2 ** 31).all() and r20 < 2 ** 23
+
+
+def _fast_mod_emulated(x, p):
+    """The product kernel's six-operation reduction, emulated exactly on the host:
+    t = fp32 fma(fp32(x), fp32(1/p), 1.5 * 2^23) (the product of two fp32 values and the
+    sum are exact in fp64, then rounded once to fp32), q = bits(t) - bits(1.5 * 2^23),
+    r = x - q p, canonical = min(r, r + p) as unsigned 32-bit values."""
+    import numpy as np
+    xf = x.astype(np.float32).astype(np.float64)
+    inv = np.float64(np.float32(1.0 / p))
+    t = (xf * inv + 12582912.0).astype(np.float32)
+    q = t.view(np.int32).astype(np.int64) - int(np.float32(12582912.0).view(np.int32))
+    r = x - q * p
+    ru = np.mod(r, 2 ** 32)
+    rp = np.mod(r + p, 2 ** 32)
+    return np.minimum(ru, rp)
+
+
+def test_fast_epilogue_reduction_is_exact_below_its_bound():
+    # the kernel takes it when K ((p-1)/2)^2 < 2^22 p, i.e. every accumulator |x| < 2^22 p
+    import numpy as np
+    rng = np.random.default_rng(0)
+    for p in [3, 5, 7, 11, 13, 61, 127, 131, 241, 251]:
+        lim = (1 << 22) * p - 1
+        x = np.concatenate([rng.integers(-lim, lim + 1, 200000),
+                            np.array([-lim, lim, 0, 1, -1, p, -p, p - 1, -(p - 1)])])
+        mult = rng.integers(-(lim // p), lim // p + 1, 100000) * p
+        x = np.concatenate([x, mult - 1, mult, mult + 1]).astype(np.int64)
+        x = x[np.abs(x) <= lim]
+        assert np.array_equal(_fast_mod_emulated(x, p), np.mod(x, p)), p
