@@ -142,22 +142,22 @@ def make_input(w, torch):
 
 
 def timed_steps(ffa, torch, w, A, Ai, C, Ci, plans, steps, warmup, blocks=10):
-    """Times exactly `steps` calls of each plan (recursive, then classical if given).
+    """Times each plan (recursive, then classical if given) three ways.
 
-    The steps of each plan are cut into `blocks` blocks (at least one call each)
-    and the plans run in alternating blocks, so that clock and thermal drift
-    during the run affects both alike; every block is bracketed by a device
-    synchronisation and HIP events on the current stream.  The duration of the
-    product phase (the grouped product launch and its last-round sums) comes
-    from one pair of HIP events per call that the library records around it on
-    the same stream, during these same blocks (each recorded phase costs the
-    call some microseconds, so only this one is recorded here; the other phases
-    are measured by `phase_breakdown` outside the timed region).  Nothing is
-    flushed between calls: the inputs and the workspace stay in HBM (and partly
-    in the 256 MB MALL) from one call to the next, as in a loop of calls on
+    (a) Exactly `steps` calls in one region bracketed by a device synchronisation
+        and two HIP events on the current stream: ms per step = region time / steps
+        (the headline figure).
+    (b) The same number of calls in `blocks` blocks, each bracketed the same way,
+        the plans alternating block by block: the median of the blocks' ms per call.
+    (c) `steps` calls in one region with the library's HIP events around the product
+        phase (the grouped product launch and its last-round sums) on the same
+        stream: its ms per call, for the roofline, and the region's ms per step (the
+        events themselves cost each call some microseconds, so (a) has none).
+    Nothing is flushed between calls: the inputs and the workspace stay in HBM (and
+    partly in the 256 MB MALL) from one call to the next, as in a loop of calls on
     resident data.
-    Returns per plan: (ms per step = summed block time / steps, median over the
-    blocks of the block's ms per step, ms of the product phase per call).
+    Returns per plan: (ms per step (a), median ms per call (b), product-phase ms per
+    call (c), ms per step of region (c)).
     """
     import statistics
 
@@ -166,39 +166,45 @@ def timed_steps(ffa, torch, w, A, Ai, C, Ci, plans, steps, warmup, blocks=10):
             ffa.syrk_modp(A, w["p"], C=C, opts=opts)
         else:
             ffa.herk_modp2(A, Ai, w["p"], C_re=C, C_im=Ci, opts=opts)
+
+    def region(opts, n):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(n):
+            one(opts)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
     for opts in plans:
         for _ in range(warmup):
             one(opts)
     torch.cuda.synchronize()
+    headline = [region(opts, steps) / steps for opts in plans]
     blocks = max(1, min(blocks, steps))
-    total = [0.0] * len(plans)
-    per_step = [[] for _ in plans]
-    prod_ms = [0.0] * len(plans)
     per_block = [steps // blocks + (1 if b < steps % blocks else 0) for b in range(blocks)]
+    block_ms = [[] for _ in plans]
     for nb in per_block:
         for i, opts in enumerate(plans):
-            ffa.profile_reset(0)
-            ffa.profile_enable(0, True, phases=1 << ffa.PHASE_PRODUCTS)
-            start = torch.cuda.Event(enable_timing=True)
-            stop = torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            start.record()
-            for _ in range(nb):
-                one(opts)
-            stop.record()
-            torch.cuda.synchronize()
-            ffa.profile_enable(0, False)
-            t = start.elapsed_time(stop)
-            total[i] += t
-            per_step[i].append(t / nb)
-            prod_ms[i] += ffa.profile_read(0, ffa.PHASE_PRODUCTS)[0]
-    return [(total[i] / steps, statistics.median(per_step[i]), prod_ms[i] / steps)
-            for i in range(len(plans))]
+            block_ms[i].append(region(opts, nb) / nb)
+    prod = []
+    for opts in plans:
+        ffa.profile_reset(0)
+        ffa.profile_enable(0, True, phases=1 << ffa.PHASE_PRODUCTS)
+        t = region(opts, steps)
+        ffa.profile_enable(0, False)
+        prod.append((ffa.profile_read(0, ffa.PHASE_PRODUCTS)[0] / steps, t / steps))
+    # a product tile that waited in vain for the pre-additions beside it would have
+    # made its call's result invalid: none did, or the benchmark stops here
+    ffa.device_status(0)
+    return [(headline[i], statistics.median(block_ms[i]), prod[i][0], prod[i][1]) for i in range(len(plans))]
 
 
 def phase_breakdown(ffa, torch, w, A, Ai, C, Ci, opts, calls=5):
-    """ms per call of each phase (HIP events around every phase), and launches per call
-    of the product phase, over `calls` calls outside the timed region."""
+    """ms per call of each phase (HIP events around every phase) over `calls` calls
+    outside the timed region."""
     names = ((ffa.PHASE_COND, "conditioning"), (ffa.PHASE_PRE, "preadd"),
              (ffa.PHASE_PRODUCTS, "products"), (ffa.PHASE_POST, "postadd"))
     torch.cuda.synchronize()
@@ -216,22 +222,6 @@ def phase_breakdown(ffa, torch, w, A, Ai, C, Ci, opts, calls=5):
         ms, _ = ffa.profile_read(0, ph)
         out[name] = round(ms / calls, 4)
     return out
-
-
-def unprofiled_ms(ffa, torch, w, A, Ai, C, Ci, opts, steps):
-    """ms per call of `steps` calls in one synchronised region, without the phase events."""
-    torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(steps):
-        if Ai is None:
-            ffa.syrk_modp(A, w["p"], C=C, opts=opts)
-        else:
-            ffa.herk_modp2(A, Ai, w["p"], C_re=C, C_im=Ci, opts=opts)
-    stop.record()
-    torch.cuda.synchronize()
-    return start.elapsed_time(stop) / steps
 
 
 # ---------------------------------------------------------------- result checks
@@ -654,7 +644,7 @@ def main():
             print(json.dumps(run_batch(args, w, ffa, torch)))
             return
         run_single(args, w, ffa, torch)
-    except VerifyError as e:
+    except (VerifyError, ffa.FfaError) as e:
         print(json.dumps({"error": f"result check failed: {e}", "workload": args.workload}))
         sys.exit(1)
 
@@ -685,9 +675,8 @@ def run_single(args, w, ffa, torch):
                               kernel=args.kernel)
     plans = [opts] if args.no_classical else [opts, classical]
     res = timed_steps(ffa, torch, w, A, Ai, C, Ci, plans, args.steps, args.warmup)
-    ms, ms_med, prod_ms = res[0]
+    ms, ms_med, prod_ms, ms_prof = res[0]
     value = n * n * k / (ms * 1e-3)
-    bare = [unprofiled_ms(ffa, torch, w, A, Ai, C, Ci, o, args.steps) for o in plans]
     phases = phase_breakdown(ffa, torch, w, A, Ai, C, Ci, opts)
 
     # the result of every timed plan, checked on the host after the timed region
@@ -714,7 +703,7 @@ def run_single(args, w, ffa, torch):
         "warmup": args.warmup,
         "ms_per_step": ms,
         "ms_median": ms_med,
-        "ms_per_step_unprofiled": bare[0],
+        "ms_per_step_profiled": ms_prof,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -749,12 +738,12 @@ def run_single(args, w, ffa, torch):
                            "frac": achieved / PEAK_F64_TFLOPS, "traffic": None,
                            "ops_per_step": ops, "product_phase_ms": prod_ms}
     if not args.no_classical:
-        cms, cmed, cprod = res[1]
+        cms, cmed, cprod, cprof = res[1]
         out["classical_gpu"] = {"value": n * n * k / (cms * 1e-3), "unit": "n^2k/s",
                                 "ms_per_step": cms, "ms_median": cmed, "products_ms": cprod,
-                                "ms_per_step_unprofiled": bare[1]}
+                                "ms_per_step_profiled": cprof}
         out["speedup_vs_classical"] = cms / ms
-        out["speedup_vs_classical_unprofiled"] = bare[1] / bare[0]
+        out["speedup_vs_classical_median"] = cmed / ms_med
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
         if "levels" in w:

@@ -34,6 +34,10 @@ struct ffa_ctx {
     std::map<std::string, std::unique_ptr<Plan>> cache;
     std::map<std::string, ffa_opts> tuned;  // autotuner's choice per shape and per size class
     std::map<int, bool> coresident;         // per product configuration: fits beside the pre-additions
+    // kernels of different streams may not run at the same time in this process (a
+    // launch-blocking or kernel-serializing setting, a profiler collecting counters):
+    // nothing then runs beside the product launch
+    bool serialized = false;
     // phase timing: bit q set = phase q is recorded
     int prof = 0;
     struct Pending {
@@ -236,13 +240,29 @@ void free_tables(Plan& pl)
     pl.d_blob = nullptr;
 }
 
+// Settings under which kernels of different streams do not run concurrently, so
+// that a product tile waiting for a kernel on another stream would wait in vain.
+bool env_serializes()
+{
+    auto set = [](const char* name) {
+        const char* v = getenv(name);
+        return v && *v && strcmp(v, "0") != 0 && strcmp(v, "false") != 0;
+    };
+    if (set("AMD_SERIALIZE_KERNEL") || set("HIP_LAUNCH_BLOCKING") || set("CUDA_LAUNCH_BLOCKING")) return true;
+    // rocprofv3 collecting counters or thread traces serializes the dispatches
+    if (set("ROCPROF_COUNTER_COLLECTION") || set("ROCPROF_COUNTERS") || set("ROCPROF_ADVANCED_THREAD_TRACE"))
+        return true;
+    const char* q = getenv("GPU_MAX_HW_QUEUES");
+    return q && atoi(q) == 1;
+}
+
 // Whether the signalling pre-addition kernel fits a CU beside a workgroup of the
 // plan's product kernel (gfx950: 512 VGPRs per SIMD lane, 160 KiB of LDS per CU),
 // so that it runs while the product launch holds every CU.  Measured once per
 // product configuration and context.
 bool coresident(ffa_ctx* c, const Plan& pl)
 {
-    if (pl.carrier != CAR_I8) return false;
+    if (pl.carrier != CAR_I8 || c->serialized) return false;
     auto it = c->coresident.find(pl.gemm_cfg);
     if (it != c->coresident.end()) return it->second;
     bool ok = false;
@@ -563,6 +583,7 @@ int ffa_create(ffa_ctx** out, int device, void* hip_stream)
         std::unique_ptr<ffa_ctx> owner(new ffa_ctx);
         ffa_ctx* c = owner.get();
         c->device = device;
+        c->serialized = env_serializes();
         c->stream = (hipStream_t)hip_stream;
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, device) == hipSuccess) {

@@ -573,6 +573,23 @@ __device__ __forceinline__ void store_rowv(char* base, int64_t idx, const int32_
     }
 }
 
+// v <- alpha v + beta C_old mod p on the first n of V consecutive entries of a row
+// of the caller's C (the SYRK update form of Section 7; beta = 0 does not read C).
+// alpha v and beta C_old are below 2^52 for p < 2^26, so the sum is exact in fp64.
+template <typename OT, int V>
+__device__ __forceinline__ void update_rowv(const char* base, int64_t idx, int32_t* v, int n,
+                                            const FieldParams& fp)
+{
+    const OT* src = reinterpret_cast<const OT*>(base) + idx;
+#pragma unroll
+    for (int e = 0; e < V; ++e)
+        if (e < n) {
+            double val = (double)fp.alpha * (double)v[e];
+            if (fp.beta) val += (double)fp.beta * (double)src[e];
+            v[e] = mod_canon(val, fp.p, fp.inv_p);
+        }
+}
+
 // V consecutive residues of a row, kept packed as loaded (V * sizeof(RT) bytes).
 template <typename RT, int V>
 struct RowV {
@@ -704,6 +721,14 @@ __global__ void __launch_bounds__(512) postadd(const PostaddTask* tasks, Bases b
                 c11[e] = add_mod(P1[q][e], P2[q][e], p);  // U3 = P1 + P2
                 c22[e] = add_mod(u2, p4t, p);             // U5 = U2 + phi(P4)
             }
+            if (T.upd) {
+                // the top level of an update call: alpha U + beta C as the results are stored
+                if (gi < nv) update_rowv<OT, V>(cpl[q], (int64_t)gi * ldc + gj0, c11, min(wantC, lowlen), fp);
+                if (h + gi < nv) {
+                    update_rowv<OT, V>(cpl[q], (int64_t)(h + gi) * ldc + gj0, c21, wantC, fp);
+                    update_rowv<OT, V>(cpl[q], (int64_t)(h + gi) * ldc + h + gj0, c22, min(wantH, lowlen), fp);
+                }
+            }
             if (gi < nv) store_rowv<OT, V>(cpl[q], (int64_t)gi * ldc + gj0, c11, min(wantC, lowlen));
             if (h + gi < nv) {
                 store_rowv<OT, V>(cpl[q], (int64_t)(h + gi) * ldc + gj0, c21, wantC);
@@ -722,6 +747,7 @@ __global__ void __launch_bounds__(512) postadd(const PostaddTask* tasks, Bases b
                 const int32_t u1 = conjv(q, u1s[q][tc + e][tr]);
                 c21[e] = add_mod(add_mod(u1, Q4[q][e], p), Q3[q][e], p);
             }
+            if (T.upd) update_rowv<OT, V>(cpl[q], (int64_t)(h + mi) * ldc + mj0, c21, want, fp);
             store_rowv<OT, V>(cpl[q], (int64_t)(h + mi) * ldc + mj0, c21, want);
         }
     }

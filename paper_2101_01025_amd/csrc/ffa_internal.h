@@ -118,12 +118,16 @@ struct PreaddTask {
 };
 
 // Post-additions of one node: products P1..P5 (h x h residues) into the
-// node's C (2h x 2h), rows/columns >= nvalid are not written.
+// node's C (2h x 2h), rows/columns >= nvalid are not written.  At the top of an
+// update call (C <- alpha Low(A A^T) + beta Low(C), Section 7) the update is
+// applied as the results are stored (upd = 1).
 struct PostaddTask {
     ResRef p[5];
     ResRef c;
     int32_t h;
     int32_t nvalid;
+    int32_t upd;   // 1: c is the caller's C of an update call, which receives alpha U + beta C
+    int32_t pad_;
 };
 
 // One product C = X * phi(Z) restricted to tiles; syrk: X == Z, only the

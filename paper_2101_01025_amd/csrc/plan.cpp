@@ -243,6 +243,7 @@ struct Builder {
         PostaddTask qt{};
         for (int j = 0; j < 5; ++j) qt.p[j] = P[j];
         qt.c = c;
+        qt.upd = level == 0 && pl.fold_update ? 1 : 0;
         qt.h = (int32_t)h;
         qt.nvalid = (int32_t)nvalid;
         pl.post[level].push_back(qt);
@@ -632,6 +633,12 @@ ResRef root_output(Plan& pl, Builder& B, const Problem& pr)
     c.ld = (int32_t)pr.ldc;
     c.dt = pr.dC;
     if (pr.alpha == 1 && pr.beta == 0) return c;
+    // with recursion the top-level post-additions apply the update as they store
+    // (Section 7's schedule for alpha A A^T + beta C needs no pass of its own)
+    if (pl.levels > 0) {
+        pl.fold_update = true;
+        return c;
+    }
     const ResRef x = B.new_res(pr.n);
     UpdateTask u{};
     u.x = x;

@@ -53,7 +53,8 @@ struct Plan {
     std::vector<WinoPreTask> wpre;
     std::vector<WinoPostTask> wpost;
     int wpre_max_h = 0, wpre_max_w = 0, wpost_max_h = 0;
-    std::vector<UpdateTask> upd;       // final C <- alpha X + beta C
+    std::vector<UpdateTask> upd;       // final C <- alpha X + beta C (no recursion)
+    bool fold_update = false;          // the level-0 post-additions apply the update (recursion)
     int upd_max_n = 0;
     std::vector<std::vector<PreaddTask>> pre;   // per level, top-down
     std::vector<std::vector<PostaddTask>> post; // per level
