@@ -18,7 +18,8 @@ OBJDIR = os.path.join(CSRC, "_build")
 LIB = os.path.join(HERE, "libffa.so")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["gemm_i8.hip", "gemm_f64.hip", "elementwise.hip", "noalloc.hip"]
+HIP_SOURCES = ["gemm_i8_part_a.hip", "gemm_i8_part_b.hip", "gemm_i8_part_c.hip", "gemm_i8_part_d.hip",
+               "gemm_i8.hip", "gemm_f64.hip", "elementwise.hip", "noalloc.hip"]
 CPP_SOURCES = ["field.cpp", "plan.cpp", "api.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function"]
@@ -50,7 +51,7 @@ def _compile(src):
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = HIP_SOURCES + CPP_SOURCES
-    with cf.ThreadPoolExecutor(max_workers=min(6, len(srcs))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -1,0 +1,43 @@
+// Configurations of the INT8 product kernel: id -> (limbs, complex, tile edge,
+// wave grid, k-tile bytes, prefetch depth; depth 0 = direct global-to-LDS loads).
+// Accumulator registers per lane: NROLE * NACC * (BT/WGM/32) * (BT/WGN/32) * 16.
+// Configurations whose accumulators do not fit the register file without
+// spilling are left out; ids are not renumbered.
+// Each list holds the configurations that one translation unit instantiates, so
+// that the units compile in parallel.
+#pragma once
+
+#define FFA_I8_CONFIGS_A(X)               \
+    X(24, 1, 0, 256, 2, 4, 128, 0)        \
+    X(2, 1, 0, 128, 2, 2, 128, 2)         \
+    X(1, 1, 0, 256, 2, 4, 64, 2)          \
+    X(14, 1, 0, 64, 2, 2, 128, 2)
+
+#define FFA_I8_CONFIGS_B(X)               \
+    X(16, 2, 0, 128, 2, 4, 128, 2)        \
+    X(15, 2, 0, 128, 2, 4, 128, 1)        \
+    X(26, 2, 0, 128, 2, 4, 128, 0)        \
+    X(9, 2, 0, 128, 2, 2, 128, 1)
+
+#define FFA_I8_CONFIGS_C(X)               \
+    X(10, 1, 0, 256, 2, 4, 128, 2)        \
+    X(11, 1, 0, 256, 2, 4, 64, 3)         \
+    X(12, 1, 0, 256, 4, 2, 64, 2)         \
+    X(25, 2, 0, 128, 2, 2, 128, 0)        \
+    X(13, 2, 0, 64, 2, 2, 128, 2)
+
+#define FFA_I8_CONFIGS_D(X)               \
+    X(4, 1, 1, 128, 2, 2, 128, 2)         \
+    X(8, 2, 1, 64, 2, 2, 128, 2)          \
+    X(17, 2, 0, 64, 2, 2, 64, 2)          \
+    X(18, 2, 0, 128, 2, 4, 64, 4)         \
+    X(21, 2, 0, 64, 2, 2, 64, 4)
+
+#define FFA_I8_CONFIGS(X) \
+    FFA_I8_CONFIGS_A(X)   \
+    FFA_I8_CONFIGS_B(X)   \
+    FFA_I8_CONFIGS_C(X)   \
+    FFA_I8_CONFIGS_D(X)
+
+// Returned by a unit's entry points for a configuration that the unit does not hold.
+#define FFA_I8_NOT_HERE (-100000)
