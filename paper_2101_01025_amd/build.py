@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libffa.so")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["gemm_i8_part_a.hip", "gemm_i8_part_b.hip", "gemm_i8_part_c.hip", "gemm_i8_part_d.hip",
-               "gemm_i8.hip", "gemm_f64.hip", "elementwise.hip", "noalloc.hip"]
+               "gemm_i8_part_e.hip", "gemm_i8.hip", "gemm_f64.hip", "elementwise.hip", "noalloc.hip"]
 CPP_SOURCES = ["field.cpp", "plan.cpp", "api.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function"]

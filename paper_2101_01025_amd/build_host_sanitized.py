@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(CSRC, "_build")
 HOST_SOURCES = ["field.cpp", "plan.cpp", "api.cpp"]
 DEVICE_OBJECTS = ["gemm_i8_part_a.o", "gemm_i8_part_b.o", "gemm_i8_part_c.o", "gemm_i8_part_d.o",
-                  "gemm_i8.o", "gemm_f64.o", "elementwise.o", "noalloc.o"]
+                  "gemm_i8_part_e.o", "gemm_i8.o", "gemm_f64.o", "elementwise.o", "noalloc.o"]
 ROCM = "/opt/rocm"
 SAN = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined"]
 

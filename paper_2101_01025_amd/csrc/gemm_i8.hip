@@ -16,6 +16,7 @@ FFA_I8_DECLARE_PART(a)
 FFA_I8_DECLARE_PART(b)
 FFA_I8_DECLARE_PART(c)
 FFA_I8_DECLARE_PART(d)
+FFA_I8_DECLARE_PART(e)
 #undef FFA_I8_DECLARE_PART
 
 struct CfgInfo {
@@ -24,9 +25,10 @@ struct CfgInfo {
 
 static CfgInfo cfg_info(int id)
 {
-#define FFA_INFO(ID, NL, CP, BT, WM, WN, KT, PF) \
+#define FFA_INFO(ID, NL, CP, BT, WM, WN, KT, PF, MS) \
     if (id == ID)                                                                              \
-        return CfgInfo{NL, CP, BT, KT, WM * WN * 64, 2 * ((CP ? 2 : 1) * NL + NL) * BT * KT, \
+        return CfgInfo{NL, CP, BT, KT, WM * WN * 64,                                        \
+                       (PF < 0 ? -PF : 2) * ((CP ? 2 : 1) * NL + NL) * BT * KT,           \
                        NL == 2 && !CP && PF > 0};
     FFA_I8_CONFIGS(FFA_INFO)
 #undef FFA_INFO
@@ -49,10 +51,11 @@ int gemm_i8_default_config(int nl, int cplx, int64_t max_dim)
     // 8 waves, two k-tiles in flight: 6.85 ms against 7.11 ms for configuration 15 (one
     // k-tile in flight) for the products at n = k = 16384
     if (nl == 2) return 16;
-    // 8 waves of 128x64, operands loaded straight into LDS: 1.75 ms against 1.85 ms for
-    // configuration 10 (the same tiles through a register ring) for the products at
-    // n = k = 16384, p = 251
-    return max_dim >= 2048 ? 24 : 2;
+    // 8 waves of 128x64, operands loaded straight into LDS, 16x16x64 MFMAs: 1.78 ms
+    // against 1.86 ms for configuration 24 (the same with 32x32x32 MFMAs) and 1.84 ms
+    // for configuration 29 (loads spread over the k-steps) per call at n = k = 16384,
+    // p = 251, no recursion (medians of alternating blocks)
+    return max_dim >= 2048 ? 34 : 2;
 }
 
 int gemm_i8_config_regs(int cfg, int* vgprs, int* threads, int* lds)
@@ -63,6 +66,7 @@ int gemm_i8_config_regs(int cfg, int* vgprs, int* threads, int* lds)
     if (r == FFA_I8_NOT_HERE) r = gemm_i8_regs_b(cfg, vgprs);
     if (r == FFA_I8_NOT_HERE) r = gemm_i8_regs_c(cfg, vgprs);
     if (r == FFA_I8_NOT_HERE) r = gemm_i8_regs_d(cfg, vgprs);
+    if (r == FFA_I8_NOT_HERE) r = gemm_i8_regs_e(cfg, vgprs);
     if (r == FFA_I8_NOT_HERE) return (int)hipErrorInvalidValue;
     if (r == 0) {
         *threads = ci.nthreads;
@@ -80,6 +84,7 @@ int launch_gemm_i8(int cfg, int src, const GemmTask* d_tasks, const TileEnt* d_s
     if (r == FFA_I8_NOT_HERE) r = gemm_i8_launch_b(cfg, src, d_tasks, d_sched, nblocks, b, fp, s);
     if (r == FFA_I8_NOT_HERE) r = gemm_i8_launch_c(cfg, src, d_tasks, d_sched, nblocks, b, fp, s);
     if (r == FFA_I8_NOT_HERE) r = gemm_i8_launch_d(cfg, src, d_tasks, d_sched, nblocks, b, fp, s);
+    if (r == FFA_I8_NOT_HERE) r = gemm_i8_launch_e(cfg, src, d_tasks, d_sched, nblocks, b, fp, s);
     return r == FFA_I8_NOT_HERE ? (int)hipErrorInvalidValue : r;
 }
 

@@ -1,4 +1,5 @@
-// Grouped product kernel on INT8 MFMA (gfx950 v_mfma_i32_32x32x32_i8).
+// Grouped product kernel on INT8 MFMA (gfx950 v_mfma_i32_32x32x32_i8 or
+// v_mfma_i32_16x16x64_i8).
 //
 // Computes, for every task of a table, C = X * phi(Z) mod p on square tiles:
 // the general products P3 = A22 phi(S4), P4 = S1 phi(S2) of every recursion
@@ -132,6 +133,35 @@ __device__ __forceinline__ void lds_load16(__amdgpu_buffer_rsrc_t rs, char* dst,
                                              0);
 }
 
+// One INT8 MFMA of shape MS: 32x32 blocks with 32 bytes of K, or 16x16 blocks
+// with 64 bytes of K (16 bytes per lane either way).  A block's result in a lane:
+// MS = 32: row lane % 32, columns 8 (v / 4) + 4 (lane / 32) + v % 4 of register v;
+// MS = 16: row lane % 16, columns 4 (lane / 16) + v.
+template <int MS, typename ACC>
+__device__ __forceinline__ ACC mfma_i8(v4i b, v4i a, ACC c)
+{
+    if constexpr (MS == 32) return __builtin_amdgcn_mfma_i32_32x32x32_i8(b, a, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_i32_16x16x64_i8(b, a, c, 0, 0, 0);
+}
+
+// s_waitcnt vmcnt(N) alone (expcnt and lgkmcnt at their maxima: not waited for).
+template <int N>
+__device__ __forceinline__ void wait_vm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt field");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// A workgroup barrier without a memory fence: the waits that it needs are explicit
+// (a fence would also wait for the operand loads that are meant to stay in flight).
+// Nothing is moved across it, by the compiler or its scheduler.
+__device__ __forceinline__ void phase_barrier()
+{
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_barrier" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 // acc + the sum of the 8 uint16 values of a chunk.
@@ -147,32 +177,45 @@ __device__ __forceinline__ uint32_t sum_u16x8(v4i v, uint32_t acc)
     return acc;
 }
 
-template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC>
+template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC, int MS>
 __global__ void __launch_bounds__(WGM* WGN * 64)
     gemm_i8(Bases bases, const GemmTask* __restrict__ tasks, const TileEnt* __restrict__ sched,
             FieldParams fp)
 {
     constexpr bool RAW = SRC == SRC_RAW_U16;
     static_assert(!RAW || (NL == 2 && !CPLX), "raw uint16 operands feed two limbs of a real field");
-    // PF = 0: operands go from global memory straight into LDS (no register ring)
-    constexpr bool DMA = PF == 0;
+    // PF = 0: operands go from global memory straight into LDS (no register ring),
+    // two buffers, the next k-tile's loads issued at the start of an iteration.
+    // PF < 0: the same loads into -PF buffers, k-tile st - PF - 1 loaded while
+    // k-tile st is multiplied, its loads spread over the k-steps.
+    constexpr bool DMA = PF <= 0;
+    constexpr bool RING = PF < 0;
+    constexpr int NBUFS = RING ? -PF : 2;
     constexpr int PFR = DMA ? 1 : PF;
     static_assert(!(DMA && RAW), "raw operands are split into limbs in registers");
     constexpr int NT = WGM * WGN * 64;
+    constexpr int NTL = NT;  // threads that load operands
+    static_assert(!RING || NBUFS >= 2, "ring: at least two buffers");
     constexpr int NROLE = CPLX ? 2 : 1;
     constexpr int NSEG = CPLX ? 2 : 1;
     constexpr int NA = NROLE * NL;  // A sub-tiles per stage
     constexpr int NB = NL;          // B sub-tiles per stage
     constexpr int WM = BT / WGM, WN = BT / WGN;
-    constexpr int FM = WM / 32, FN = WN / 32;
+    // MFMA shape: MS = 32 (v_mfma_i32_32x32x32_i8, a k-step of 32 bytes) or 16
+    // (v_mfma_i32_16x16x64_i8, a k-step of 64 bytes); FM x FN blocks of MS x MS per wave
+    static_assert(MS == 32 || MS == 16, "MFMA shape");
+    constexpr int FM = WM / MS, FN = WN / MS;
+    constexpr int NREG = MS == 32 ? 16 : 4;  // accumulator registers per block
+    constexpr int SPK = 64 / MS;             // 16-byte segments of a row per k-step
+    static_assert(KT % (16 * SPK) == 0, "k-tile of whole k-steps");
     constexpr int NACC = NL == 1 ? 1 : 3;
     constexpr int TILE = BT * KT;
     constexpr int STAGE = (NA + NB) * TILE;
     constexpr int SPR = KT / 16;  // 16-byte segments per carrier row
     constexpr int RPR = KT / 8;   // 16-byte raw chunks (8 residues) per row
-    constexpr int ACH = NA * TILE / 16 / NT;
-    constexpr int BCH = NB * TILE / 16 / NT;
-    static_assert(NA * TILE % (16 * NT) == 0 && NB * TILE % (16 * NT) == 0, "chunking");
+    constexpr int ACH = NA * TILE / 16 / NTL;
+    constexpr int BCH = NB * TILE / 16 / NTL;
+    static_assert(NA * TILE % (16 * NTL) == 0 && NB * TILE % (16 * NTL) == 0, "chunking");
     static_assert(FM >= 1 && FN >= 1, "wave tile");
 
     extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -211,7 +254,7 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     for (int i = 0; i < (RAW ? BCH : 1); ++i) bsum[i] = 0;
 #pragma unroll
     for (int i = 0; i < ACH; ++i) {
-        const int c = tid + i * NT;
+        const int c = tid + i * NTL;
         if (RAW) {
             // (row, chunk) -> hi limb at sub-tile 0, lo limb at sub-tile 1, 8 bytes each
             const int r = c / RPR, s = c % RPR;
@@ -229,7 +272,7 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     }
 #pragma unroll
     for (int i = 0; i < BCH; ++i) {
-        const int c = tid + i * NT;
+        const int c = tid + i * NTL;
         if (RAW) {
             const int r = c / RPR, s = c % RPR;
             boff[i] = min(r, rows_b - 1) * T.z.ld + s * 16;
@@ -277,19 +320,27 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
         const int kc = st - seg * nkc;
         const int oa = seg * seg_a + kc * KT, ob = seg * seg_b + kc * KT;
         if (DMA) {
-            // chunk c = tid + i * NT lands at LDS byte 16 c of the stage: the wave's 64
+            // chunk c = tid + i * NTL lands at LDS byte 16 c of the stage: the wave's 64
             // lanes fill 1 KiB from the wave-uniform base given here
-            char* base = lds + (st & 1) * STAGE + wave * 1024;
+            char* base = lds + (st % NBUFS) * STAGE + wave * 1024;
 #pragma unroll
-            for (int i = 0; i < ACH; ++i) lds_load16(rsa, base + i * NT * 16, aoff[i], oa);
+            for (int i = 0; i < ACH; ++i) lds_load16(rsa, base + i * NTL * 16, aoff[i], oa);
 #pragma unroll
-            for (int i = 0; i < BCH; ++i) lds_load16(rsb, base + NA * TILE + i * NT * 16, boff[i], ob);
+            for (int i = 0; i < BCH; ++i) lds_load16(rsb, base + NA * TILE + i * NTL * 16, boff[i], ob);
             return;
         }
 #pragma unroll
         for (int i = 0; i < ACH; ++i) a[i] = __builtin_amdgcn_raw_buffer_load_b128(rsa, aoff[i], oa, 0);
 #pragma unroll
         for (int i = 0; i < BCH; ++i) b[i] = __builtin_amdgcn_raw_buffer_load_b128(rsb, boff[i], ob, 0);
+    };
+    // one direct load of stage st: chunk q of A (q < ACH) or q - ACH of B
+    auto gload_one = [&](int st, int q) {
+        const int seg = st >= nkc ? 1 : 0;
+        const int kc = st - seg * nkc;
+        char* base = lds + (st % NBUFS) * STAGE + wave * 1024;
+        if (q < ACH) lds_load16(rsa, base + q * NTL * 16, aoff[q], seg * seg_a + kc * KT);
+        else lds_load16(rsb, base + NA * TILE + (q - ACH) * NTL * 16, boff[q - ACH], seg * seg_b + kc * KT);
     };
     auto sstore = [&](int buf, const v4i* a, const v4i* b) {
         char* base = lds + buf * STAGE;
@@ -318,7 +369,8 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
         for (int i = 0; i < BCH; ++i) *reinterpret_cast<v4i*>(base + blds[i]) = b[i];
     };
 
-    v16i acc[NROLE][NACC][FM][FN];
+    using acc_t = std::conditional_t<MS == 32, v16i, v4i>;
+    acc_t acc[NROLE][NACC][FM][FN];
 #pragma unroll
     for (int r = 0; r < NROLE; ++r)
 #pragma unroll
@@ -328,23 +380,24 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
 #pragma unroll
                 for (int n = 0; n < FN; ++n)
 #pragma unroll
-                    for (int v = 0; v < 16; ++v) acc[r][a][m][n][v] = 0;
+                    for (int v = 0; v < NREG; ++v) acc[r][a][m][n][v] = 0;
 
-    const int lrow = lane & 31, lseg = lane >> 5;
-    // fragment reads of k-step ks (32 bytes of K) from an LDS stage
+    // lane -> row lane % MS of a block, 16-byte segment lane / MS of the k-step
+    const int lrow = lane % MS, lseg = lane / MS;
+    // fragment reads of k-step ks (16 SPK bytes of K) from an LDS stage
     auto load_frags = [&](const char* base, int ks, v4i (*af)[FM], v4i (*bf)[FN]) {
 #pragma unroll
         for (int a = 0; a < NA; ++a)
 #pragma unroll
             for (int m = 0; m < FM; ++m)
                 af[a][m] = *reinterpret_cast<const v4i*>(
-                    base + a * TILE + swz<KT>(wm0 + m * 32 + lrow, ks * 2 + lseg));
+                    base + a * TILE + swz<KT>(wm0 + m * MS + lrow, ks * SPK + lseg));
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int n = 0; n < FN; ++n)
                 bf[b][n] = *reinterpret_cast<const v4i*>(
-                    base + (NA + b) * TILE + swz<KT>(wn0 + n * 32 + lrow, ks * 2 + lseg));
+                    base + (NA + b) * TILE + swz<KT>(wn0 + n * MS + lrow, ks * SPK + lseg));
     };
     auto mfmas = [&](v4i (*af)[FM], v4i (*bf)[FN]) {
         if (NL == 1) {
@@ -354,8 +407,7 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
                 for (int m = 0; m < FM; ++m)
 #pragma unroll
                     for (int n = 0; n < FN; ++n)
-                        acc[r][0][m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                            bf[0][n], af[r][m], acc[r][0][m][n], 0, 0, 0);
+                        acc[r][0][m][n] = mfma_i8<MS>(bf[0][n], af[r][m], acc[r][0][m][n]);
         } else {
             // limb products (hi,hi) -> 0, (hi,lo) and (lo,hi) -> 1, (lo,lo) -> 2, ordered
             // so that consecutive MFMAs do not share an accumulator
@@ -369,21 +421,20 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
                     for (int m = 0; m < FM; ++m)
 #pragma unroll
                         for (int n = 0; n < FN; ++n)
-                            acc[r][ai][m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                                bf[lb][n], af[r * NL + la][m], acc[r][ai][m][n], 0, 0, 0);
+                            acc[r][ai][m][n] = mfma_i8<MS>(bf[lb][n], af[r * NL + la][m], acc[r][ai][m][n]);
             }
         }
     };
     // the fragments of k-step ks + 1 are read while the MFMAs of k-step ks run;
-    // hook() runs after the MFMAs of k-step HK are issued
-    constexpr int NKS = KT / 32;
+    // hook(ks) runs after the MFMAs of k-step ks are issued
+    constexpr int NKS = KT / (16 * SPK);
     // Where stage st + 1 is written to LDS: before compute(st) when it was loaded at
     // least one iteration earlier (PF >= 2), else halfway through compute(st) (its
     // loads are issued at the start of the iteration).  Measured against writing it
     // after compute(st): 1.86 vs 1.93 ms (one limb, 256-tiles, PF = 2) and 7.11 vs
     // 7.26 ms (two limbs, PF = 1) for the products at n = k = 16384.
     constexpr int SPOS = PF >= 2 ? 2 : 1;
-    constexpr int HK = SPOS == 1 && !DMA ? NKS / 2 - 1 : -1;
+    constexpr int HK = SPOS == 1 && !DMA ? (NKS >= 2 ? NKS / 2 - 1 : 0) : -1;
     // The compiler's MFMA / LDS-read interleaving strategy 0 for the two-limb products
     // read from carrier planes through registers (6.40 vs 6.82 ms of products at
     // n = k = 16384).  One limb (its 128 accumulator registers) and raw operands
@@ -398,7 +449,7 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
         for (int ks = 0; ks < NKS; ++ks) {
             if (ks + 1 < NKS) load_frags(base, ks + 1, af[(ks + 1) & 1], bf[(ks + 1) & 1]);
             mfmas(af[ks & 1], bf[ks & 1]);
-            if (ks == HK) hook();
+            hook(ks);
         }
         if (IGLP) __builtin_amdgcn_iglp_opt(0);
     };
@@ -409,12 +460,41 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     // Direct loads: stage st + 1 is loaded into that buffer while compute(st) runs;
     // the barrier ending iteration st waits for the loads (vmcnt) before any wave
     // reads the stage.
-    if (DMA) {
+    if (RING) {
+        // k-tiles 0 .. NBUFS - 2 are loaded before the loop; during iteration st the
+        // loads of k-tile st + NBUFS - 1 (into the buffer of k-tile st - 1, released by
+        // the barrier that ended iteration st - 1) follow the MFMAs of the k-steps, a
+        // few after each; the iteration ends with a wait for k-tile st + 1 (the loads
+        // issued after it stay in flight) and a barrier.
+        constexpr int LPB = ACH + BCH;
+        // with two buffers the loads issued in an iteration are waited for at its end:
+        // they follow the first half of the k-steps only
+        constexpr int NKW = NBUFS == 2 ? (NKS + 1) / 2 : NKS;
+        constexpr int LPK = (LPB + NKW - 1) / NKW;  // loads after each of the first NKW k-steps
+        for (int u = 0; u < min(NBUFS - 1, nst); ++u) gload(u, ra[0], rb[0]);
+        if (nst - 1 >= NBUFS - 2) wait_vm<LPB * (NBUFS - 2)>();
+        else wait_vm<0>();
+        phase_barrier();
+        for (int st = 0; st < nst; ++st) {
+            const int ld = st + NBUFS - 1;
+            compute(st % NBUFS, [&](int ks) {
+                if (ld < nst) {
+#pragma unroll
+                    for (int q = ks * LPK; q < min(LPB, (ks + 1) * LPK); ++q) gload_one(ld, q);  // none past NKW
+                }
+            });
+            if (st + 1 < nst) {
+                if (nst - 2 - st >= NBUFS - 2) wait_vm<LPB * (NBUFS - 2)>();
+                else wait_vm<0>();
+            }
+            phase_barrier();
+        }
+    } else if (DMA) {
         if (nst > 0) gload(0, ra[0], rb[0]);
         __syncthreads();
         for (int st = 0; st < nst; ++st) {
             if (st + 1 < nst) gload(st + 1, ra[0], rb[0]);
-            compute(st & 1, [] {});
+            compute(st & 1, [](int) {});
             __syncthreads();
         }
     }
@@ -434,7 +514,9 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
                 // register slot u held stage st (already in LDS): refill it with stage st + PF
                 if (SPOS == 2) next();
                 if (st + PFR < nst) gload(st + PFR, ra[u], rb[u]);
-                compute(st & 1, next);
+                compute(st & 1, [&](int ks) {
+                    if (ks == HK) next();
+                });
                 __syncthreads();
             }
         }
@@ -444,11 +526,11 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     // stage buffers are free after the last barrier of the loop).  The RPR
     // consecutive threads that loaded one row's chunks reduce across lanes.
     constexpr int RSUM_BYTES = RAW ? 2 * BT * 4 : 0;  // at the end of LDS, clear of the staging below
-    const uint32_t* rsum_a = reinterpret_cast<const uint32_t*>(lds + 2 * STAGE - RSUM_BYTES);
+    const uint32_t* rsum_a = reinterpret_cast<const uint32_t*>(lds + NBUFS * STAGE - RSUM_BYTES);
     const uint32_t* rsum_b = rsum_a + BT;
     if (RAW) {
         static_assert(RPR <= 64 && NT % RPR == 0, "row chunks within a wave");
-        uint32_t* rs = reinterpret_cast<uint32_t*>(lds + 2 * STAGE - RSUM_BYTES);
+        uint32_t* rs = reinterpret_cast<uint32_t*>(lds + NBUFS * STAGE - RSUM_BYTES);
 #pragma unroll
         for (int i = 0; i < ACH; ++i) {
             uint32_t v = asum[i];
@@ -486,6 +568,11 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     // 2^22 p in magnitude (K ((p-1)/2)^2 below it: the planner's products up to
     // K = 67000 at p = 251), else the exact 24-bit folding
     const bool fast = NL == 1 && (int64_t)K * fp.half * fp.half < ((int64_t)p << 22);
+    // tile row and column of accumulator register v of block (m, n) in this lane
+    auto row_of = [&](int m) { return wm0 + m * MS + lane % MS; };
+    auto col_of = [&](int n, int v) {
+        return MS == 32 ? wn0 + n * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3) : wn0 + n * 16 + 4 * (lane >> 4) + v;
+    };
     const float inv_p32 = (float)fp.inv_p;
     auto residue_in = [&](auto fast_tag, int r, int m, int n, int v) __attribute__((always_inline)) -> int32_t {
         if (NL == 1) {
@@ -495,8 +582,8 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
         double val = 65536.0 * (double)acc[r][0][m][n][v] + 256.0 * (double)acc[r][NACC - 2][m][n][v] +
                      (double)acc[r][NACC - 1][m][n][v];
         if (RAW) {
-            const int li = wm0 + m * 32 + (lane & 31);
-            const int lj = wn0 + n * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            const int li = row_of(m);
+            const int lj = col_of(n, v);
             val += RAW_D * ((double)rsum_a[li] + (double)rsum_b[lj]) - raw_kdd;
         }
         return mod_canon(val, p, fp.inv_p);
@@ -515,7 +602,7 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
         constexpr int RB = BT * ES;   // bytes per staged row
         constexpr int NSR = RB / 16;  // segments per row
         constexpr int EPS = 16 / ES;  // elements per segment
-        constexpr bool CAN_STAGE = BT * RB <= 2 * STAGE - RSUM_BYTES;
+        constexpr bool CAN_STAGE = BT * RB <= NBUFS * STAGE - RSUM_BYTES;
 #pragma unroll
         for (int r = 0; r < NROLE; ++r) {
             char* cb = (r == 0 ? bases.p[T.c.buf] + T.c.off : bases.p[T.c.buf2] + T.c.off2) +
@@ -529,12 +616,12 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
 #pragma unroll
                     for (int n = 0; n < FN; ++n)
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
+                        for (int q = 0; q < NREG / 4; ++q) {
                             OT vals[4];
 #pragma unroll
                             for (int e = 0; e < 4; ++e) vals[e] = (OT)residue(r, m, n, 4 * q + e);
-                            const int li = wm0 + m * 32 + (lane & 31);
-                            const int byte = (wn0 + n * 32 + 8 * q + 4 * (lane >> 5)) * ES;
+                            const int li = row_of(m);
+                            const int byte = col_of(n, 4 * q) * ES;
 #pragma unroll
                             for (int h = 0; h < (4 * ES + 15) / 16; ++h) {
                                 // 4 * ES bytes: part of one segment, or whole segments (ES = 8)
@@ -544,7 +631,7 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
                                 else if (ES == 2) *reinterpret_cast<uint2*>(dst) = *reinterpret_cast<const uint2*>(vals);
                                 else *reinterpret_cast<int4*>(dst) = reinterpret_cast<const int4*>(vals)[h];
                             }
-                            if (q == 3) __builtin_amdgcn_sched_barrier(0);
+                            if (q == NREG / 4 - 1) __builtin_amdgcn_sched_barrier(0);
                         }
                 __syncthreads();
                 const int ext = (int)((int64_t)(rows_c - 1) * ldc * ES + (int64_t)cols_c * ES);
@@ -577,9 +664,9 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
 #pragma unroll
                     for (int n = 0; n < FN; ++n)
 #pragma unroll
-                        for (int v = 0; v < 16; ++v) {
-                            const int li = wm0 + m * 32 + (lane & 31);
-                            const int lj = wn0 + n * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                        for (int v = 0; v < NREG; ++v) {
+                            const int li = row_of(m);
+                            const int lj = col_of(n, v);
                             const int32_t res = residue(r, m, n, v);
                             if (li < rows_c && lj < cols_c && (!syrk || row0 + li >= col0 + lj))
                                 cp[(int64_t)li * ldc + lj] = (OT)res;
@@ -604,13 +691,13 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     }
 }
 
-template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC>
+template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC, int MS>
 static int launch_cfg(const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks, const Bases& b,
                       const FieldParams& fp, hipStream_t s)
 {
     constexpr int NA = (CPLX ? 2 : 1) * NL, NB = NL;
-    constexpr int lds_bytes = 2 * (NA + NB) * BT * KT;
-    auto kern = gemm_i8<NL, CPLX, BT, WGM, WGN, KT, PF, SRC>;
+    constexpr int lds_bytes = (PF < 0 ? -PF : 2) * (NA + NB) * BT * KT;
+    auto kern = gemm_i8<NL, CPLX, BT, WGM, WGN, KT, PF, SRC, MS>;
     // the LDS limit is raised once per device the kernel runs on
     static uint64_t attr_devices = 0;
     int dev = 0;
@@ -629,15 +716,15 @@ static int launch_cfg(const GemmTask* d_tasks, const TileEnt* d_sched, int nbloc
 
 // Raw uint16 operands exist only for the two-limb real configurations that load
 // through registers.
-template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF>
+template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int MS>
 static int launch_src(int src, const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks,
                       const Bases& b, const FieldParams& fp, hipStream_t s)
 {
     if (src == SRC_CARRIER)
-        return launch_cfg<NL, CPLX, BT, WGM, WGN, KT, PF, SRC_CARRIER>(d_tasks, d_sched, nblocks, b, fp, s);
+        return launch_cfg<NL, CPLX, BT, WGM, WGN, KT, PF, SRC_CARRIER, MS>(d_tasks, d_sched, nblocks, b, fp, s);
     if constexpr (NL == 2 && CPLX == 0 && PF > 0) {
         if (src == SRC_RAW_U16)
-            return launch_cfg<NL, CPLX, BT, WGM, WGN, KT, PF, SRC_RAW_U16>(d_tasks, d_sched, nblocks, b, fp, s);
+            return launch_cfg<NL, CPLX, BT, WGM, WGN, KT, PF, SRC_RAW_U16, MS>(d_tasks, d_sched, nblocks, b, fp, s);
     }
     return (int)hipErrorInvalidValue;
 }
@@ -661,14 +748,14 @@ static int launch_src(int src, const GemmTask* d_tasks, const TileEnt* d_sched, 
         return FFA_I8_NOT_HERE;                                                                        \
     }
 
-#define FFA_I8_PART_LAUNCH(ID, NL, CP, BT, WM, WN, KT, PF) \
-    if (cfg == ID) return launch_src<NL, CP, BT, WM, WN, KT, PF>(src, d_tasks, d_sched, nblocks, b, fp, s);
+#define FFA_I8_PART_LAUNCH(ID, NL, CP, BT, WM, WN, KT, PF, MS) \
+    if (cfg == ID) return launch_src<NL, CP, BT, WM, WN, KT, PF, MS>(src, d_tasks, d_sched, nblocks, b, fp, s);
 
-#define FFA_I8_PART_REGS(ID, NL, CP, BT, WM, WN, KT, PF)                                            \
+#define FFA_I8_PART_REGS(ID, NL, CP, BT, WM, WN, KT, PF, MS)                                        \
     if (cfg == ID) {                                                                                \
         hipFuncAttributes a{};                                                                      \
         const hipError_t e =                                                                        \
-            hipFuncGetAttributes(&a, (const void*)gemm_i8<NL, CP, BT, WM, WN, KT, PF, SRC_CARRIER>); \
+            hipFuncGetAttributes(&a, (const void*)gemm_i8<NL, CP, BT, WM, WN, KT, PF, SRC_CARRIER, MS>); \
         if (e != hipSuccess) return (int)e;                                                         \
         *vgprs = a.numRegs;                                                                         \
         return 0;                                                                                   \

@@ -215,15 +215,15 @@ def _check_planned(n, k, p, dA, dC, **kw):
 
 
 @pytest.mark.parametrize("kind", ["hi", "lo", "alt"])
-@pytest.mark.parametrize("cfg", ["default", "cfg24"])
+@pytest.mark.parametrize("cfg", ["default", "cfg24", "cfg34"])
 def test_int8_p251_at_bound(kind, cfg):
     """One limb, p = 251: K = 137344 (137344 * 125^2 = 2146000000, the last k-tile
     multiple below 2^31 - 2^17) with entries +125, -125, or both alternating."""
     ffa = _ffa()
     p, n, k = 251, 256, 137344
     kw = dict(algo=ffa.ALGO_CLASSICAL)
-    if cfg == "cfg24":
-        kw["kernel"] = 25
+    if cfg != "default":
+        kw["kernel"] = int(cfg[3:]) + 1  # 256-tiles with 32x32x32 or 16x16x64 MFMAs
     d = _check_planned(n, k, p, ffa.I8_CENTRED, ffa.U8, **kw)
     assert d["max_k"] == k and d["max_abs"] == 125
     assert ffa.plan_describe(n, k + 128, p, dA=ffa.I8_CENTRED, dC=ffa.U8,

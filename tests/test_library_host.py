@@ -111,14 +111,14 @@ def test_plan_operand_source():
 
 def test_default_product_configurations():
     # one limb: 128-tiles below 2048 rows per leaf, else 8 waves of 128x64 on 256-tiles with
-    # direct loads; two limbs: 128-tiles with a register ring
-    for n, cfg in ((1024, 2), (2048, 24), (16384, 24)):
+    # direct loads and 16x16x64 MFMAs; two limbs: 128-tiles with a register ring
+    for n, cfg in ((1024, 2), (2048, 34), (16384, 34)):
         st, d = ffa.plan_describe(n, n, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
                                   opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
         assert st == 0 and d["cfg"] == cfg and d["tile"] == (128 if cfg == 2 else 256), (n, d)
     st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8)
     # centred int8 input is read in place by the pre-additions and products
-    assert st == 0 and d["levels"] == 1 and d["cfg"] == 24 and d["direct"] == 1 and d["conditioning"] == 0
+    assert st == 0 and d["levels"] == 1 and d["cfg"] == 34 and d["direct"] == 1 and d["conditioning"] == 0
     st, d = ffa.plan_describe(16384, 16384, 65521, dA=ffa.U16, dC=ffa.U16)
     assert st == 0 and d["cfg"] == 16
 
