@@ -92,7 +92,9 @@ enum { FFA_CARRIER_AUTO = 0, FFA_CARRIER_INT8 = 1, FFA_CARRIER_F64 = 2 };
  *                 where those planes would not be addressable with 32-bit offsets;
  *                 FFA_OPERANDS_PLANES: always; FFA_OPERANDS_RAW: without recursion and
  *                 with uint16 input in 16-byte aligned rows, the product kernel reads A
- *                 itself and forms the limbs on the fly (else ignored)
+ *                 itself and forms the limbs on the fly (else ignored); it reads whole
+ *                 16-byte chunks, so a single call takes this path only when k is a
+ *                 multiple of 8 (batches: any k, their packed rows are padded)
  *   streams       FFA_STREAMS_AUTO: with one level of recursion and one limb of a real
  *                 field, the pre-additions run on the context's second stream beside the
  *                 single product launch on the caller's stream, whose tiles that read only
@@ -114,12 +116,19 @@ enum { FFA_CARRIER_AUTO = 0, FFA_CARRIER_INT8 = 1, FFA_CARRIER_F64 = 2 };
  *                 smaller ones stay single products (their block additions cost more HBM
  *                 time than the multiplications they save).  0 = built-in: every general
  *                 product under FFA_GENERAL_WINOGRAD, 2048 rows under FFA_GENERAL_AUTO.
- *                 Negative: FFA_EINVAL. */
+ *                 Negative: FFA_EINVAL.
+ *   persist       the INT8 product launch of a batch (or of a single call without a
+ *                 launch beside it): FFA_PERSIST_ON runs it persistent (at most the
+ *                 workgroups that fit the device at once, each taking tiles from an
+ *                 in-kernel work queue per XCD until it is drained); FFA_PERSIST_OFF one
+ *                 workgroup per tile; FFA_PERSIST_AUTO: persistent for batches.
+ *                 Other values: FFA_EINVAL. */
 enum { FFA_LAUNCH_GRAPH = 0, FFA_LAUNCH_DIRECT = 1 };
 enum { FFA_HERK_AUTO = 0, FFA_HERK_2M = 1, FFA_HERK_4M = 2 };
 enum { FFA_GENERAL_AUTO = 0, FFA_GENERAL_CLASSICAL = 1, FFA_GENERAL_WINOGRAD = 2 };
 enum { FFA_OPERANDS_AUTO = 0, FFA_OPERANDS_PLANES = 1, FFA_OPERANDS_RAW = 2 };
 enum { FFA_STREAMS_AUTO = 0, FFA_STREAMS_ONE = 1, FFA_STREAMS_TWO = 2 };
+enum { FFA_PERSIST_AUTO = 0, FFA_PERSIST_OFF = 1, FFA_PERSIST_ON = 2 };
 typedef struct {
     int32_t algo;
     int32_t levels;
@@ -133,6 +142,7 @@ typedef struct {
     int32_t herk_base;
     int32_t general;
     int32_t wino_min;
+    int32_t persist;
 } ffa_opts;
 
 /* Context bound to a HIP device and stream (stream NULL = the null stream).

@@ -28,6 +28,7 @@ OPERANDS_AUTO, OPERANDS_PLANES, OPERANDS_RAW = 0, 1, 2
 STREAMS_AUTO, STREAMS_ONE, STREAMS_TWO = 0, 1, 2
 HERK_AUTO, HERK_2M, HERK_4M = 0, 1, 2
 GENERAL_AUTO, GENERAL_CLASSICAL, GENERAL_WINOGRAD = 0, 1, 2
+PERSIST_AUTO, PERSIST_OFF, PERSIST_ON = 0, 1, 2
 
 SYMBOLS = [
     "ffa_create", "ffa_destroy", "ffa_set_stream", "ffa_last_device_error", "ffa_status_string",
@@ -52,7 +53,8 @@ class Opts(ctypes.Structure):
                 ("carrier", ctypes.c_int32), ("check_inputs", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("launch", ctypes.c_int32), ("operands", ctypes.c_int32),
                 ("streams", ctypes.c_int32), ("herk_base", ctypes.c_int32),
-                ("general", ctypes.c_int32), ("wino_min", ctypes.c_int32)]
+                ("general", ctypes.c_int32), ("wino_min", ctypes.c_int32),
+                ("persist", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -60,9 +62,9 @@ class Opts(ctypes.Structure):
 
 def make_opts(algo=ALGO_AUTO, levels=-1, cutoff=0, carrier=CARRIER_AUTO, check_inputs=False,
               kernel=0, launch=LAUNCH_GRAPH, operands=OPERANDS_AUTO, streams=STREAMS_AUTO,
-              herk_base=0, general=0, wino_min=0):
+              herk_base=0, general=0, wino_min=0, persist=0):
     return Opts(algo, levels, cutoff, carrier, int(bool(check_inputs)), kernel, launch, operands,
-                streams, herk_base, general, wino_min)
+                streams, herk_base, general, wino_min, persist)
 
 
 _lib = None

@@ -94,11 +94,11 @@ ffa_opts default_opts()
 std::string key_of(const Problem& p)
 {
     char buf[256];
-    snprintf(buf, sizeof(buf), "%lld|%lld|%lld|%lld|%u|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%u|%u",
+    snprintf(buf, sizeof(buf), "%lld|%lld|%lld|%lld|%u|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%u|%u|%d",
              (long long)p.n, (long long)p.k, (long long)p.lda, (long long)p.ldc, p.p, p.herm, p.dA,
              p.dC, p.opts.algo, p.opts.levels, p.opts.cutoff, p.opts.carrier, p.opts.check_inputs,
              p.opts.kernel, p.opts.operands, p.opts.streams * 16 + p.opts.herk_base * 4 + p.opts.general,
-             p.opts.wino_min, p.aligned ? 1 : 0, p.trans, p.alpha, p.beta);
+             p.opts.wino_min, p.aligned ? 1 : 0, p.trans, p.alpha, p.beta, p.opts.persist);
     return buf;
 }
 
@@ -364,7 +364,18 @@ int run_plan(ffa_ctx* c, const Plan& pl, Bases b, char* ws, const char* blob)
     }
     // one event pair around the grouped product launch and its last-round sums
     hipEvent_t pev = pl.sched.empty() ? nullptr : phase_begin(c, ms, 2);
-    if ((e = products(ms, pl.off_sched, pl.sched.size()))) return dev_fail(c, e);
+    if (pl.persist && !pl.sched.empty()) {
+        // persistent: the queue counters start at zero (a fill kernel: graph-capturable)
+        if ((e = launch_zero_words(b, pl.queue_off, 8, s))) return dev_fail(c, e);
+        FieldParams fq = pl.fp;
+        fq.nent = (int32_t)pl.sched.size();
+        fq.queue_off = pl.queue_off;
+        e = launch_gemm_i8(pl.gemm_cfg, pl.gemm_src, g, (const TileEnt*)(blob + pl.off_sched), (int)pl.sched.size(),
+                           b, fq, (void*)ms);
+    } else {
+        e = products(ms, pl.off_sched, pl.sched.size());
+    }
+    if (e) return dev_fail(c, e);
     if (!pl.tail.empty()) {
         // the K-pieces of the launch's split last-round tiles, added into their places;
         // one launch per output format (the planner groups the tasks by it)
@@ -1125,7 +1136,8 @@ int ffa_batch_autotune(ffa_batch* b, const void* A_packed, void* C_packed, int r
             if (cprobe.status) continue;
             for (int kc : kernel_candidates(cprobe)) {
                 for (int64_t cut : cutoffs)
-                for (int opr : {FFA_OPERANDS_PLANES, FFA_OPERANDS_RAW}) {
+                for (int opr : {FFA_OPERANDS_PLANES, FFA_OPERANDS_RAW})
+                for (int per : {FFA_PERSIST_ON, FFA_PERSIST_OFF}) {
                     std::vector<Problem> prs = cprs;
                     for (auto& q : prs) {
                         q.opts.kernel = kc;
@@ -1133,6 +1145,7 @@ int ffa_batch_autotune(ffa_batch* b, const void* A_packed, void* C_packed, int r
                         q.opts.levels = -1;
                         q.opts.algo = cut == 0 ? FFA_ALGO_CLASSICAL : FFA_ALGO_AUTO;
                         q.opts.operands = opr;
+                        q.opts.persist = per;
                     }
                     ffa_batch trial;
                     trial.ctx = c;
@@ -1223,9 +1236,9 @@ int64_t ffa_tune_export(const ffa_ctx* c, char* buf, int64_t size)
             snprintf(rec, sizeof(rec),
                      "%s{\"n\":%lld,\"k\":%lld,\"p\":%u,\"herm\":%d,\"dA\":%d,\"dC\":%d,\"algo\":%d,"
                      "\"levels\":%d,\"cutoff\":%d,\"carrier\":%d,\"kernel\":%d,\"operands\":%d,"
-                     "\"general\":%d,\"wino_min\":%d}",
+                     "\"general\":%d,\"wino_min\":%d,\"persist\":%d}",
                      first ? "" : ",", n, k, p, herm, dA, dC, o.algo, o.levels, o.cutoff, o.carrier, o.kernel,
-                     o.operands, o.general, o.wino_min);
+                     o.operands, o.general, o.wino_min, o.persist);
             s += rec;
             first = false;
         }
@@ -1269,6 +1282,7 @@ int ffa_tune_import(ffa_ctx* c, const char* json)
             if (json_int(p, e, "operands", &v)) o.operands = (int32_t)v;
             if (json_int(p, e, "general", &v)) o.general = (int32_t)v;
             if (json_int(p, e, "wino_min", &v)) o.wino_min = (int32_t)v;
+            if (json_int(p, e, "persist", &v)) o.persist = (int32_t)v;
             record_tuned(c, n, k, (uint32_t)pp, (int)herm, (int)dA, (int)dC, o);
             ++taken;
             p = e + 1;

@@ -105,7 +105,8 @@ struct FieldParams {
     int32_t npo;          // complex carriers: 4 = planes re, im, -re and re + im (2M base case)
     int32_t st32;         // fp64 carrier held in fp32 storage (exact integers below 2^24)
     int32_t r20;          // round(2^20 / p): centred reduction of short sums for p < 2^8
-    int32_t pad_;
+    int32_t nent;         // product launch: 0, or the schedule's entries when it runs persistent
+    int64_t queue_off;    // persistent product launch: workspace offset of its 8 queue counters
 };
 
 // ---- tasks ----------------------------------------------------------------

@@ -48,9 +48,12 @@ int gemm_i8_config_valid(int cfg, int nl, int cplx)
 int gemm_i8_default_config(int nl, int cplx, int64_t max_dim)
 {
     if (cplx) return nl == 1 ? 4 : 8;
-    // 8 waves, two k-tiles in flight: 6.85 ms against 7.11 ms for configuration 15 (one
-    // k-tile in flight) for the products at n = k = 16384
-    if (nl == 2) return 16;
+    // 8 waves, direct loads into two buffers issued between the k-steps: 7.69 ms (no
+    // recursion) and 6.81 ms (one level) per call at n = k = 16384, p = 65521, against
+    // 7.82 and 7.20 ms for configuration 16 (two k-tiles in flight in registers);
+    // smaller problems keep configuration 16 (the raw uint16 operand path needs
+    // register loads)
+    if (nl == 2) return max_dim >= 2048 ? 32 : 16;
     // 8 waves of 128x64, operands loaded straight into LDS, 16x16x64 MFMAs: 1.78 ms
     // against 1.86 ms for configuration 24 (the same with 32x32x32 MFMAs) and 1.84 ms
     // for configuration 29 (loads spread over the k-steps) per call at n = k = 16384,

@@ -23,8 +23,9 @@
 // (c & 255) - 128, i.e. the two bytes of c with their top bit flipped.  With
 // s_i = sum_t c_it (row sums over the padded K, taken on the same loads),
 //   sum_t c_it c_jt = sum_t r_it r_jt + D (s_i + s_j) - K D^2,
-// exact in the fp64 epilogue.  Columns at or past the valid width are never read
-// (the last chunk of a row is read element by element) and enter as c = 0.
+// exact in the fp64 epilogue.  Columns at or past the valid width enter as c = 0
+// (a chunk past them is not read; the part of the row's last chunk past them is
+// zeroed after the load).
 //
 // Data movement: global -> registers (a ring of PF k-tiles in flight) -> LDS
 // (double buffer, XOR-swizzled 16-byte segments so that the ds_read_b128 of
@@ -39,6 +40,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "device_common.h"
@@ -95,19 +97,6 @@ __device__ __forceinline__ int32_t mod_fast_p(int32_t x, int32_t p, float inv_p)
     const int32_t q = __float_as_int(t) - __float_as_int(MAGIC);
     const int32_t r = mad24_s(q, -p, x);
     return (int32_t)min((uint32_t)r, (uint32_t)(r + p));
-}
-
-// The first lim (1 <= lim < 8) uint16 elements at byte offset off, element by
-// element (the row ends inside this chunk), the rest zero.
-__device__ __forceinline__ v4i load_u16_partial(__amdgpu_buffer_rsrc_t rs, int off, int lim)
-{
-    uint32_t w[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-    for (int e = 0; e < 7; ++e)
-        if (e < lim)
-            w[e >> 1] |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rs, off + 2 * e, 0, 0)
-                         << (16 * (e & 1));
-    return v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
 }
 
 // Offset-binary limbs of 8 uint16 values: high limbs into hi (8 bytes), low
@@ -177,10 +166,11 @@ __device__ __forceinline__ uint32_t sum_u16x8(v4i v, uint32_t acc)
     return acc;
 }
 
+// One tile of the grouped product launch: entry e of the schedule.
 template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC, int MS>
-__global__ void __launch_bounds__(WGM* WGN * 64)
-    gemm_i8(Bases bases, const GemmTask* __restrict__ tasks, const TileEnt* __restrict__ sched,
-            FieldParams fp)
+__device__ __forceinline__ void gemm_i8_tile(const Bases& bases, const GemmTask* __restrict__ tasks,
+                                             const TileEnt* __restrict__ sched, const FieldParams& fp,
+                                             char* lds, int e)
 {
     constexpr bool RAW = SRC == SRC_RAW_U16;
     static_assert(!RAW || (NL == 2 && !CPLX), "raw uint16 operands feed two limbs of a real field");
@@ -218,9 +208,7 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     static_assert(NA * TILE % (16 * NTL) == 0 && NB * TILE % (16 * NTL) == 0, "chunking");
     static_assert(FM >= 1 && FN >= 1, "wave tile");
 
-    extern __shared__ __attribute__((aligned(16))) char lds[];
-
-    const TileEnt ent = sched[blockIdx.x];
+    const TileEnt ent = sched[e];
     if (ent.x < 0) return;  // padding entry of the XCD-balanced schedule
     const GemmTask& T = tasks[ent.x];
     if (T.wait > 0) {
@@ -293,27 +281,23 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
 
     v4i ra[PFR][ACH], rb[PFR][BCH];
     const int kvalid = T.kvalid;
+    // Register-ring loads are issued without branches (the same instructions for every
+    // stage, so that each wait covers only the stage it needs): a load that has nothing
+    // to read (a stage past the last, a raw chunk past the valid columns) gets an offset
+    // past the resource's extent, which the buffer range check turns into zeros
+    // without a memory access.
+    constexpr int OOR = (int)0x80000000u;
     auto gload = [&](int st, v4i* a, v4i* b) {
         if (RAW) {
-            // only chunks holding valid columns are read (the whole offset in the
-            // per-thread register); the tail of a partial chunk is zeroed
+            // a chunk that holds valid columns is read whole (16-byte aligned rows: it
+            // stays in its row); sstore zeroes the columns past the valid ones
             const int kb = st * KT;
 #pragma unroll
-            for (int i = 0; i < ACH; ++i) {
-                const int lim = kvalid - kb - acol[i];
-                v4i v = {0, 0, 0, 0};
-                if (lim >= 8) v = __builtin_amdgcn_raw_buffer_load_b128(rsa, aoff[i] + 2 * kb, 0, 0);
-                else if (lim > 0) v = load_u16_partial(rsa, aoff[i] + 2 * kb, lim);
-                a[i] = v;
-            }
+            for (int i = 0; i < ACH; ++i)
+                a[i] = __builtin_amdgcn_raw_buffer_load_b128(rsa, kvalid - kb - acol[i] > 0 ? aoff[i] + 2 * kb : OOR, 0, 0);
 #pragma unroll
-            for (int i = 0; i < BCH; ++i) {
-                const int lim = kvalid - kb - bcol[i];
-                v4i v = {0, 0, 0, 0};
-                if (lim >= 8) v = __builtin_amdgcn_raw_buffer_load_b128(rsb, boff[i] + 2 * kb, 0, 0);
-                else if (lim > 0) v = load_u16_partial(rsb, boff[i] + 2 * kb, lim);
-                b[i] = v;
-            }
+            for (int i = 0; i < BCH; ++i)
+                b[i] = __builtin_amdgcn_raw_buffer_load_b128(rsb, kvalid - kb - bcol[i] > 0 ? boff[i] + 2 * kb : OOR, 0, 0);
             return;
         }
         const int seg = st >= nkc ? 1 : 0;
@@ -329,10 +313,11 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
             for (int i = 0; i < BCH; ++i) lds_load16(rsb, base + NA * TILE + i * NTL * 16, boff[i], ob);
             return;
         }
+        const bool live = st < nst;
 #pragma unroll
-        for (int i = 0; i < ACH; ++i) a[i] = __builtin_amdgcn_raw_buffer_load_b128(rsa, aoff[i], oa, 0);
+        for (int i = 0; i < ACH; ++i) a[i] = __builtin_amdgcn_raw_buffer_load_b128(rsa, live ? aoff[i] : OOR, live ? oa : 0, 0);
 #pragma unroll
-        for (int i = 0; i < BCH; ++i) b[i] = __builtin_amdgcn_raw_buffer_load_b128(rsb, boff[i], ob, 0);
+        for (int i = 0; i < BCH; ++i) b[i] = __builtin_amdgcn_raw_buffer_load_b128(rsb, live ? boff[i] : OOR, live ? ob : 0, 0);
     };
     // one direct load of stage st: chunk q of A (q < ACH) or q - ACH of B
     auto gload_one = [&](int st, int q) {
@@ -342,22 +327,36 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
         if (q < ACH) lds_load16(rsa, base + q * NTL * 16, aoff[q], seg * seg_a + kc * KT);
         else lds_load16(rsb, base + NA * TILE + (q - ACH) * NTL * 16, boff[q - ACH], seg * seg_b + kc * KT);
     };
-    auto sstore = [&](int buf, const v4i* a, const v4i* b) {
+    // raw chunk of 8 uint16 columns with lim valid ones: the others zeroed
+    auto keep_valid = [&](v4i v, int lim) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t m = lim >= 2 * j + 2 ? 0xffffffffu : (lim == 2 * j + 1 ? 0x0000ffffu : 0u);
+            v[j] = (int)((uint32_t)v[j] & m);
+        }
+        return v;
+    };
+    auto sstore = [&](int buf, int st, const v4i* a, const v4i* b) {
         char* base = lds + buf * STAGE;
         if (RAW) {
+            // the stage holds columns past the valid ones when it reaches kvalid
+            const int kb = st * KT;
+            const bool edge = kb + KT > kvalid;
 #pragma unroll
             for (int i = 0; i < ACH; ++i) {
                 int2 hi, lo;
-                split_u16x8(a[i], hi, lo);
-                asum[i] = sum_u16x8(a[i], asum[i]);
+                const v4i av = edge ? keep_valid(a[i], kvalid - kb - acol[i]) : a[i];
+                split_u16x8(av, hi, lo);
+                asum[i] = sum_u16x8(av, asum[i]);
                 *reinterpret_cast<int2*>(base + alds[i]) = hi;
                 *reinterpret_cast<int2*>(base + alds[i] + TILE) = lo;
             }
 #pragma unroll
             for (int i = 0; i < BCH; ++i) {
                 int2 hi, lo;
-                split_u16x8(b[i], hi, lo);
-                bsum[i] = sum_u16x8(b[i], bsum[i]);
+                const v4i bv = edge ? keep_valid(b[i], kvalid - kb - bcol[i]) : b[i];
+                split_u16x8(bv, hi, lo);
+                bsum[i] = sum_u16x8(bv, bsum[i]);
                 *reinterpret_cast<int2*>(base + blds[i]) = hi;
                 *reinterpret_cast<int2*>(base + blds[i] + TILE) = lo;
             }
@@ -498,28 +497,33 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
             __syncthreads();
         }
     }
+    if (!DMA) {
+        // register slot u holds stage st with st % PF == u.  The main loop runs whole
+        // groups of PF stages, each refilling its slot with the stage PF ahead (nothing
+        // past the last stage is read); the stages left over follow without loads.
 #pragma unroll
-    for (int u = 0; u < (DMA ? 0 : PF); ++u)
-        if (u < nst) gload(u, ra[u], rb[u]);
-    if (!DMA && nst > 0) sstore(0, ra[0], rb[0]);
-    if (!DMA) __syncthreads();
-    for (int st0 = 0; st0 < (DMA ? 0 : nst); st0 += PFR) {
+        for (int u = 0; u < PFR; ++u) gload(u, ra[u], rb[u]);
+        if (nst > 0) sstore(0, 0, ra[0], rb[0]);
+        __syncthreads();
+        auto step = [&](int st, int u, bool refill) __attribute__((always_inline)) {
+            auto next = [&] {
+                if (st + 1 < nst) sstore((st + 1) & 1, st + 1, ra[(u + 1) % PFR], rb[(u + 1) % PFR]);
+            };
+            if (SPOS == 2) next();
+            if (refill) gload(st + PFR, ra[u], rb[u]);
+            compute(st & 1, [&](int ks) {
+                if (ks == HK) next();
+            });
+            __syncthreads();
+        };
+        int st0 = 0;
+        for (; st0 + PFR <= nst; st0 += PFR) {
 #pragma unroll
-        for (int u = 0; u < PFR; ++u) {
-            const int st = st0 + u;
-            if (st < nst) {
-                auto next = [&] {
-                    if (st + 1 < nst) sstore((st + 1) & 1, ra[(u + 1) % PFR], rb[(u + 1) % PFR]);
-                };
-                // register slot u held stage st (already in LDS): refill it with stage st + PF
-                if (SPOS == 2) next();
-                if (st + PFR < nst) gload(st + PFR, ra[u], rb[u]);
-                compute(st & 1, [&](int ks) {
-                    if (ks == HK) next();
-                });
-                __syncthreads();
-            }
+            for (int u = 0; u < PFR; ++u) step(st0 + u, u, true);
         }
+#pragma unroll
+        for (int u = 0; u < PFR - 1; ++u)
+            if (st0 + u < nst) step(st0 + u, u, false);
     }
 
     // ---- raw operands: row sums of the tile's A rows and B rows into LDS (the
@@ -691,6 +695,41 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     }
 }
 
+// The grouped product launch.  fp.nent == 0: workgroup b computes schedule entry b.
+// fp.nent > 0 (persistent): a grid of at most the resident workgroups; workgroup b
+// takes the entries of its XCD (x = b mod 8; entries x, x + 8, ... were dealt to it by
+// the host) in order from that XCD's queue counter in the workspace (zeroed before
+// the launch), grabbing the next one while it computes the current one, until the
+// queue passes fp.nent.  Every workgroup ends once its queue is drained.
+template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC, int MS>
+__global__ void __launch_bounds__(WGM* WGN * 64)
+    gemm_i8(Bases bases, const GemmTask* __restrict__ tasks, const TileEnt* __restrict__ sched,
+            FieldParams fp)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    __shared__ int s_next;
+    const bool persist = fp.nent > 0;
+    const int x = blockIdx.x & 7;
+    int* q = reinterpret_cast<int*>(bases.p[BUF_WS] + fp.queue_off) + x;
+    int e = blockIdx.x;
+    if (persist) {
+        if (threadIdx.x == 0) s_next = atomicAdd(q, 1) * 8 + x;
+        __syncthreads();
+        e = s_next;
+    }
+    const int nent = persist ? fp.nent : (int)gridDim.x;
+    while (e < nent) {
+        int nx = 0;
+        if (persist && threadIdx.x == 0) nx = atomicAdd(q, 1) * 8 + x;
+        gemm_i8_tile<NL, CPLX, BT, WGM, WGN, KT, PF, SRC, MS>(bases, tasks, sched, fp, lds, e);
+        if (!persist) break;
+        __syncthreads();  // the tile's last reads of LDS are done
+        if (threadIdx.x == 0) s_next = nx;
+        __syncthreads();
+        e = s_next;
+    }
+}
+
 template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC, int MS>
 static int launch_cfg(const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks, const Bases& b,
                       const FieldParams& fp, hipStream_t s)
@@ -709,7 +748,22 @@ static int launch_cfg(const GemmTask* d_tasks, const TileEnt* d_sched, int nbloc
         if (e != hipSuccess) return (int)e;
         attr_devices |= bit;
     }
-    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(WGM * WGN * 64), lds_bytes, s, b, d_tasks,
+    int grid = nblocks;
+    if (fp.nent > 0) {
+        // persistent: at most the workgroups that fit the device at once, a multiple of 8
+        static int resident[64] = {0};
+        int& r = resident[dev & 63];
+        if (r == 0) {
+            int per_cu = 0, cus = 0;
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, WGM * WGN * 64, lds_bytes);
+            if (e != hipSuccess) return (int)e;
+            e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            if (e != hipSuccess) return (int)e;
+            r = std::max(8, std::max(per_cu, 1) * cus / 8 * 8);
+        }
+        grid = std::min(grid, r);
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(WGM * WGN * 64), lds_bytes, s, b, d_tasks,
                        d_sched, fp);
     return (int)hipGetLastError();
 }

@@ -754,11 +754,14 @@ void choose_kernel(Plan& pl, int64_t max_dim)
 
 // Whether a problem's products can read the caller's uint16 rows directly: two
 // limbs of a real field, no recursion (nothing else reads A), no input check,
-// 16-byte aligned rows, and a product kernel that loads through registers.
+// 16-byte aligned rows, and a product kernel that loads through registers.  The
+// kernel reads whole 16-byte chunks of a row (the columns past k are zeroed after
+// the load), so the row's last chunk must be inside the caller's buffer: k a
+// multiple of 8, or the library's packed layout, whose rows are padded to 16 bytes.
 bool raw_u16_ok(const Plan& pl, const Problem& pr, int levels)
 {
     return pl.carrier == CAR_I8 && pl.nl == 2 && !pl.cplx && gemm_i8_config_raw(pl.gemm_cfg) && pr.dA == FFA_U16 &&
-           levels == 0 && !pr.trans &&
+           levels == 0 && !pr.trans && (pr.k % 8 == 0 || pr.packed) &&
            !pl.check_inputs && pr.k > 0 && pr.aligned && (pr.lda * 2) % 16 == 0 &&
            (pr.a_off * 2) % 16 == 0 && pr.lda * 2 < (1ll << 31) / 256;
 }
@@ -813,7 +816,8 @@ Plan make_plan(const Problem& pr)
     pl.pre.assign(pl.levels, {});
     pl.post.assign(pl.levels, {});
     pl.kernel_req = o.kernel;
-    if (o.general < FFA_GENERAL_AUTO || o.general > FFA_GENERAL_WINOGRAD || o.wino_min < 0) {
+    if (o.general < FFA_GENERAL_AUTO || o.general > FFA_GENERAL_WINOGRAD || o.wino_min < 0 ||
+        o.persist < FFA_PERSIST_AUTO || o.persist > FFA_PERSIST_ON) {
         pl.status = FFA_EINVAL;
         return pl;
     }
@@ -836,11 +840,20 @@ Plan make_plan(const Problem& pr)
     };
     const bool raw_ok = raw_u16_ok(pl, pr, pl.levels);
     build(pl, raw_ok && o.operands == FFA_OPERANDS_RAW ? SRC_RAW_U16 : SRC_CARRIER);
-    if (pl.status == FFA_EUNSUPPORTED && raw_ok && o.operands == FFA_OPERANDS_AUTO) {
+    if (pl.status == FFA_EUNSUPPORTED && o.operands == FFA_OPERANDS_AUTO) {
         // limb planes too large for the product kernel's 32-bit offsets: raw
-        // operands need no planes
-        pl = base;
-        build(pl, SRC_RAW_U16);
+        // operands need no planes; they need a configuration that loads through
+        // registers (the built-in two-limb one that does, unless one was asked for)
+        Plan q = base;
+        if (q.kernel_req == 0 && q.carrier == CAR_I8 && q.nl == 2 && !q.cplx && !gemm_i8_config_raw(q.gemm_cfg)) {
+            q.gemm_cfg = gemm_i8_default_config(2, 0, 0);
+            q.tile = gemm_i8_config_tile(q.gemm_cfg);
+            q.ktile = gemm_i8_config_ktile(q.gemm_cfg);
+        }
+        if (raw_u16_ok(q, pr, q.levels)) {
+            pl = q;
+            build(pl, SRC_RAW_U16);
+        }
     }
     if (pl.status != FFA_OK && pl.status != FFA_EBOUND && pl.status != FFA_EUNSUPPORTED) return pl;
     if (pl.status == FFA_OK) pl.status = check_bound(pl);
@@ -863,6 +876,14 @@ Plan make_plan(const Problem& pr)
                 pl.gemm[t].wait_off = pl.wait_off;
             }
     }
+    // a single call's product launch runs persistent on request only, and never beside
+    // the pre-additions (a waiting tile would hold its slot) or split over two streams
+    pl.persist = o.persist == FFA_PERSIST_ON && pl.status == FFA_OK && pl.carrier == CAR_I8 &&
+                 !pl.overlap_pre && !pl.fork;
+    if (pl.persist) {
+        pl.queue_off = round_up(pl.ws_bytes, 256);
+        pl.ws_bytes = pl.queue_off + 256;
+    }
     size_grids(pl);
     return pl;
 }
@@ -883,7 +904,8 @@ Plan make_batch_plan(const std::vector<Problem>& prs)
     pl.herk2m = pl.cplx && pl.carrier == CAR_I8 && p0.opts.herk_base != FFA_HERK_4M;
     pl.fp.npo = pl.herk2m ? 4 : 3;
     const ffa_opts& o0 = p0.opts;
-    if (o0.general < FFA_GENERAL_AUTO || o0.general > FFA_GENERAL_WINOGRAD || o0.wino_min < 0) {
+    if (o0.general < FFA_GENERAL_AUTO || o0.general > FFA_GENERAL_WINOGRAD || o0.wino_min < 0 ||
+        o0.persist < FFA_PERSIST_AUTO || o0.persist > FFA_PERSIST_ON) {
         pl.status = FFA_EINVAL;
         return pl;
     }
@@ -920,6 +942,7 @@ Plan make_batch_plan(const std::vector<Problem>& prs)
             Problem q = prs[i];
             q.lda = lda_of(q);
             q.a_off = off;
+            q.packed = true;
             off += round_up(q.n * q.lda * ain, 16) / ain;
             raw = q.n == 0 || raw_u16_ok(pl, q, L[i]);
         }
@@ -952,6 +975,12 @@ Plan make_batch_plan(const std::vector<Problem>& prs)
     pl.ws_bytes = B.ws;
     if (pl.status == FFA_OK) pl.status = check_bound(pl);
     pl.fork = p0.opts.streams == FFA_STREAMS_TWO && pl.levels > 0;
+    // a batch's many short tiles: persistent unless asked otherwise
+    pl.persist = o0.persist != FFA_PERSIST_OFF && pl.status == FFA_OK && pl.carrier == CAR_I8 && !pl.fork;
+    if (pl.persist) {
+        pl.queue_off = round_up(pl.ws_bytes, 256);
+        pl.ws_bytes = pl.queue_off + 256;
+    }
     size_grids(pl);
     return pl;
 }
@@ -1004,7 +1033,7 @@ std::string describe(const Plan& pl)
              "\"macs\":%lld,\"ykind\":%d,\"ya\":%d,\"yb\":%d,\"src\":\"%s\",\"streams\":%d,"
              "\"blocks_a_only\":%zu,\"herk_base\":\"%s\",\"real_tasks\":%zu,\"general\":\"%s\","
              "\"wino_tasks\":%zu,\"wino_min\":%lld,\"cfg_real\":%d,\"st32\":%d,\"tail_tiles\":%zu,"
-             "\"overlap_pre\":%d}",
+             "\"overlap_pre\":%d,\"persist\":%d}",
              pl.status, pl.levels, pl.carrier == CAR_F64 ? "f64" : "int8", pl.nl, pl.cplx,
              (long long)pl.npad, (long long)pl.kpad, pl.direct ? 1 : 0, pl.max_abs,
              (long long)pl.max_k, (long long)pl.ws_bytes, pl.cond.size(), pre.c_str(), post.c_str(),
@@ -1013,7 +1042,8 @@ std::string describe(const Plan& pl)
              pl.fp.yb, pl.gemm_src == SRC_RAW_U16 ? "raw_u16" : "carrier", pl.fork ? 2 : 1,
              pl.sched.size(), pl.herk2m ? "2m" : (pl.cplx ? "4m" : "none"), pl.gemm_r.size(),
              pl.wpre.empty() ? "classical" : "winograd", pl.wpre.size(), (long long)pl.wino_min,
-             pl.herk2m ? pl.gemm_cfg_r : -1, pl.fp.st32, pl.tail.size(), pl.overlap_pre ? 1 : 0);
+             pl.herk2m ? pl.gemm_cfg_r : -1, pl.fp.st32, pl.tail.size(), pl.overlap_pre ? 1 : 0,
+             pl.persist ? 1 : 0);
     return buf;
 }
 

@@ -23,6 +23,7 @@ struct Problem {
     int64_t c_off = 0;
     int trans = 0;             // A is k x n and the product is A^T A
     uint32_t alpha = 1, beta = 0;  // C <- alpha Low(A A^T) + beta C
+    bool packed = false;       // A in the library's packed layout (rows padded to 16 bytes)
 };
 
 struct Plan {
@@ -86,6 +87,10 @@ struct Plan {
     bool overlap_pre = false;
     int pre_blocks = 0;                 // workgroups of the pre-addition kernel (the counter's target)
     int64_t wait_off = 0;
+    // Persistent INT8 product launch: at most the resident workgroups, taking tiles
+    // from 8 queue counters (one per XCD) at workspace byte queue_off
+    bool persist = false;
+    int64_t queue_off = 0;
     int64_t ws_bytes = 0;
     int64_t products_macs = 0;         // multiply-accumulates of the products (per limb product)
     std::vector<int64_t> a_off, c_off; // packed batch layout (elements)

@@ -450,7 +450,8 @@ def test_syrk_update_degenerate():
 @pytest.mark.parametrize("k", [1, 7, 8, 9, 127, 128, 129, 300, 1000])
 def test_raw_u16_products_ragged_k(n, k):
     """No recursion, uint16 input with 16-byte rows: the product kernel reads the
-    caller's rows and splits them into limbs.  The row padding holds nonzero
+    caller's rows and splits them into limbs when k is a multiple of 8 (it reads whole
+    16-byte chunks), else the limb planes are built.  The row padding holds nonzero
     residues, which must never reach the result."""
     ffa = _ffa()
     p = 65521
@@ -460,7 +461,7 @@ def test_raw_u16_products_ragged_k(n, k):
     Ares = big[:, :k].copy()
     st, d = ffa.plan_describe(n, k, p, dA=ffa.U16, dC=ffa.U16, lda=lda,
                               opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL, operands=ffa.OPERANDS_RAW))
-    assert st == 0 and d["src"] == "raw_u16"
+    assert st == 0 and d["src"] == ("raw_u16" if k % 8 == 0 else "carrier")
     A = _dev(big, torch.uint16)[:, :k]
     C = _sentinel_c(n, torch.uint16)
     ffa.syrk_modp(A, p, C=C, algo=ffa.ALGO_CLASSICAL, operands=ffa.OPERANDS_RAW)
@@ -504,6 +505,81 @@ def test_batched_uneven_problems():
             exp = oracle.syrk_modp(M, p)
             assert np.array_equal(np.tril(got), exp), f"problem {i} ({n}x{ks[i]})"
         B.close()
+
+
+def test_batch_plan_persistent_by_default():
+    ffa = _ffa()
+    ns, ks = np.array([40, 300, 7]), np.array([50, 310, 9])
+    B = ffa.BatchSyrk(ns, ks, 65521, ffa.U16, ffa.U16)
+    assert B.describe()["persist"] == 1
+    B.close()
+    B = ffa.BatchSyrk(ns, ks, 65521, ffa.U16, ffa.U16, persist=ffa.PERSIST_OFF)
+    assert B.describe()["persist"] == 0
+    B.close()
+    with pytest.raises(ffa.FfaError):
+        ffa.BatchSyrk(ns, ks, 65521, ffa.U16, ffa.U16, persist=5)
+
+
+@pytest.mark.parametrize("persist", ["on", "off"])
+@pytest.mark.parametrize("cfg", [16, 21])
+def test_batched_raw_rows_with_nonzero_padding(cfg, persist):
+    """Raw uint16 operands over the packed layout with ragged k: the row's last
+    16-byte chunk is read whole and its columns past k are zeroed in the kernel.  The
+    packed rows' padding is filled with nonzero residues here, which must never
+    reach the result."""
+    ffa = _ffa()
+    p = 65521
+    ns, ks = si.batch_shapes(40, 91, nmin=1, nmax=200)
+    ks = ks + (ks % 8 == 0)  # every k ragged
+    mats = si.batch_residues(ns, ks, p, 91)
+    _say("batch raw padding", cfg, len(ns))
+    B = ffa.BatchSyrk(ns, ks, p, ffa.U16, ffa.U16, algo=ffa.ALGO_CLASSICAL,
+                      operands=ffa.OPERANDS_RAW, kernel=cfg + 1,
+                      persist=ffa.PERSIST_ON if persist == "on" else ffa.PERSIST_OFF)
+    assert B.describe()["src"] == "raw_u16" and B.describe()["persist"] == (persist == "on")
+    Ap = B.pack(mats, np.int64)
+    rng = np.random.default_rng(91)
+    for i in range(len(ns)):
+        n, k, ld, o = int(ns[i]), int(ks[i]), int(B.lda[i]), int(B.a_off[i])
+        if n:
+            rows = Ap[o:o + n * ld].reshape(n, ld)
+            rows[:, k:] = rng.integers(1, p, (n, ld - k))
+    Cp = torch.zeros(B.c_total, dtype=torch.int32, device="cuda").to(torch.uint16)
+    B.run(_dev(Ap, torch.uint16), Cp)
+    torch.cuda.synchronize()
+    Ch = _host(Cp)
+    for i, M in enumerate(mats):
+        n = int(ns[i])
+        got = Ch[B.c_off[i]:B.c_off[i] + n * n].reshape(n, n)
+        assert np.array_equal(np.tril(got), oracle.syrk_modp(M, p)), f"problem {i} ({n}x{ks[i]})"
+    B.close()
+
+
+@pytest.mark.parametrize("case", ["p251-default", "p251-cfg34", "p65521-planes", "p65521-raw", "p65521-cfg32"])
+def test_persistent_product_launch(case):
+    """The product launch run persistent (workgroups taking tiles from a queue per XCD)
+    against the oracle, on shapes of many ragged tiles, twice in a row (the queue
+    counters are cleared before each launch)."""
+    ffa = _ffa()
+    p = 251 if case.startswith("p251") else 65521
+    n, k = (1000, 777) if p == 251 else (700, 520)
+    A = si.uniform_residues(n, k, p, 4242)
+    kw = dict(algo=ffa.ALGO_CLASSICAL, persist=ffa.PERSIST_ON)
+    if case.endswith("cfg34"):
+        kw["kernel"] = 35
+    if case.endswith("cfg32"):
+        kw["kernel"] = 33
+    if case.endswith("raw"):
+        kw["operands"] = ffa.OPERANDS_RAW
+    dA = torch.int8 if p == 251 else torch.uint16
+    dC = torch.uint8 if p == 251 else torch.uint16
+    d = _check_planned(n, k, p, ffa.I8_CENTRED if p == 251 else ffa.U16, ffa.U8 if p == 251 else ffa.U16,
+                       **kw)
+    assert d["persist"] == 1 and d["blocks"] > 8
+    if case.endswith("raw"):
+        assert d["src"] == "raw_u16"
+    for _ in range(2):
+        check_syrk(A, p, dA, dC, **kw)
 
 
 # ------------------------------------------------------------------ full size, sampled

@@ -111,7 +111,8 @@ def test_plan_operand_source():
 
 def test_default_product_configurations():
     # one limb: 128-tiles below 2048 rows per leaf, else 8 waves of 128x64 on 256-tiles with
-    # direct loads and 16x16x64 MFMAs; two limbs: 128-tiles with a register ring
+    # direct loads and 16x16x64 MFMAs; two limbs: 128-tiles, direct loads into two buffers
+    # from 2048 rows, else a register ring
     for n, cfg in ((1024, 2), (2048, 34), (16384, 34)):
         st, d = ffa.plan_describe(n, n, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
                                   opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
@@ -120,6 +121,8 @@ def test_default_product_configurations():
     # centred int8 input is read in place by the pre-additions and products
     assert st == 0 and d["levels"] == 1 and d["cfg"] == 34 and d["direct"] == 1 and d["conditioning"] == 0
     st, d = ffa.plan_describe(16384, 16384, 65521, dA=ffa.U16, dC=ffa.U16)
+    assert st == 0 and d["cfg"] == 32
+    st, d = ffa.plan_describe(1024, 1024, 65521, dA=ffa.U16, dC=ffa.U16)
     assert st == 0 and d["cfg"] == 16
 
 
@@ -140,6 +143,24 @@ def test_plan_product_groups_and_streams():
     assert d["streams"] == 1 and d["blocks_a_only"] == d["blocks"]
     assert ffa.plan_describe(10, 10, 251, opts=ffa.make_opts(streams=3))[0] == ffa.EINVAL
     assert ffa.plan_describe(10, 10, 251, opts=ffa.make_opts(operands=3))[0] == ffa.EINVAL
+
+
+def test_plan_persistent_product_launch():
+    # single calls: persistent on request only, never beside the pre-additions or split
+    # over two streams (batches, planned with a device context, in the GPU tests)
+    kw = dict(dA=ffa.I8_CENTRED, dC=ffa.U8)
+    assert ffa.plan_describe(2048, 2048, 251, opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL), **kw)[1]["persist"] == 0
+    st, d = ffa.plan_describe(2048, 2048, 251, opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL,
+                                                                  persist=ffa.PERSIST_ON), **kw)
+    st0, d0 = ffa.plan_describe(2048, 2048, 251, opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL), **kw)
+    assert st == 0 and d["persist"] == 1 and d["ws_bytes"] == d0["ws_bytes"] + 256  # the queue counters
+    st, d = ffa.plan_describe(4096, 4096, 251, opts=ffa.make_opts(levels=1, persist=ffa.PERSIST_ON), **kw)
+    assert st == 0 and d["overlap_pre"] == 1 and d["persist"] == 0
+    st, d = ffa.plan_describe(4096, 4096, 251, opts=ffa.make_opts(levels=1, streams=ffa.STREAMS_TWO,
+                                                                  persist=ffa.PERSIST_ON), **kw)
+    assert st == 0 and d["streams"] == 2 and d["persist"] == 0
+    for bad in (-1, 3):
+        assert ffa.plan_describe(10, 10, 251, opts=ffa.make_opts(persist=bad))[0] == ffa.EINVAL
 
 
 def test_plan_herk_base_case_2m():
