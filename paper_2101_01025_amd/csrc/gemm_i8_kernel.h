@@ -32,11 +32,13 @@
 // consecutive rows hits distinct banks) -> MFMA.  Configurations with PF = 0
 // load global -> LDS directly (buffer loads that write LDS, each thread reading
 // the segment that the swizzle puts in its slot): no ring registers, and the
-// next k-tile is in flight while the current one is multiplied.  Which tile a workgroup
-// computes comes from a host-built schedule indexed by blockIdx: tiles are
-// grouped into L2-friendly blocks and the blocks are dealt to the 8 XCDs
-// (workgroup b runs on XCD b mod 8) so that each XCD's L2 serves a compact set
-// of operand panels and every XCD gets the same amount of work.
+// next k-tile is in flight while the current one is multiplied; PF < 0 does the
+// same into -PF buffers with the loads spread between the k-steps.  Which tile a
+// workgroup computes comes from a host-built schedule: tiles are grouped into
+// L2-friendly blocks and the blocks are dealt to the 8 XCDs (workgroup b runs on
+// XCD b mod 8) so that each XCD's L2 serves a compact set of operand panels and
+// every XCD gets the same amount of work.  Workgroup b computes entry b, or, in
+// a persistent launch, the entries of its XCD taken from a queue counter.
 #pragma once
 #include <hip/hip_runtime.h>
 
