@@ -40,7 +40,9 @@
     X(32, 2, 0, 128, 2, 4, 128, -2, 32)   \
     X(34, 1, 0, 256, 2, 4, 128, 0, 16)    \
     X(35, 1, 0, 256, 2, 4, 128, -2, 16)   \
-    X(36, 2, 0, 128, 2, 4, 128, -2, 16)
+    X(36, 2, 0, 128, 2, 4, 128, -2, 16)   \
+    X(37, 1, 0, 256, 4, 2, 128, 0, 16)    \
+    X(38, 1, 0, 128, 2, 2, 128, 0, 16)
 
 #define FFA_I8_CONFIGS(X) \
     FFA_I8_CONFIGS_A(X)   \

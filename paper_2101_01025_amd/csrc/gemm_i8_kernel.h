@@ -221,7 +221,12 @@ __device__ __forceinline__ void gemm_i8_tile(const Bases& bases, const GemmTask*
     }
     const int row0 = (ent.y & 0xffff) * BT, col0 = (ent.y >> 16) * BT;
     const int M = T.M, N = T.N, K = T.K;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // (the thread index passes through an empty asm statement so that the compiler
+    // does not hoist the per-thread offsets derived from it out of a persistent
+    // launch's loop over tiles, where they would stay live and spill)
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
 
     // ---- operand panels as buffer resources: every load is (constant per-thread

@@ -302,15 +302,19 @@ Common common_setup(uint32_t p, int herm, int dA, int dC, const ffa_opts& o)
     return cm;
 }
 
-// Built-in recursion cutoffs (measured on MI355X: one level wins at n = 16384 for
-// the INT8 carriers, four levels at n = 8192 for fp64, one level at n = 4096 for F_p[i]).
+// Built-in recursion cutoffs (measured on MI355X: one level wins from n = 32768 for one
+// INT8 limb and at n = 16384 for two, four levels at n = 8192 for fp64; F_p[i] with the
+// 2M base case: no recursion).
 int default_cutoff(int carrier, int nl, int cplx, bool herk2m)
 {
     if (carrier == CAR_F64) return 512;
     // F_p[i]: with the 2M base case (1.5 n^2 k real products) one level of Algorithm 1,
     // whose P3, P4 are complex products of four real ones, costs 1.04x more products
     if (cplx) return herk2m ? (1 << 30) : 2048;
-    return 8192;
+    // one limb: the classical product is as fast at n = 16384 (1.72-1.75 ms against 1.76-1.83 ms
+    // per call with one level) and slower at n = 32768 (14.40 ms against 13.19 ms for one
+    // level, 13.22 ms for two); two limbs: one level wins at 16384 (6.81 against 7.69 ms)
+    return nl == 1 ? 16384 : 8192;
 }
 
 int choose_levels(int64_t n, int64_t k, const ffa_opts& o, int carrier, int nl, int cplx, bool herk2m)

@@ -603,7 +603,7 @@ def test_full_size_p251_sampled_and_freivalds(algo):
     A8 = si.centred_int8(n, k, p, si.config_seed(2))
     _say("full", n, k, p, algo)
     dA = torch.from_numpy(A8).to("cuda")
-    kw = dict(algo=1) if algo == "classical" else dict()
+    kw = dict(algo=1) if algo == "classical" else dict(levels=1)
     C = ffa.syrk_modp(dA, p, **kw)
     torch.cuda.synchronize()
     ffa.device_status(0)

@@ -53,9 +53,13 @@ def test_skew_unitary_errors():
 
 
 def test_plan_levels_padding_and_carriers():
-    st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8)
+    st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8, opts=ffa.make_opts(levels=1))
     assert st == 0 and d["carrier"] == "int8" and d["limbs"] == 1 and d["direct"] == 1
     assert d["levels"] == 1 and d["npad"] == 16384 and d["kpad"] == 16384
+    # built-in depth, one limb: classical at 16384, one level at 32768; two limbs: one at 16384
+    assert ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8)[1]["levels"] == 0
+    assert ffa.plan_describe(32768, 32768, 251, dA=ffa.I8_CENTRED, dC=ffa.U8)[1]["levels"] == 1
+    assert ffa.plan_describe(16384, 16384, 65521, dA=ffa.U16, dC=ffa.U16)[1]["levels"] == 1
     assert d["ykind"] == 1 and (d["ya"], d["yb"]) == (80, 80)
     st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
                               opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
@@ -117,7 +121,7 @@ def test_default_product_configurations():
         st, d = ffa.plan_describe(n, n, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
                                   opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
         assert st == 0 and d["cfg"] == cfg and d["tile"] == (128 if cfg == 2 else 256), (n, d)
-    st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8)
+    st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8, opts=ffa.make_opts(levels=1))
     # centred int8 input is read in place by the pre-additions and products
     assert st == 0 and d["levels"] == 1 and d["cfg"] == 34 and d["direct"] == 1 and d["conditioning"] == 0
     st, d = ffa.plan_describe(16384, 16384, 65521, dA=ffa.U16, dC=ffa.U16)
@@ -329,7 +333,7 @@ def test_plans_keep_every_task_inside_the_workspace():
 def test_last_round_split():
     # one level at 16384^2, p = 251: 3632 tiles of 256 on 8 XCDs of 32 CUs leave 6 tiles
     # past 14 full rounds on each XCD; they run as four K-quarters each
-    st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8)
+    st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8, opts=ffa.make_opts(levels=1))
     assert st == 0 and d["tail_tiles"] == 48 and d["tiles"] == 3632 + 3 * 48, d
     # the classical product: 2080 tiles, 4 past 8 full rounds per XCD
     st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
@@ -345,7 +349,7 @@ def test_last_round_split():
     # two streams, the fp64 carrier, F_p[i]
     for args, kw in (((4096, 4096, 251), dict(algo=ffa.ALGO_CLASSICAL)),
                      ((2304, 2560 - 128, 251), dict(algo=ffa.ALGO_CLASSICAL)),
-                     ((16384, 16384, 251), dict(streams=ffa.STREAMS_TWO))):
+                     ((16384, 16384, 251), dict(levels=1, streams=ffa.STREAMS_TWO))):
         st, d = ffa.plan_describe(*args, dA=ffa.I8_CENTRED, dC=ffa.U8, opts=ffa.make_opts(**kw))
         assert st == 0 and d["tail_tiles"] == 0, (args, kw, d)
     st, d = ffa.plan_describe(8192, 8192, 65521, dA=ffa.F64, dC=ffa.U16)
