@@ -276,6 +276,7 @@ int launch_gemm_f64(const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks
 int gemm_i8_config_tile(int cfg);
 int gemm_i8_config_ktile(int cfg);
 int gemm_i8_config_raw(int cfg);  // the configuration can read raw uint16 operands
+int gemm_i8_config_lds(int cfg);  // dynamic LDS bytes of one workgroup
 int gemm_i8_config_valid(int cfg, int nl, int cplx);
 int gemm_i8_default_config(int nl, int cplx, int64_t max_dim);
 // VGPRs per thread, threads per workgroup and LDS bytes of a configuration's kernel

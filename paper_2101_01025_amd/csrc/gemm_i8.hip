@@ -38,6 +38,7 @@ static CfgInfo cfg_info(int id)
 int gemm_i8_config_tile(int cfg) { return cfg_info(cfg).bt; }
 int gemm_i8_config_ktile(int cfg) { return cfg_info(cfg).kt; }
 int gemm_i8_config_raw(int cfg) { return cfg_info(cfg).raw; }
+int gemm_i8_config_lds(int cfg) { return cfg_info(cfg).lds; }
 
 int gemm_i8_config_valid(int cfg, int nl, int cplx)
 {

@@ -420,11 +420,14 @@ int build_schedule(const std::vector<GemmTask>& tasks, bool cplx, size_t first, 
 // workspace, and a TailTask adds them into the tile's place mod p before
 // anything reads it.  The launch then ends a quarter (half) round after its last
 // full round instead of a whole round.  Tiles on the diagonal of a base case
-// (written in part) are not split.
+// (written in part) are not split.  A round is 32 tiles per XCD only when one
+// workgroup fills a CU; configurations whose LDS lets two or more share a CU are
+// not split (their rounds are not known on the host).
 void split_tail(Plan& pl)
 {
     constexpr int NX = 8, CPX = 32;
     if (pl.carrier != CAR_I8 || pl.cplx || pl.gemm_src != SRC_CARRIER || pl.sched.empty()) return;
+    if (2 * gemm_i8_config_lds(pl.gemm_cfg) <= 160 * 1024) return;
     const int bt = pl.tile;
     const size_t len = pl.sched.size() / NX;
     std::vector<std::vector<TileEnt>> bins(NX);
@@ -441,12 +444,17 @@ void split_tail(Plan& pl)
     std::vector<TailTask> tail;
     for (auto& v : bins) {
         const int nt = (int)(v.size() % CPX);
-        NQ = nt * 4 <= CPX ? 4 : 2;
-        if (nt == 0 || nt * NQ > CPX) continue;
-        std::vector<char> taken(v.size(), 0);
+        if (nt == 0 || nt * 2 > CPX) continue;
+        // quarters when they fit the round and divide K, else halves
+        std::vector<char> taken;
         int got = 0;
-        for (size_t i = v.size(); i-- > 0 && got < nt;)
-            if (splittable(v[i])) taken[i] = 1, ++got;
+        for (NQ = nt * 4 <= CPX ? 4 : 2; NQ >= 2; NQ /= 2) {
+            taken.assign(v.size(), 0);
+            got = 0;
+            for (size_t i = v.size(); i-- > 0 && got < nt;)
+                if (splittable(v[i])) taken[i] = 1, ++got;
+            if (got == nt) break;
+        }
         if (got < nt) continue;
         std::vector<TileEnt> keep, pieces;
         for (size_t i = 0; i < v.size(); ++i) {

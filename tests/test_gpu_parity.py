@@ -153,6 +153,31 @@ def test_split_last_round_tiles(n, k, p, di, do, kw):
     check_syrk(A, p, tdA, tdC, **kw)
 
 
+@pytest.mark.parametrize("n,k", [(2304, 2560), (2304, 2816)])
+def test_split_last_round_into_strided_unaligned_c(n, k):
+    """The last-round pieces summed into a view of C whose rows are not 16-byte aligned
+    (odd offset, odd row stride): the product kernel's element-wise edge stores and the
+    scalar path of the piece sums; quarters (20 k-tiles) and halves (22 k-tiles)."""
+    ffa = _ffa()
+    p = 251
+    st, d = ffa.plan_describe(n, k, p, dA=ffa.I8_CENTRED, dC=ffa.U8, opts=ffa.make_opts(algo=1))
+    assert st == 0 and d["tail_tiles"] > 0, d
+    A = si.uniform_residues(n, k, p, 1700 + k)
+    big = torch.full((n + 2, n + 7), 0x5A, dtype=torch.uint8, device="cuda")
+    C = big[1:1 + n, 3:3 + n]
+    ffa.syrk_modp(_dev(si.to_centred(A, p).astype(np.int8), torch.int8), p, C=C, algo=1)
+    torch.cuda.synchronize()
+    g = big.cpu().numpy().astype(np.int64)
+    exp = oracle.syrk_modp(A, p)
+    low = np.tril(np.ones((n, n), dtype=bool))
+    view = g[1:1 + n, 3:3 + n]
+    assert np.array_equal(view[low], exp[low])
+    assert (view[~low] == 0x5A).all()
+    outside = np.ones_like(g, dtype=bool)
+    outside[1:1 + n, 3:3 + n] = False
+    assert (g[outside] == 0x5A).all()
+
+
 @pytest.mark.parametrize("p", [3, 5, 13, 241])
 def test_int8_small_primes(p):
     # p = 3 and 251 use Y = [[a,b],[-b,a]] (x) I; p = 5, 13, 241 use Y = sqrt(-1) I

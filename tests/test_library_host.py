@@ -356,6 +356,15 @@ def test_last_round_split():
     assert st == 0 and d["tail_tiles"] == 0
     st, d = ffa.plan_describe(4096, 8192, 65519, hermitian=True, dA=ffa.U16, dC=ffa.U16)
     assert st == 0 and d["tail_tiles"] == 0
+    # quarters that do not divide K (22 k-tiles of 128 bytes): halves instead
+    st, d = ffa.plan_describe(2304, 2816, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
+                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
+    assert st == 0 and d["tail_tiles"] > 0 and d["gemm_tasks"] == 1 + 2 * d["tail_tiles"], d
+    # a configuration whose LDS lets two workgroups share a CU (128-tiles, 64 KiB): its
+    # rounds are not 32 tiles per XCD, so nothing is split
+    st, d = ffa.plan_describe(4352, 1024, 251, dA=ffa.I8_CENTRED, dC=ffa.U8,
+                              opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL, kernel=3))
+    assert st == 0 and d["cfg"] == 2 and d["tail_tiles"] == 0, d
 
 
 def test_sizes_beyond_the_limits_are_refused_quickly():
