@@ -717,7 +717,7 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     __shared__ int s_next;
     const bool persist = fp.nent > 0;
     const int x = blockIdx.x & 7;
-    int* q = reinterpret_cast<int*>(bases.p[BUF_WS] + fp.queue_off) + x;
+    int* q = persist ? reinterpret_cast<int*>(bases.p[BUF_WS] + fp.queue_off) + x : nullptr;
     int e = blockIdx.x;
     if (persist) {
         if (threadIdx.x == 0) s_next = atomicAdd(q, 1) * 8 + x;
