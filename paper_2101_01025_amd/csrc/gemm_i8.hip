@@ -25,7 +25,7 @@ struct CfgInfo {
 
 static CfgInfo cfg_info(int id)
 {
-#define FFA_INFO(ID, NL, CP, BT, WM, WN, KT, PF, MS) \
+#define FFA_INFO(ID, NL, CP, BT, WM, WN, KT, PF, MS, OCC) \
     if (id == ID)                                                                              \
         return CfgInfo{NL, CP, BT, KT, WM * WN * 64,                                        \
                        (PF < 0 ? -PF : 2) * ((CP ? 2 : 1) * NL + NL) * BT * KT,           \

@@ -1,5 +1,6 @@
 // Configurations of the INT8 product kernel: id -> (limbs, complex, tile edge,
-// wave grid, k-tile bytes, prefetch depth, MFMA block edge; depth 0 = direct
+// wave grid, k-tile bytes, prefetch depth, MFMA block edge, waves per SIMD the
+// register allocation must allow (0: the compiler's choice); depth 0 = direct
 // global-to-LDS loads into two buffers).
 // Accumulator registers per lane: NROLE * NACC * (BT/WGM/32) * (BT/WGN/32) * 16.
 // Configurations whose accumulators do not fit the register file without
@@ -9,40 +10,41 @@
 #pragma once
 
 #define FFA_I8_CONFIGS_A(X)               \
-    X(24, 1, 0, 256, 2, 4, 128, 0, 32)    \
-    X(2, 1, 0, 128, 2, 2, 128, 2, 32)     \
-    X(1, 1, 0, 256, 2, 4, 64, 2, 32)      \
-    X(14, 1, 0, 64, 2, 2, 128, 2, 32)
+    X(24, 1, 0, 256, 2, 4, 128, 0, 32, 0)   \
+    X(2, 1, 0, 128, 2, 2, 128, 2, 32, 0)    \
+    X(1, 1, 0, 256, 2, 4, 64, 2, 32, 0)     \
+    X(14, 1, 0, 64, 2, 2, 128, 2, 32, 0)     \
+    X(39, 2, 0, 64, 2, 2, 64, 2, 32, 4)
 
 #define FFA_I8_CONFIGS_B(X)               \
-    X(16, 2, 0, 128, 2, 4, 128, 2, 32)    \
-    X(15, 2, 0, 128, 2, 4, 128, 1, 32)    \
-    X(26, 2, 0, 128, 2, 4, 128, 0, 32)    \
-    X(9, 2, 0, 128, 2, 2, 128, 1, 32)
+    X(16, 2, 0, 128, 2, 4, 128, 2, 32, 0)   \
+    X(15, 2, 0, 128, 2, 4, 128, 1, 32, 0)   \
+    X(26, 2, 0, 128, 2, 4, 128, 0, 32, 0)   \
+    X(9, 2, 0, 128, 2, 2, 128, 1, 32, 0)
 
 #define FFA_I8_CONFIGS_C(X)               \
-    X(10, 1, 0, 256, 2, 4, 128, 2, 32)    \
-    X(11, 1, 0, 256, 2, 4, 64, 3, 32)     \
-    X(12, 1, 0, 256, 4, 2, 64, 2, 32)     \
-    X(25, 2, 0, 128, 2, 2, 128, 0, 32)    \
-    X(13, 2, 0, 64, 2, 2, 128, 2, 32)
+    X(10, 1, 0, 256, 2, 4, 128, 2, 32, 0)   \
+    X(11, 1, 0, 256, 2, 4, 64, 3, 32, 0)    \
+    X(12, 1, 0, 256, 4, 2, 64, 2, 32, 0)    \
+    X(25, 2, 0, 128, 2, 2, 128, 0, 32, 0)   \
+    X(13, 2, 0, 64, 2, 2, 128, 2, 32, 0)
 
 #define FFA_I8_CONFIGS_D(X)               \
-    X(4, 1, 1, 128, 2, 2, 128, 2, 32)     \
-    X(8, 2, 1, 64, 2, 2, 128, 2, 32)      \
-    X(17, 2, 0, 64, 2, 2, 64, 2, 32)      \
-    X(18, 2, 0, 128, 2, 4, 64, 4, 32)     \
-    X(21, 2, 0, 64, 2, 2, 64, 4, 32)
+    X(4, 1, 1, 128, 2, 2, 128, 2, 32, 0)    \
+    X(8, 2, 1, 64, 2, 2, 128, 2, 32, 0)     \
+    X(17, 2, 0, 64, 2, 2, 64, 2, 32, 0)     \
+    X(18, 2, 0, 128, 2, 4, 64, 4, 32, 0)    \
+    X(21, 2, 0, 64, 2, 2, 64, 4, 32, 0)
 
 // depth -NBUF: direct loads into NBUF buffers, issued between the k-steps
 #define FFA_I8_CONFIGS_E(X)               \
-    X(29, 1, 0, 256, 2, 4, 128, -2, 32)   \
-    X(32, 2, 0, 128, 2, 4, 128, -2, 32)   \
-    X(34, 1, 0, 256, 2, 4, 128, 0, 16)    \
-    X(35, 1, 0, 256, 2, 4, 128, -2, 16)   \
-    X(36, 2, 0, 128, 2, 4, 128, -2, 16)   \
-    X(37, 1, 0, 256, 4, 2, 128, 0, 16)    \
-    X(38, 1, 0, 128, 2, 2, 128, 0, 16)
+    X(29, 1, 0, 256, 2, 4, 128, -2, 32, 0)  \
+    X(32, 2, 0, 128, 2, 4, 128, -2, 32, 0)  \
+    X(34, 1, 0, 256, 2, 4, 128, 0, 16, 0)   \
+    X(35, 1, 0, 256, 2, 4, 128, -2, 16, 0)  \
+    X(36, 2, 0, 128, 2, 4, 128, -2, 16, 0)  \
+    X(37, 1, 0, 256, 4, 2, 128, 0, 16, 0)   \
+    X(38, 1, 0, 128, 2, 2, 128, 0, 16, 0)
 
 #define FFA_I8_CONFIGS(X) \
     FFA_I8_CONFIGS_A(X)   \

@@ -708,8 +708,8 @@ __device__ __forceinline__ void gemm_i8_tile(const Bases& bases, const GemmTask*
 // the host) in order from that XCD's queue counter in the workspace (zeroed before
 // the launch), grabbing the next one while it computes the current one, until the
 // queue passes fp.nent.  Every workgroup ends once its queue is drained.
-template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC, int MS>
-__global__ void __launch_bounds__(WGM* WGN * 64)
+template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC, int MS, int OCC>
+__global__ void __launch_bounds__(WGM* WGN * 64, OCC > 0 ? OCC : 1)
     gemm_i8(Bases bases, const GemmTask* __restrict__ tasks, const TileEnt* __restrict__ sched,
             FieldParams fp)
 {
@@ -737,13 +737,13 @@ __global__ void __launch_bounds__(WGM* WGN * 64)
     }
 }
 
-template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC, int MS>
+template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC, int MS, int OCC>
 static int launch_cfg(const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks, const Bases& b,
                       const FieldParams& fp, hipStream_t s)
 {
     constexpr int NA = (CPLX ? 2 : 1) * NL, NB = NL;
     constexpr int lds_bytes = (PF < 0 ? -PF : 2) * (NA + NB) * BT * KT;
-    auto kern = gemm_i8<NL, CPLX, BT, WGM, WGN, KT, PF, SRC, MS>;
+    auto kern = gemm_i8<NL, CPLX, BT, WGM, WGN, KT, PF, SRC, MS, OCC>;
     // the LDS limit is raised once per device the kernel runs on
     static uint64_t attr_devices = 0;
     int dev = 0;
@@ -777,15 +777,15 @@ static int launch_cfg(const GemmTask* d_tasks, const TileEnt* d_sched, int nbloc
 
 // Raw uint16 operands exist only for the two-limb real configurations that load
 // through registers.
-template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int MS>
+template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int MS, int OCC>
 static int launch_src(int src, const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks,
                       const Bases& b, const FieldParams& fp, hipStream_t s)
 {
     if (src == SRC_CARRIER)
-        return launch_cfg<NL, CPLX, BT, WGM, WGN, KT, PF, SRC_CARRIER, MS>(d_tasks, d_sched, nblocks, b, fp, s);
+        return launch_cfg<NL, CPLX, BT, WGM, WGN, KT, PF, SRC_CARRIER, MS, OCC>(d_tasks, d_sched, nblocks, b, fp, s);
     if constexpr (NL == 2 && CPLX == 0 && PF > 0) {
         if (src == SRC_RAW_U16)
-            return launch_cfg<NL, CPLX, BT, WGM, WGN, KT, PF, SRC_RAW_U16, MS>(d_tasks, d_sched, nblocks, b, fp, s);
+            return launch_cfg<NL, CPLX, BT, WGM, WGN, KT, PF, SRC_RAW_U16, MS, OCC>(d_tasks, d_sched, nblocks, b, fp, s);
     }
     return (int)hipErrorInvalidValue;
 }
@@ -809,14 +809,14 @@ static int launch_src(int src, const GemmTask* d_tasks, const TileEnt* d_sched, 
         return FFA_I8_NOT_HERE;                                                                        \
     }
 
-#define FFA_I8_PART_LAUNCH(ID, NL, CP, BT, WM, WN, KT, PF, MS) \
-    if (cfg == ID) return launch_src<NL, CP, BT, WM, WN, KT, PF, MS>(src, d_tasks, d_sched, nblocks, b, fp, s);
+#define FFA_I8_PART_LAUNCH(ID, NL, CP, BT, WM, WN, KT, PF, MS, OCC) \
+    if (cfg == ID) return launch_src<NL, CP, BT, WM, WN, KT, PF, MS, OCC>(src, d_tasks, d_sched, nblocks, b, fp, s);
 
-#define FFA_I8_PART_REGS(ID, NL, CP, BT, WM, WN, KT, PF, MS)                                        \
+#define FFA_I8_PART_REGS(ID, NL, CP, BT, WM, WN, KT, PF, MS, OCC)                                   \
     if (cfg == ID) {                                                                                \
         hipFuncAttributes a{};                                                                      \
         const hipError_t e =                                                                        \
-            hipFuncGetAttributes(&a, (const void*)gemm_i8<NL, CP, BT, WM, WN, KT, PF, SRC_CARRIER, MS>); \
+            hipFuncGetAttributes(&a, (const void*)gemm_i8<NL, CP, BT, WM, WN, KT, PF, SRC_CARRIER, MS, OCC>); \
         if (e != hipSuccess) return (int)e;                                                         \
         *vgprs = a.numRegs;                                                                         \
         return 0;                                                                                   \
