@@ -25,7 +25,7 @@ struct CfgInfo {
 
 static CfgInfo cfg_info(int id)
 {
-#define FFA_INFO(ID, NL, CP, BT, WM, WN, KT, PF, MS, OCC) \
+#define FFA_INFO(ID, NL, CP, BT, WM, WN, KT, PF, MS, OPT) \
     if (id == ID)                                                                              \
         return CfgInfo{NL, CP, BT, KT, WM * WN * 64,                                        \
                        (PF < 0 ? -PF : 2) * ((CP ? 2 : 1) * NL + NL) * BT * KT,           \
@@ -58,7 +58,9 @@ int gemm_i8_default_config(int nl, int cplx, int64_t max_dim)
     // 8 waves of 128x64, operands loaded straight into LDS, 16x16x64 MFMAs: 1.78 ms
     // against 1.86 ms for configuration 24 (the same with 32x32x32 MFMAs) and 1.84 ms
     // for configuration 29 (loads spread over the k-steps) per call at n = k = 16384,
-    // p = 251, no recursion (medians of alternating blocks)
+    // p = 251, no recursion (medians of alternating blocks); configuration 40 (each
+    // k-tile's last k-step after its barrier) 1.71 vs 1.74 ms without recursion but
+    // 1.84 vs 1.81 ms with one level
     return max_dim >= 2048 ? 34 : 2;
 }
 

@@ -169,7 +169,7 @@ __device__ __forceinline__ uint32_t sum_u16x8(v4i v, uint32_t acc)
 }
 
 // One tile of the grouped product launch: entry e of the schedule.
-template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC, int MS>
+template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC, int MS, int OPT>
 __device__ __forceinline__ void gemm_i8_tile(const Bases& bases, const GemmTask* __restrict__ tasks,
                                              const TileEnt* __restrict__ sched, const FieldParams& fp,
                                              char* lds, int e)
@@ -224,8 +224,13 @@ __device__ __forceinline__ void gemm_i8_tile(const Bases& bases, const GemmTask*
     // (the thread index passes through an empty asm statement so that the compiler
     // does not hoist the per-thread offsets derived from it out of a persistent
     // launch's loop over tiles, where they would stay live and spill)
+    // (the mask gives the compiler the index's range back: LDS addresses derived from
+    // it are then known to be non-negative, so that constant parts of them go into
+    // the instructions' offset fields instead of registers; option bit 5 leaves it
+    // out for the configurations whose allocation grows with it)
     int tid = (int)threadIdx.x;
     asm volatile("" : "+v"(tid));
+    if (!(OPT & 32)) tid &= NT - 1;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
 
@@ -434,6 +439,11 @@ __device__ __forceinline__ void gemm_i8_tile(const Bases& bases, const GemmTask*
     // the fragments of k-step ks + 1 are read while the MFMAs of k-step ks run;
     // hook(ks) runs after the MFMAs of k-step ks are issued
     constexpr int NKS = KT / (16 * SPK);
+    // option bit 4: the last k-step's MFMAs after the k-tile's barrier (direct loads,
+    // an even number of k-steps, so that they and the next k-tile's first fragments
+    // use different halves of the fragment double buffer)
+    constexpr bool DEFER = (OPT & 16) != 0;
+    static_assert(!DEFER || (DMA && !RING && NKS % 2 == 0), "deferred MFMAs: direct loads, even k-steps");
     // Where stage st + 1 is written to LDS: before compute(st) when it was loaded at
     // least one iteration earlier (PF >= 2), else halfway through compute(st) (its
     // loads are issued at the start of the iteration).  Measured against writing it
@@ -495,12 +505,44 @@ __device__ __forceinline__ void gemm_i8_tile(const Bases& bases, const GemmTask*
             }
             phase_barrier();
         }
-    } else if (DMA) {
+    } else if (DMA && DEFER) {
+        // The MFMAs of each k-tile's last k-step (their fragments already in registers)
+        // are issued after the barrier that ends the k-tile, while the next k-tile's
+        // first fragments are read: the two waves of a SIMD leave the barrier together,
+        // and without this both would wait for those reads before their next MFMA.
+        // The loads of k-tile st + 2 are issued right after that barrier (their buffer's
+        // last reads are behind it), ahead of the deferred MFMAs.
+        v4i af[2][NA][FM], bf[2][NB][FN];
         if (nst > 0) gload(0, ra[0], rb[0]);
+        wait_vm<0>();
+        __syncthreads();
+        if (nst > 1) gload(1, ra[0], rb[0]);
+        if (nst > 0) load_frags(lds, 0, af[0], bf[0]);
+        for (int st = 0; st < nst; ++st) {
+            const char* base = lds + (st & 1) * STAGE;
+#pragma unroll
+            for (int ks = 0; ks < NKS - 1; ++ks) {
+                load_frags(base, ks + 1, af[(ks + 1) & 1], bf[(ks + 1) & 1]);
+                mfmas(af[ks & 1], bf[ks & 1]);
+            }
+            wait_vm<0>();  // k-tile st + 1 is in LDS
+            __syncthreads();
+            __builtin_amdgcn_sched_barrier(0);
+            if (st + 2 < nst) gload(st + 2, ra[0], rb[0]);
+            if (st + 1 < nst) load_frags(lds + ((st + 1) & 1) * STAGE, 0, af[0], bf[0]);
+            mfmas(af[(NKS - 1) & 1], bf[(NKS - 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else if (DMA) {
+        // (the waits for the direct loads are explicit: the barrier's fence need not
+        // cover loads that write LDS)
+        if (nst > 0) gload(0, ra[0], rb[0]);
+        wait_vm<0>();
         __syncthreads();
         for (int st = 0; st < nst; ++st) {
             if (st + 1 < nst) gload(st + 1, ra[0], rb[0]);
             compute(st & 1, [](int) {});
+            wait_vm<0>();
             __syncthreads();
         }
     }
@@ -708,8 +750,8 @@ __device__ __forceinline__ void gemm_i8_tile(const Bases& bases, const GemmTask*
 // the host) in order from that XCD's queue counter in the workspace (zeroed before
 // the launch), grabbing the next one while it computes the current one, until the
 // queue passes fp.nent.  Every workgroup ends once its queue is drained.
-template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC, int MS, int OCC>
-__global__ void __launch_bounds__(WGM* WGN * 64, OCC > 0 ? OCC : 1)
+template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC, int MS, int OPT>
+__global__ void __launch_bounds__(WGM* WGN * 64, (OPT & 15) > 0 ? (OPT & 15) : 1)
     gemm_i8(Bases bases, const GemmTask* __restrict__ tasks, const TileEnt* __restrict__ sched,
             FieldParams fp)
 {
@@ -728,7 +770,7 @@ __global__ void __launch_bounds__(WGM* WGN * 64, OCC > 0 ? OCC : 1)
     while (e < nent) {
         int nx = 0;
         if (persist && threadIdx.x == 0) nx = atomicAdd(q, 1) * 8 + x;
-        gemm_i8_tile<NL, CPLX, BT, WGM, WGN, KT, PF, SRC, MS>(bases, tasks, sched, fp, lds, e);
+        gemm_i8_tile<NL, CPLX, BT, WGM, WGN, KT, PF, SRC, MS, OPT>(bases, tasks, sched, fp, lds, e);
         if (!persist) break;
         __syncthreads();  // the tile's last reads of LDS are done
         if (threadIdx.x == 0) s_next = nx;
@@ -737,13 +779,13 @@ __global__ void __launch_bounds__(WGM* WGN * 64, OCC > 0 ? OCC : 1)
     }
 }
 
-template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC, int MS, int OCC>
+template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int SRC, int MS, int OPT>
 static int launch_cfg(const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks, const Bases& b,
                       const FieldParams& fp, hipStream_t s)
 {
     constexpr int NA = (CPLX ? 2 : 1) * NL, NB = NL;
     constexpr int lds_bytes = (PF < 0 ? -PF : 2) * (NA + NB) * BT * KT;
-    auto kern = gemm_i8<NL, CPLX, BT, WGM, WGN, KT, PF, SRC, MS, OCC>;
+    auto kern = gemm_i8<NL, CPLX, BT, WGM, WGN, KT, PF, SRC, MS, OPT>;
     // the LDS limit is raised once per device the kernel runs on
     static uint64_t attr_devices = 0;
     int dev = 0;
@@ -777,15 +819,15 @@ static int launch_cfg(const GemmTask* d_tasks, const TileEnt* d_sched, int nbloc
 
 // Raw uint16 operands exist only for the two-limb real configurations that load
 // through registers.
-template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int MS, int OCC>
+template <int NL, int CPLX, int BT, int WGM, int WGN, int KT, int PF, int MS, int OPT>
 static int launch_src(int src, const GemmTask* d_tasks, const TileEnt* d_sched, int nblocks,
                       const Bases& b, const FieldParams& fp, hipStream_t s)
 {
     if (src == SRC_CARRIER)
-        return launch_cfg<NL, CPLX, BT, WGM, WGN, KT, PF, SRC_CARRIER, MS, OCC>(d_tasks, d_sched, nblocks, b, fp, s);
+        return launch_cfg<NL, CPLX, BT, WGM, WGN, KT, PF, SRC_CARRIER, MS, OPT>(d_tasks, d_sched, nblocks, b, fp, s);
     if constexpr (NL == 2 && CPLX == 0 && PF > 0) {
         if (src == SRC_RAW_U16)
-            return launch_cfg<NL, CPLX, BT, WGM, WGN, KT, PF, SRC_RAW_U16, MS, OCC>(d_tasks, d_sched, nblocks, b, fp, s);
+            return launch_cfg<NL, CPLX, BT, WGM, WGN, KT, PF, SRC_RAW_U16, MS, OPT>(d_tasks, d_sched, nblocks, b, fp, s);
     }
     return (int)hipErrorInvalidValue;
 }
@@ -809,14 +851,14 @@ static int launch_src(int src, const GemmTask* d_tasks, const TileEnt* d_sched, 
         return FFA_I8_NOT_HERE;                                                                        \
     }
 
-#define FFA_I8_PART_LAUNCH(ID, NL, CP, BT, WM, WN, KT, PF, MS, OCC) \
-    if (cfg == ID) return launch_src<NL, CP, BT, WM, WN, KT, PF, MS, OCC>(src, d_tasks, d_sched, nblocks, b, fp, s);
+#define FFA_I8_PART_LAUNCH(ID, NL, CP, BT, WM, WN, KT, PF, MS, OPT) \
+    if (cfg == ID) return launch_src<NL, CP, BT, WM, WN, KT, PF, MS, OPT>(src, d_tasks, d_sched, nblocks, b, fp, s);
 
-#define FFA_I8_PART_REGS(ID, NL, CP, BT, WM, WN, KT, PF, MS, OCC)                                   \
+#define FFA_I8_PART_REGS(ID, NL, CP, BT, WM, WN, KT, PF, MS, OPT)                                   \
     if (cfg == ID) {                                                                                \
         hipFuncAttributes a{};                                                                      \
         const hipError_t e =                                                                        \
-            hipFuncGetAttributes(&a, (const void*)gemm_i8<NL, CP, BT, WM, WN, KT, PF, SRC_CARRIER, MS, OCC>); \
+            hipFuncGetAttributes(&a, (const void*)gemm_i8<NL, CP, BT, WM, WN, KT, PF, SRC_CARRIER, MS, OPT>); \
         if (e != hipSuccess) return (int)e;                                                         \
         *vgprs = a.numRegs;                                                                         \
         return 0;                                                                                   \

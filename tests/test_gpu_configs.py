@@ -15,7 +15,7 @@ import seeded_inputs as si
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-MAX_CFG = 40
+MAX_CFG = 48
 
 
 def _ffa():

@@ -240,7 +240,7 @@ def _check_planned(n, k, p, dA, dC, **kw):
 
 
 @pytest.mark.parametrize("kind", ["hi", "lo", "alt"])
-@pytest.mark.parametrize("cfg", ["default", "cfg24", "cfg34"])
+@pytest.mark.parametrize("cfg", ["default", "cfg24", "cfg34", "cfg40"])
 def test_int8_p251_at_bound(kind, cfg):
     """One limb, p = 251: K = 137344 (137344 * 125^2 = 2146000000, the last k-tile
     multiple below 2^31 - 2^17) with entries +125, -125, or both alternating."""
@@ -248,7 +248,7 @@ def test_int8_p251_at_bound(kind, cfg):
     p, n, k = 251, 256, 137344
     kw = dict(algo=ffa.ALGO_CLASSICAL)
     if cfg != "default":
-        kw["kernel"] = int(cfg[3:]) + 1  # 256-tiles with 32x32x32 or 16x16x64 MFMAs
+        kw["kernel"] = int(cfg[3:]) + 1  # 256-tiles with 32x32x32 or 16x16x64 MFMAs (40: deferred k-step)
     d = _check_planned(n, k, p, ffa.I8_CENTRED, ffa.U8, **kw)
     assert d["max_k"] == k and d["max_abs"] == 125
     assert ffa.plan_describe(n, k + 128, p, dA=ffa.I8_CENTRED, dC=ffa.U8,
@@ -580,7 +580,8 @@ def test_batched_raw_rows_with_nonzero_padding(cfg, persist):
     B.close()
 
 
-@pytest.mark.parametrize("case", ["p251-default", "p251-cfg34", "p65521-planes", "p65521-raw", "p65521-cfg32"])
+@pytest.mark.parametrize("case", ["p251-default", "p251-cfg34", "p251-cfg40", "p65521-planes", "p65521-raw",
+                                  "p65521-cfg32"])
 def test_persistent_product_launch(case):
     """The product launch run persistent (workgroups taking tiles from a queue per XCD)
     against the oracle, on shapes of many ragged tiles, twice in a row (the queue
@@ -592,6 +593,8 @@ def test_persistent_product_launch(case):
     kw = dict(algo=ffa.ALGO_CLASSICAL, persist=ffa.PERSIST_ON)
     if case.endswith("cfg34"):
         kw["kernel"] = 35
+    if case.endswith("cfg40"):
+        kw["kernel"] = 41
     if case.endswith("cfg32"):
         kw["kernel"] = 33
     if case.endswith("raw"):
