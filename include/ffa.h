@@ -89,7 +89,10 @@ enum { FFA_CARRIER_AUTO = 0, FFA_CARRIER_INT8 = 1, FFA_CARRIER_F64 = 2 };
  *                 launch sequence as one captured hipGraph; FFA_LAUNCH_DIRECT enqueues
  *                 the kernels one by one
  *   operands      FFA_OPERANDS_AUTO: limb planes prepared by a conditioning pass, except
- *                 where those planes would not be addressable with 32-bit offsets;
+ *                 where those planes would not be addressable with 32-bit offsets, and
+ *                 for batches of two-limb uint16 problems under 2048 rows without
+ *                 recursion and without a requested configuration, which read their
+ *                 rows raw (below) with configuration 39;
  *                 FFA_OPERANDS_PLANES: always; FFA_OPERANDS_RAW: without recursion and
  *                 with uint16 input in 16-byte aligned rows, the product kernel reads A
  *                 itself and forms the limbs on the fly (else ignored); it reads whole

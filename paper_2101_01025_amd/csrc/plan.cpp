@@ -770,6 +770,9 @@ void choose_kernel(Plan& pl, int64_t max_dim)
 // kernel reads whole 16-byte chunks of a row (the columns past k are zeroed after
 // the load), so the row's last chunk must be inside the caller's buffer: k a
 // multiple of 8, or the library's packed layout, whose rows are padded to 16 bytes.
+// Product configuration of the batches that read raw uint16 operands by default.
+constexpr int RAW_BATCH_CONFIG = 39;
+
 bool raw_u16_ok(const Plan& pl, const Problem& pr, int levels)
 {
     return pl.carrier == CAR_I8 && pl.nl == 2 && !pl.cplx && gemm_i8_config_raw(pl.gemm_cfg) && pr.dA == FFA_U16 &&
@@ -942,12 +945,22 @@ Plan make_batch_plan(const std::vector<Problem>& prs)
     for (const auto& q : prs) maxn = std::max(maxn, q.n);
     pl.kernel_req = p0.opts.kernel;
     choose_kernel(pl, maxn);
-    Builder B = make_builder(pl);
-    int64_t aoff = 0, coff = 0;
     const int ain = dtype_size(p0.dA), cout = dtype_size(p0.dC);
     // packed layout: A_i rows padded to 16 bytes, every A_i and C_i 16-byte aligned
     auto lda_of = [&](const Problem& q) { return round_up(std::max<int64_t>(q.k, 1), 16 / ain); };
-    if (p0.opts.operands == FFA_OPERANDS_RAW) {
+    // Many small two-limb problems without recursion: unless a configuration or the
+    // operand source is asked for, the products read the caller's uint16 rows with
+    // configuration 39 (no conditioning pass; four workgroups per CU), the plan the
+    // autotuner keeps for such batches (1.28-1.31 ms against 1.65-1.78 ms with limb
+    // planes for 4096 problems of n in [32, 512] at p = 65521)
+    const bool auto_raw = p0.opts.operands == FFA_OPERANDS_AUTO && p0.opts.kernel == 0 && pl.carrier == CAR_I8 &&
+                          pl.nl == 2 && !pl.cplx && maxL == 0 && maxn < 2048;
+    if (auto_raw) {
+        pl.gemm_cfg = RAW_BATCH_CONFIG;
+        pl.tile = gemm_i8_config_tile(pl.gemm_cfg);
+        pl.ktile = gemm_i8_config_ktile(pl.gemm_cfg);
+    }
+    if (p0.opts.operands == FFA_OPERANDS_RAW || auto_raw) {
         bool raw = true;
         int64_t off = 0;
         for (size_t i = 0; i < prs.size() && raw; ++i) {
@@ -959,7 +972,10 @@ Plan make_batch_plan(const std::vector<Problem>& prs)
             raw = q.n == 0 || raw_u16_ok(pl, q, L[i]);
         }
         if (raw) pl.gemm_src = SRC_RAW_U16;
+        else if (auto_raw) choose_kernel(pl, maxn);  // limb planes with the built-in configuration
     }
+    Builder B = make_builder(pl);
+    int64_t aoff = 0, coff = 0;
     for (size_t i = 0; i < prs.size(); ++i) {
         Problem q = prs[i];
         q.lda = lda_of(q);

@@ -545,8 +545,28 @@ def test_batch_plan_persistent_by_default():
         ffa.BatchSyrk(ns, ks, 65521, ffa.U16, ffa.U16, persist=5)
 
 
+def test_batch_default_operands():
+    """A batch of small two-limb problems reads the caller's uint16 rows with
+    configuration 39 unless limb planes or a configuration are asked for; input that is
+    not uint16, or a problem of 2048 rows or more, keeps limb planes."""
+    ffa = _ffa()
+    ns, ks = np.array([40, 300, 7]), np.array([50, 310, 9])
+    for kw, dA, src, cfg in (({}, ffa.U16, "raw_u16", 39),
+                             (dict(operands=ffa.OPERANDS_PLANES), ffa.U16, "carrier", 16),
+                             (dict(kernel=17), ffa.U16, "carrier", 16),
+                             ({}, ffa.I64, "carrier", 16)):
+        B = ffa.BatchSyrk(ns, ks, 65521, dA, ffa.U16, **kw)
+        d = B.describe()
+        assert d["src"] == src and d["cfg"] == cfg, (kw, dA, d)
+        B.close()
+    B = ffa.BatchSyrk(np.array([40, 2048]), np.array([50, 64]), 65521, ffa.U16, ffa.U16)
+    d = B.describe()
+    assert d["src"] == "carrier" and d["cfg"] == 32, d
+    B.close()
+
+
 @pytest.mark.parametrize("persist", ["on", "off"])
-@pytest.mark.parametrize("cfg", [16, 21])
+@pytest.mark.parametrize("cfg", [16, 21, 39])
 def test_batched_raw_rows_with_nonzero_padding(cfg, persist):
     """Raw uint16 operands over the packed layout with ragged k: the row's last
     16-byte chunk is read whole and its columns past k are zeroed in the kernel.  The
