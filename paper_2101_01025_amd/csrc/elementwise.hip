@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(256) condition_i8(const CondTask* tasks, int n
     for (int q = 0; q < NPL; ++q)
 #pragma unroll
         for (int l = 0; l < NL; ++l)
-            if (q < npl)
+            if (q < npl && !((t.skip >> q) & 1))
                 *reinterpret_cast<int4*>(ob + (int64_t)(q * NL + l) * t.out.ps) =
                     *reinterpret_cast<const int4*>(out[q][l]);
 }

@@ -184,6 +184,8 @@ struct CondTask {
     CarRef out;
     int32_t trans;
     int32_t blk0;  // first block of this task in the one-dimensional grid of the launch
+    int32_t skip;  // bit q set: carrier plane q is not written (no product reads it)
+    int32_t pad_;
 };
 
 // 2M base case of a Hermitian leaf (Algorithm 3 with epsilon = 1): from the real

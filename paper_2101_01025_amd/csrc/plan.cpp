@@ -716,6 +716,9 @@ int add_problem(Plan& pl, Builder& B, const Problem& pr, int levels, bool allow_
         ct.off_re = ct.off_im = pr.a_off * in_size;
         ct.out = a;
         ct.trans = pr.trans;
+        // the 2M base case reads planes re, im and re + im: without recursion (the input
+        // itself is the leaf) nothing reads -re
+        ct.skip = pl.herk2m && levels == 0 ? 1 << 2 : 0;
         if (pr.trans) {
             // 64 x 64 tiles of the carrier; grid (largest task, tasks)
             pl.cond_trans = true;
