@@ -89,7 +89,7 @@ def copy_calibration():
 
 PROFILE_FILE = os.path.join(ROOT, "profiles", "gemm_i8_syrk_p251_n16384.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2101_01025_amd", "csrc", f)
-                  for f in ("gemm_i8_kernel.h", "device_common.h", "ffa_internal.h")]
+                  for f in ("gemm_i8_kernel.h", "gemm_i8_configs.h", "device_common.h", "ffa_internal.h")]
 
 
 def kernel_hash():

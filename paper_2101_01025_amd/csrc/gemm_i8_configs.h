@@ -49,7 +49,8 @@
     X(37, 1, 0, 256, 4, 2, 128, 0, 16, 0)   \
     X(38, 1, 0, 128, 2, 2, 128, 0, 16, 0)   \
     X(40, 1, 0, 256, 2, 4, 128, 0, 16, 48)  \
-    X(41, 2, 0, 128, 2, 4, 128, 0, 32, 16)
+    X(41, 2, 0, 128, 2, 4, 128, 0, 32, 16)  \
+    X(42, 1, 0, 256, 2, 4, 128, 0, 16, 0)
 
 #define FFA_I8_CONFIGS(X) \
     FFA_I8_CONFIGS_A(X)   \

@@ -240,7 +240,7 @@ def _check_planned(n, k, p, dA, dC, **kw):
 
 
 @pytest.mark.parametrize("kind", ["hi", "lo", "alt"])
-@pytest.mark.parametrize("cfg", ["default", "cfg24", "cfg34", "cfg40"])
+@pytest.mark.parametrize("cfg", ["default", "cfg24", "cfg34", "cfg40", "cfg42"])
 def test_int8_p251_at_bound(kind, cfg):
     """One limb, p = 251: K = 137344 (137344 * 125^2 = 2146000000, the last k-tile
     multiple below 2^31 - 2^17) with entries +125, -125, or both alternating."""

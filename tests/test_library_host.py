@@ -122,8 +122,9 @@ def test_default_product_configurations():
                                   opts=ffa.make_opts(algo=ffa.ALGO_CLASSICAL))
         assert st == 0 and d["cfg"] == cfg and d["tile"] == (128 if cfg == 2 else 256), (n, d)
     st, d = ffa.plan_describe(16384, 16384, 251, dA=ffa.I8_CENTRED, dC=ffa.U8, opts=ffa.make_opts(levels=1))
-    # centred int8 input is read in place by the pre-additions and products
-    assert st == 0 and d["levels"] == 1 and d["cfg"] == 34 and d["direct"] == 1 and d["conditioning"] == 0
+    # centred int8 input is read in place by the pre-additions and products; recursive
+    # plans take the same kernel with the thread index's range restated (configuration 42)
+    assert st == 0 and d["levels"] == 1 and d["cfg"] == 42 and d["direct"] == 1 and d["conditioning"] == 0
     st, d = ffa.plan_describe(16384, 16384, 65521, dA=ffa.U16, dC=ffa.U16)
     assert st == 0 and d["cfg"] == 32
     st, d = ffa.plan_describe(1024, 1024, 65521, dA=ffa.U16, dC=ffa.U16)
